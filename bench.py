@@ -1,0 +1,251 @@
+#!/usr/bin/env python3
+"""Benchmark of the SIPDG elliptic operator and solvers on one MI355X.
+
+Workload (the operator-throughput sweep): a 512 x 512-square triangulation of
+the unit square (524,288 triangles), interior vertices jittered by +-0.2 h,
+all faces Dirichlet, x ~ N(0,1) per node, c_tau = (N+1)^2.
+
+A step is one application y = (lambda M - Lap_IPDG) x of the headline
+configuration (default N = 3, FP64, lambda = 100).  Inputs are resident in
+device memory; the timed loop rotates over enough independent copies of the
+mesh data and vectors (> 1.2 GB) that the 256 MB last-level cache cannot hold
+them, and is bracketed by HIP events on the stream the kernels run on.
+
+One JSON line is printed with the headline throughput, the roofline of the
+operator kernel, the CPU oracle baseline, the per-degree sweep and (when
+built) the PCG + p-multigrid time-to-solution comparison.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
+FP64_PEAK_TFS = 78.6           # vector FP64, published
+FP32_PEAK_TFS = 157.3          # vector FP32, published
+
+
+def np_of(N):
+    return (N + 1) * (N + 2) // 2
+
+
+def alg_bytes(N, w):
+    """Minimum bytes per element: x and y (Np each), 5 metric terms, 3
+    neighbour ids."""
+    return (2 * np_of(N) + 5) * w + 12
+
+
+def alg_flops(N):
+    """Flops per element of the operator in its local-gradient + SIPDG form
+    with the lift done once per face: 10 Np^2 + 12 Np Nfp."""
+    Np = np_of(N)
+    return 10 * Np * Np + 12 * Np * (N + 1)
+
+
+def time_applies(P, torch, msh, N, dtype, lam, steps, warmup, rotate_bytes):
+    """Time `steps` applications rotating over independent data sets."""
+    import synth
+    w = 8 if dtype == torch.float64 else 4
+    K = msh.K
+    Np = np_of(N)
+    set_bytes = K * (2 * Np * w + 4 * w + 16)
+    R = max(1, math.ceil(rotate_bytes / set_bytes))
+    meshes = [P.Mesh.from_synth(N, msh) for _ in range(R)]
+    x0 = torch.from_numpy(synth.nodal_normal(K, Np, seed=1)).to("cuda", dtype)
+    xs = [x0.clone() for _ in range(R)]
+    ys = [torch.empty_like(x0) for _ in range(R)]
+    for i in range(warmup):
+        meshes[i % R].apply(xs[i % R], lam=lam, out=ys[i % R])
+    torch.cuda.synchronize()
+    s = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for i in range(steps):
+        meshes[i % R].apply(xs[i % R], lam=lam, out=ys[i % R])
+    e1.record(s)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    for m in meshes:
+        m.close()
+    return ms / steps, R
+
+
+def roofline(N, dtype_bytes, ms):
+    t = ms * 1e-3
+    K = 524288
+    nbytes = K * alg_bytes(N, dtype_bytes)
+    flops = K * alg_flops(N)
+    peak_f = FP64_PEAK_TFS if dtype_bytes == 8 else FP32_PEAK_TFS
+    ai = flops / nbytes
+    ridge = peak_f * 1e12 / (HBM_PEAK_GBS * 1e9)
+    if ai < ridge:
+        ach = nbytes / t / 1e9
+        return {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+                "alg_bytes_per_launch": nbytes, "alg_flops_per_launch": flops}
+    ach = flops / t / 1e12
+    return {"bound": "alu", "achieved": round(ach, 3), "peak": peak_f, "unit": "TFLOP/s",
+            "frac": round(ach / peak_f, 4), "traffic": None,
+            "alg_bytes_per_launch": nbytes, "alg_flops_per_launch": flops}
+
+
+def copy_probe(torch, nbytes, reps=20):
+    """Device-to-device copy bandwidth (the paper's empirical roof): GB/s of
+    read + write traffic, rotating over > 1.2 GB."""
+    n = max(1, int(nbytes // 8))
+    R = max(2, math.ceil(1.2e9 / (2 * 8 * n)))
+    src = [torch.empty(n, dtype=torch.float64, device="cuda").fill_(1.0) for _ in range(R)]
+    dst = [torch.empty(n, dtype=torch.float64, device="cuda") for _ in range(R)]
+    for i in range(R):
+        dst[i].copy_(src[i])
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for i in range(reps):
+        dst[i % R].copy_(src[i % R])
+    e1.record()
+    torch.cuda.synchronize()
+    t = e0.elapsed_time(e1) * 1e-3 / reps
+    return 2 * 8 * n / t / 1e9
+
+
+def cpu_baseline(N, lam, target_s=12.0):
+    """The FP64 oracle timed on the host: block rows of the assembled operator
+    for a contiguous sample of elements of the same mesh, multiplied
+    repeatedly (sparse matrix-vector product over those rows)."""
+    import numpy as np
+    import scipy.sparse as sp
+    import synth
+    from oracle.assemble import OracleMesh, block_rows
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
+    except Exception:
+        cores = 1
+    msh = synth.ax_sweep_mesh(512, seed=0)
+    m = OracleMesh(msh.VX, msh.VY, msh.EToV, msh.EToB, N)
+    Np = m.Np
+    S = 32768
+    t0 = time.time()
+    r, c, b = block_rows(m, lam, float((N + 1) ** 2), elems=np.arange(S))
+    ii = np.broadcast_to(r[:, None, None] * Np + np.arange(Np)[None, :, None], b.shape).ravel()
+    jj = np.broadcast_to(c[:, None, None] * Np + np.arange(Np)[None, None, :], b.shape).ravel()
+    A = sp.csr_matrix((b.ravel(), (ii, jj)), shape=(S * Np, msh.K * Np))
+    t_asm = time.time() - t0
+    x = synth.nodal_normal(msh.K, Np, seed=1)
+    reps = 0
+    t0 = time.time()
+    while True:
+        A @ x
+        reps += 1
+        dt = time.time() - t0
+        if dt >= target_s or reps >= 2000:
+            break
+    rate = reps * S * Np / dt / 1e9
+    return {"value": rate, "unit": "GDOF/s", "cores": cores, "kind": "oracle",
+            "sample": (f"assembled block rows of elements 0..{S - 1} (of 524,288) at N={N}, "
+                       f"lambda={lam}, multiplied {reps}x in {dt:.1f}s; assembly of the sample "
+                       f"took {t_asm:.1f}s (excluded)")}
+
+
+def run_pcg_compare(P, torch):
+    """PCG + p-multigrid (7 -> 3 -> 1) on 256 x 256 squares, N = 7, FP64 vs
+    mixed precision, time to a true relative residual of 1e-8."""
+    import numpy as np
+    import synth
+    msh = synth.square_mesh(256)
+    N = 7
+    g = P.Mesh.from_synth(N, msh)
+    x, y = g.node_coords()
+    f = torch.from_numpy(2 * np.pi ** 2 * np.sin(np.pi * x) * np.sin(np.pi * y)).to("cuda")
+    b = g.mass(f)
+    out = {"workload": "256x256 squares (131,072 triangles), N=7, f from sin(pi x) sin(pi y), "
+                       "Dirichlet, lambda=0, tol 1e-8, pMG 7->3->1, Chebyshev(2), coarse Jacobi-PCG"}
+    for name, prec in (("fp64", P.PREC_FP64), ("mixed", P.PREC_MIXED)):
+        o = P.default_opts(pc=P.PC_PMG, prec=prec, degrees=[7, 3, 1])
+        g.pcg(b, tol=1e-8, opts=o)                 # setup + warm-up
+        torch.cuda.synchronize()
+        t0 = time.time()
+        xs, info, st = g.pcg(b, tol=1e-8, opts=o)
+        torch.cuda.synchronize()
+        out[name] = {"time_to_solution_ms": round((time.time() - t0) * 1e3, 2),
+                     "iters": info["iters"], "true_relres": info["relres"],
+                     "restarts": info["restarts"], "setup_ms": round(info["setup_ms"], 2)}
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--order", type=int, default=3)
+    ap.add_argument("--dtype", default="f64", choices=["f64", "f32"])
+    ap.add_argument("--lam", type=float, default=100.0)
+    ap.add_argument("--rotate-gb", type=float, default=1.2)
+    ap.add_argument("--no-sweep", action="store_true")
+    ap.add_argument("--no-pcg", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
+                          "n_gpus_requested": args.gpus}))
+        sys.exit(2)
+
+    import torch
+    import paper_1801_00246_amd as P
+    import synth
+
+    msh = synth.ax_sweep_mesh(512, seed=0)
+    dt = torch.float64 if args.dtype == "f64" else torch.float32
+    w = 8 if args.dtype == "f64" else 4
+    N = args.order
+    ms, R = time_applies(P, torch, msh, N, dt, args.lam, args.steps, args.warmup,
+                         args.rotate_gb * 1e9)
+    gdofs = msh.K * np_of(N) / (ms * 1e-3) / 1e9
+    line = {
+        "metric": "IPDG Ax GDOF/s and PCG+pMG time-to-1e-8 (FP64 vs mixed), % HBM roofline",
+        "value": round(gdofs, 3), "unit": "GDOF/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms, 5), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": args.dtype, "data": "synthetic",
+        "config": {"workload": "Ax throughput: 512x512-square jittered triangulation "
+                               "(524,288 triangles), all Dirichlet, x ~ N(0,1)",
+                   "N": N, "Np": np_of(N), "lambda": args.lam, "c_tau": (N + 1) ** 2,
+                   "rotation_sets": R, "parallelism": "single GPU"},
+    }
+    line["roofline"] = roofline(N, w, ms)
+    line["copy_roof_gbs"] = round(copy_probe(torch, msh.K * alg_bytes(N, w) / 2), 1)
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline(N, args.lam)
+    if not args.no_sweep:
+        sweep = []
+        for Ns in range(1, 9):
+            for dname, dts, ws in (("f64", torch.float64, 8), ("f32", torch.float32, 4)):
+                for lam in (0.0, 100.0):
+                    msw, _ = time_applies(P, torch, msh, Ns, dts, lam, 50, 5, args.rotate_gb * 1e9)
+                    rf = roofline(Ns, ws, msw)
+                    sweep.append({"N": Ns, "dtype": dname, "lambda": lam, "ms": round(msw, 5),
+                                  "GDOF/s": round(msh.K * np_of(Ns) / (msw * 1e-3) / 1e9, 3),
+                                  "bound": rf["bound"], "frac": rf["frac"],
+                                  "achieved": rf["achieved"], "unit": rf["unit"]})
+                    print(f"# sweep N={Ns} {dname} lam={lam}: {sweep[-1]}", file=sys.stderr, flush=True)
+        line["sweep"] = sweep
+    if not args.no_pcg:
+        try:
+            line["pcg"] = run_pcg_compare(P, torch)
+        except P.IpdgError as e:
+            line["pcg"] = {"error": str(e)}
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,177 @@
+/*
+ * ipdg.h - C ABI of the MI355X symmetric interior-penalty DG elliptic solver.
+ *
+ * The library applies and inverts the screened-Poisson operator
+ *     A = lambda M - Lap_IPDG
+ * discretised with nodal discontinuous Galerkin on triangles of degree N
+ * (Karakus, Chalmers, Swirydowicz, Warburton: Sec. 2.1 for the SIPDG
+ * Laplacian, Eq. INS_SD_5 and the penalty Eq. Ch2.PenaltyParameter; Sec. 5.2,
+ * Eq. ellipticOp1 / ellipticOp3, for the operator A; Sec. 3 for the
+ * preconditioned conjugate-gradient solvers).
+ *
+ * Conventions shared by every entry point
+ *   - Every call returns an ipdg_status; no C++ exception crosses the ABI.
+ *     On failure ipdg_last_error() (thread-local) describes the cause.
+ *   - Field vectors are DEVICE pointers to K*Np contiguous values,
+ *     element-major (value i of element e at e*Np + i), node order: row by
+ *     row from face 0 (j = 0..N, i = 0..N-j), Warp & Blend nodes on the
+ *     bi-unit triangle (-1,-1), (1,-1), (-1,1).  Np = (N+1)(N+2)/2.
+ *   - Mesh arrays passed to ipdg_mesh_create are HOST pointers, copied.
+ *   - hip_stream is a hipStream_t (NULL = default stream).  apply-type calls
+ *     are asynchronous on that stream; solve calls synchronise it before
+ *     returning their iteration count and residual.
+ *   - A handle is used from one stream at a time; calls on one handle must
+ *     not overlap.
+ *   - Boundary conditions are homogeneous and imposed through a mirror ghost
+ *     state: Dirichlet u+ = -u-, grad u+ = grad u-; Neumann u+ = u-,
+ *     n.grad u+ = -n.grad u-.
+ *   - tau is the penalty constant c_tau: on face F between E- and E+,
+ *     tau_F = c_tau * max(kappa- |F|/|E-|, kappa+ |F|/|E+|) (one-sided on
+ *     boundary faces, kappa = 1 unless a coefficient was given).
+ *     tau <= 0 selects (N+1)^2.
+ */
+#ifndef IPDG_H
+#define IPDG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ipdg_mesh_s* ipdg_mesh;
+
+typedef enum {
+  IPDG_OK = 0,
+  IPDG_NOT_CONVERGED = 1,   /* max_iters reached; x holds the last iterate */
+  IPDG_EINVAL = -1,         /* bad argument (null pointer, size, option) */
+  IPDG_EMESH = -2,          /* invalid mesh (see ipdg_mesh_create) */
+  IPDG_EHIP = -3,           /* HIP runtime error; text has hipGetErrorString */
+  IPDG_ENOMEM = -4,         /* device or host allocation failed */
+  IPDG_EUNSUPPORTED = -5,   /* degree outside 1..8 or feature not built */
+  IPDG_EBREAKDOWN = -6      /* CG breakdown: p^T A p <= 0 or not finite */
+} ipdg_status;
+
+typedef enum { IPDG_F64 = 0, IPDG_F32 = 1 } ipdg_dtype;
+typedef enum { IPDG_BC_INTERIOR = 0, IPDG_BC_DIRICHLET = 1, IPDG_BC_NEUMANN = 2 } ipdg_bc;
+typedef enum { IPDG_PC_NONE = 0, IPDG_PC_JACOBI = 1, IPDG_PC_BLOCK_MASS = 2, IPDG_PC_PMG = 3 } ipdg_pc;
+typedef enum { IPDG_PREC_FP64 = 0, IPDG_PREC_MIXED = 1 } ipdg_prec;
+
+#define IPDG_MAX_LEVELS 8
+
+/* Options of the PCG solvers.  ipdg_default_opts() fills every field. */
+typedef struct {
+  ipdg_pc pc;              /* preconditioner */
+  ipdg_prec prec;          /* FP64 throughout, or FP32 operator/preconditioner
+                              inside FP64 CG recurrences, dots and residuals */
+  int max_iters;           /* outer iteration limit */
+  int check_every;         /* host polls convergence every this many iterations */
+  int flexible;            /* 1: flexible CG beta = -(z+, Ap)/(p, Ap);
+                              -1: automatic (flexible for PMG or MIXED) */
+  /* p-multigrid (pc == IPDG_PC_PMG): degrees[0] must equal the mesh degree,
+     strictly decreasing, last level solved by Jacobi-PCG. */
+  int n_levels;
+  int degrees[IPDG_MAX_LEVELS];
+  int cheb_degree;         /* Chebyshev steps per smoothing (>= 1) */
+  double cheb_lo, cheb_hi; /* interval [lo*rho, hi*rho] of D^-1 A */
+  double rho[IPDG_MAX_LEVELS]; /* spectral-radius estimates of D^-1 A per
+                              level; <= 0: estimated at setup by
+                              rho_steps Lanczos (Jacobi-PCG) steps */
+  int rho_steps;
+  double coarse_tol;       /* coarsest Jacobi-PCG relative tolerance */
+  int coarse_max_iters;    /* and iteration cap (tol 0 => exactly this many) */
+  double reliable_drop;    /* mixed: recompute r = b - A64 x when |r| fell by
+                              this factor since the last recompute */
+} ipdg_solve_opts;
+
+/* Result record of a solve (all fields written). */
+typedef struct {
+  int iters;               /* outer iterations taken */
+  double relres;           /* true ||b - A x|| / ||b|| in FP64 at exit */
+  int restarts;            /* residual replacements (reliable updates) */
+  double rho_used[IPDG_MAX_LEVELS];   /* Chebyshev radii used per level */
+  double setup_ms;         /* preconditioner setup wall time */
+  double solve_ms;         /* iteration wall time */
+} ipdg_solve_info;
+
+void ipdg_default_opts(ipdg_solve_opts* opts);
+
+/* Build a mesh handle of degree N (1..8) from K counter-clockwise triangles.
+ *   VX, VY   : Nv vertex coordinates (host).
+ *   EToV     : K*3 vertex ids, 0-based, counter-clockwise (host).
+ *   EToB     : K*3 face flags; face f joins vertices f and (f+1)%3; values
+ *              ipdg_bc (host).
+ *   kappa    : K per-element coefficients > 0, or NULL for kappa = 1 (host).
+ * IPDG_EMESH for a non-positive Jacobian, a face shared by more than two
+ * elements, an unmatched face flagged interior or a matched face flagged as
+ * boundary.  IPDG_EUNSUPPORTED for N outside 1..8.  Sec. 2.1 (mesh, degree),
+ * Sec. 5.2 (geometric factors of the affine map, Eq. operators2). */
+ipdg_status ipdg_mesh_create(int N, int Nv, const double* VX, const double* VY,
+                             int K, const int32_t* EToV, const int8_t* EToB,
+                             const double* kappa, ipdg_mesh* out);
+ipdg_status ipdg_mesh_destroy(ipdg_mesh mesh);
+ipdg_status ipdg_mesh_info(ipdg_mesh mesh, int* N, int* Np, int* K);
+
+/* Physical node coordinates, HOST arrays of K*Np values each. */
+ipdg_status ipdg_node_coords(ipdg_mesh mesh, double* x, double* y);
+
+/* Replace the per-element coefficient kappa (HOST, K values > 0; NULL = 1). */
+ipdg_status ipdg_set_kappa(ipdg_mesh mesh, const double* kappa);
+
+/* y = (lambda M - Lap_IPDG) x for device vectors x, y of the given dtype
+ * (Eq. ellipticOp1; computed in the regrouped strong form Eq. ellipticOp3).
+ * x and y must not overlap.  Asynchronous on hip_stream. */
+ipdg_status ipdg_apply(ipdg_mesh mesh, double lambda, double tau, ipdg_dtype dtype,
+                       const void* x, void* y, void* hip_stream);
+
+/* y = M x, the block-diagonal mass matrix J_e M (Eq. elMass, elementOps). */
+ipdg_status ipdg_mass_apply(ipdg_mesh mesh, ipdg_dtype dtype, const void* x, void* y,
+                            void* hip_stream);
+
+/* Solve A x = b by PCG (Sec. 3).  b, x: device FP64 vectors; x holds x0 on
+ * entry and the solution on exit.  Stops when ||r||_2 <= tol ||b||_2 with the
+ * true residual confirmed.  info may be NULL. */
+ipdg_status ipdg_pcg_solve(ipdg_mesh mesh, double lambda, double tau, const double* b,
+                           double* x, double tol, const ipdg_solve_opts* opts,
+                           ipdg_solve_info* info, void* hip_stream);
+
+/* One application z = B r of the preconditioner that ipdg_pcg_solve would use
+ * (device FP64 vectors).  Used to check a single V-cycle. */
+ipdg_status ipdg_precond_apply(ipdg_mesh mesh, double lambda, double tau,
+                               const ipdg_solve_opts* opts, const double* r, double* z,
+                               ipdg_solve_info* info, void* hip_stream);
+
+/* nb independent solves (lambda_i M - Lap) x_i = b_i, one mesh each (Sec. 3:
+ * per-component velocity Helmholtz solves), advanced together.  iters and
+ * relres are HOST arrays of nb entries (may be NULL). */
+ipdg_status ipdg_helmholtz_solve_batch(int nb, const ipdg_mesh* meshes, const double* lambdas,
+                                       double tau, const double* const* b, double* const* x,
+                                       double tol, const ipdg_solve_opts* opts, int* iters,
+                                       double* relres, void* hip_stream);
+
+/* dL/dkappa_e = -w^T (dA/dkappa_e) u for device FP64 vectors u, w;
+ * dLdkappa is a device array of K doubles. */
+ipdg_status ipdg_kappa_grad(ipdg_mesh mesh, double tau, const double* u, const double* w,
+                            double* dLdkappa, void* hip_stream);
+
+/* Host-only validation of a mesh, without any device use: the same checks
+ * and face matching as ipdg_mesh_create.  EToE (neighbour element, -1 on a
+ * boundary face) and EToF (neighbour's face index, -1 on a boundary face)
+ * are HOST arrays of K*3 entries, or NULL. */
+ipdg_status ipdg_mesh_check(int N, int Nv, const double* VX, const double* VY, int K,
+                            const int32_t* EToV, const int8_t* EToB, int32_t* EToE,
+                            int8_t* EToF);
+
+/* Host-only: reference nodes r, s (Np each) and the reference operators of
+ * Sec. 5.2, Eq. elMass / elLift on the bi-unit triangle: D_r, D_s, M
+ * (Np x Np, row-major) and LIFT (Np x 3 Nfp).  Any output may be NULL. */
+ipdg_status ipdg_reference_element(int N, double* r, double* s, double* Dr, double* Ds,
+                                   double* M, double* LIFT);
+
+/* Message of the last failed call on this thread ("" after a success). */
+const char* ipdg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* IPDG_H */

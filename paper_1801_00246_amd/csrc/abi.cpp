@@ -1,0 +1,278 @@
+// C ABI entry points (include/ipdg.h).  Every call catches library errors and
+// maps them to an ipdg_status; the message is kept per thread.
+#include <cstring>
+#include <string>
+
+#include "handle.hpp"
+#include "refelem.hpp"
+#include "solver.hpp"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+ipdg_status fail(ipdg_status s, const std::string& msg) {
+  g_last_error = msg;
+  return s;
+}
+
+template <typename F>
+ipdg_status guarded(F&& f) {
+  try {
+    g_last_error.clear();
+    return f();
+  } catch (const ipdg::Error& e) {
+    return fail(e.status, e.what());
+  } catch (const std::bad_alloc&) {
+    return fail(IPDG_ENOMEM, "host allocation failed");
+  } catch (const std::exception& e) {
+    return fail(IPDG_EINVAL, e.what());
+  }
+}
+
+ipdg::Kind kind_of(ipdg_dtype d) { return d == IPDG_F32 ? ipdg::Kind::F32 : ipdg::Kind::F64; }
+
+void upload_kappa(ipdg_mesh_s* m, const double* kappa) {
+  const int K = m->host.K;
+  if (!kappa) {
+    m->has_kappa = false;
+    m->kappa.clear();
+    return;
+  }
+  for (int e = 0; e < K; ++e)
+    if (!(kappa[e] > 0.0)) throw ipdg::Error(IPDG_EINVAL, "kappa must be positive");
+  m->kappa.assign(kappa, kappa + K);
+  std::vector<float> k32(kappa, kappa + K);
+  m->kap64.ensure(K * sizeof(double));
+  m->kap32.ensure(K * sizeof(float));
+  if (K) {
+    IPDG_HIP(hipMemcpy(m->kap64.get(), kappa, K * sizeof(double), hipMemcpyHostToDevice));
+    IPDG_HIP(hipMemcpy(m->kap32.get(), k32.data(), K * sizeof(float), hipMemcpyHostToDevice));
+  }
+  m->has_kappa = true;
+}
+
+}  // namespace
+
+extern "C" {
+
+void ipdg_default_opts(ipdg_solve_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->pc = IPDG_PC_JACOBI;
+  o->prec = IPDG_PREC_FP64;
+  o->max_iters = 10000;
+  o->check_every = 10;
+  o->flexible = -1;
+  o->n_levels = 0;
+  o->cheb_degree = 2;
+  o->cheb_lo = 0.1;
+  o->cheb_hi = 1.1;
+  o->rho_steps = 20;
+  o->coarse_tol = 1e-2;
+  o->coarse_max_iters = 200;
+  o->reliable_drop = 1e-3;
+}
+
+const char* ipdg_last_error(void) { return g_last_error.c_str(); }
+
+ipdg_status ipdg_mesh_create(int N, int Nv, const double* VX, const double* VY, int K,
+                             const int32_t* EToV, const int8_t* EToB, const double* kappa,
+                             ipdg_mesh* out) {
+  return guarded([&]() -> ipdg_status {
+    if (!out) return fail(IPDG_EINVAL, "out is null");
+    *out = nullptr;
+    if (N < 1 || N > ipdg::kMaxN) return fail(IPDG_EUNSUPPORTED, "degree outside 1..8");
+    auto m = std::make_unique<ipdg_mesh_s>();
+    std::string err = ipdg::build_host_mesh(N, Nv, VX, VY, K, EToV, EToB, m->host);
+    if (!err.empty()) return fail(IPDG_EMESH, err);
+    IPDG_HIP(hipGetDevice(&m->device));
+    m->Np = ipdg::np_of(N);
+    (void)ipdg::ref_ops(N);
+    std::vector<float> g32(m->host.geo.begin(), m->host.geo.end());
+    if (K > 0) {
+      m->geo64.alloc(m->host.geo.size() * sizeof(double));
+      m->geo32.alloc(g32.size() * sizeof(float));
+      m->conn.alloc(K * sizeof(ipdg::Conn));
+      IPDG_HIP(hipMemcpy(m->geo64.get(), m->host.geo.data(), m->host.geo.size() * sizeof(double),
+                         hipMemcpyHostToDevice));
+      IPDG_HIP(hipMemcpy(m->geo32.get(), g32.data(), g32.size() * sizeof(float), hipMemcpyHostToDevice));
+      IPDG_HIP(hipMemcpy(m->conn.get(), m->host.conn.data(), K * sizeof(ipdg::Conn),
+                         hipMemcpyHostToDevice));
+    }
+    upload_kappa(m.get(), kappa);
+    *out = m.release();
+    return IPDG_OK;
+  });
+}
+
+ipdg_status ipdg_mesh_destroy(ipdg_mesh mesh) {
+  return guarded([&]() -> ipdg_status {
+    delete mesh;
+    return IPDG_OK;
+  });
+}
+
+ipdg_status ipdg_mesh_info(ipdg_mesh mesh, int* N, int* Np, int* K) {
+  if (!mesh) return fail(IPDG_EINVAL, "mesh is null");
+  if (N) *N = mesh->host.N;
+  if (Np) *Np = mesh->Np;
+  if (K) *K = mesh->host.K;
+  return IPDG_OK;
+}
+
+ipdg_status ipdg_node_coords(ipdg_mesh mesh, double* x, double* y) {
+  return guarded([&]() -> ipdg_status {
+    if (!mesh || !x || !y) return fail(IPDG_EINVAL, "null argument");
+    std::vector<double> vx, vy;
+    ipdg::host_node_coords(mesh->host, vx, vy);
+    std::memcpy(x, vx.data(), vx.size() * sizeof(double));
+    std::memcpy(y, vy.data(), vy.size() * sizeof(double));
+    return IPDG_OK;
+  });
+}
+
+ipdg_status ipdg_set_kappa(ipdg_mesh mesh, const double* kappa) {
+  return guarded([&]() -> ipdg_status {
+    if (!mesh) return fail(IPDG_EINVAL, "mesh is null");
+    upload_kappa(mesh, kappa);
+    return IPDG_OK;
+  });
+}
+
+ipdg_status ipdg_apply(ipdg_mesh mesh, double lambda, double tau, ipdg_dtype dtype, const void* x,
+                       void* y, void* hip_stream) {
+  return guarded([&]() -> ipdg_status {
+    if (!mesh) return fail(IPDG_EINVAL, "mesh is null");
+    if (dtype != IPDG_F64 && dtype != IPDG_F32) return fail(IPDG_EINVAL, "bad dtype");
+    if (mesh->host.K == 0) return IPDG_OK;
+    if (!x || !y) return fail(IPDG_EINVAL, "null vector");
+    if (x == y) return fail(IPDG_EINVAL, "x and y must not overlap");
+    const int N = mesh->host.N;
+    const ipdg::Kind k = kind_of(dtype);
+    ipdg::ElemArgs a = ipdg::elem_args(mesh, N, k, lambda, ipdg::ctau_of(N, tau));
+    a.x = x;
+    a.y = y;
+    IPDG_HIP(ipdg::ax(N, k, a, static_cast<hipStream_t>(hip_stream)));
+    return IPDG_OK;
+  });
+}
+
+ipdg_status ipdg_mass_apply(ipdg_mesh mesh, ipdg_dtype dtype, const void* x, void* y,
+                            void* hip_stream) {
+  return guarded([&]() -> ipdg_status {
+    if (!mesh) return fail(IPDG_EINVAL, "mesh is null");
+    if (dtype != IPDG_F64 && dtype != IPDG_F32) return fail(IPDG_EINVAL, "bad dtype");
+    if (mesh->host.K == 0) return IPDG_OK;
+    if (!x || !y) return fail(IPDG_EINVAL, "null vector");
+    const int N = mesh->host.N;
+    const ipdg::Kind k = kind_of(dtype);
+    ipdg::ElemArgs a = ipdg::elem_args(mesh, N, k, 0.0, 0.0);
+    a.x = x;
+    a.y = y;
+    IPDG_HIP(ipdg::mass(N, k, a, static_cast<hipStream_t>(hip_stream)));
+    return IPDG_OK;
+  });
+}
+
+ipdg_status ipdg_pcg_solve(ipdg_mesh mesh, double lambda, double tau, const double* b, double* x,
+                           double tol, const ipdg_solve_opts* opts, ipdg_solve_info* info,
+                           void* hip_stream) {
+  return guarded([&]() -> ipdg_status {
+    if (!mesh) return fail(IPDG_EINVAL, "mesh is null");
+    ipdg_solve_opts o;
+    if (opts) o = *opts;
+    else ipdg_default_opts(&o);
+    return ipdg::pcg_solve(mesh, lambda, tau, b, x, tol, o, info,
+                           static_cast<hipStream_t>(hip_stream));
+  });
+}
+
+ipdg_status ipdg_precond_apply(ipdg_mesh mesh, double lambda, double tau,
+                               const ipdg_solve_opts* opts, const double* r, double* z,
+                               ipdg_solve_info* info, void* hip_stream) {
+  return guarded([&]() -> ipdg_status {
+    if (!mesh) return fail(IPDG_EINVAL, "mesh is null");
+    ipdg_solve_opts o;
+    if (opts) o = *opts;
+    else ipdg_default_opts(&o);
+    return ipdg::precond_apply(mesh, lambda, tau, o, r, z, info,
+                               static_cast<hipStream_t>(hip_stream));
+  });
+}
+
+ipdg_status ipdg_helmholtz_solve_batch(int nb, const ipdg_mesh* meshes, const double* lambdas,
+                                       double tau, const double* const* b, double* const* x,
+                                       double tol, const ipdg_solve_opts* opts, int* iters,
+                                       double* relres, void* hip_stream) {
+  return guarded([&]() -> ipdg_status {
+    if (nb < 0) return fail(IPDG_EINVAL, "nb < 0");
+    if (nb == 0) return IPDG_OK;
+    if (!meshes || !lambdas || !b || !x) return fail(IPDG_EINVAL, "null argument");
+    ipdg_solve_opts o;
+    if (opts) o = *opts;
+    else {
+      ipdg_default_opts(&o);
+      o.pc = IPDG_PC_BLOCK_MASS;
+    }
+    return ipdg::solve_batch(nb, meshes, lambdas, tau, b, x, tol, o, iters, relres,
+                             static_cast<hipStream_t>(hip_stream));
+  });
+}
+
+ipdg_status ipdg_kappa_grad(ipdg_mesh mesh, double tau, const double* u, const double* w,
+                            double* dLdkappa, void* hip_stream) {
+  return guarded([&]() -> ipdg_status {
+    if (!mesh) return fail(IPDG_EINVAL, "mesh is null");
+    if (mesh->host.K == 0) return IPDG_OK;
+    if (!u || !w || !dLdkappa) return fail(IPDG_EINVAL, "null vector");
+    const int N = mesh->host.N;
+    if (!mesh->has_kappa) {
+      std::vector<double> ones(mesh->host.K, 1.0);
+      upload_kappa(mesh, ones.data());
+    }
+    ipdg::KgradArgs a{u, w, dLdkappa, mesh->geo64.as<double>(), mesh->conn.as<ipdg::Conn>(),
+                      mesh->kap64.as<double>(),
+                      static_cast<const double*>(ipdg::device_ops(N, ipdg::Kind::F64)),
+                      ipdg::ctau_of(N, tau), mesh->host.K};
+    IPDG_HIP(ipdg::kgrad(N, a, static_cast<hipStream_t>(hip_stream)));
+    return IPDG_OK;
+  });
+}
+
+/* Host-only check of a mesh (no device use): connectivity and validation as
+ * in ipdg_mesh_create.  EToE / EToF are HOST arrays of K*3 (may be NULL). */
+ipdg_status ipdg_mesh_check(int N, int Nv, const double* VX, const double* VY, int K,
+                            const int32_t* EToV, const int8_t* EToB, int32_t* EToE, int8_t* EToF) {
+  return guarded([&]() -> ipdg_status {
+    ipdg::HostMesh h;
+    std::string err = ipdg::build_host_mesh(N, Nv, VX, VY, K, EToV, EToB, h);
+    if (!err.empty()) return fail(N < 1 || N > ipdg::kMaxN ? IPDG_EUNSUPPORTED : IPDG_EMESH, err);
+    if (EToE) std::memcpy(EToE, h.EToE.data(), h.EToE.size() * sizeof(int32_t));
+    if (EToF) std::memcpy(EToF, h.EToF.data(), h.EToF.size() * sizeof(int8_t));
+    return IPDG_OK;
+  });
+}
+
+/* Host-only: reference nodes (r, s; Np each) and operators D_r, D_s, M
+ * (Np x Np, row-major) and LIFT (Np x 3 Nfp) of degree N.  Any pointer may
+ * be NULL. */
+ipdg_status ipdg_reference_element(int N, double* r, double* s, double* Dr, double* Ds,
+                                   double* M, double* LIFT) {
+  return guarded([&]() -> ipdg_status {
+    if (N < 1 || N > ipdg::kMaxN) return fail(IPDG_EUNSUPPORTED, "degree outside 1..8");
+    const ipdg::RefOps& R = ipdg::ref_ops(N);
+    auto cp = [](double* dst, const std::vector<double>& v) {
+      if (dst) std::memcpy(dst, v.data(), v.size() * sizeof(double));
+    };
+    cp(r, R.r);
+    cp(s, R.s);
+    cp(Dr, R.Dr);
+    cp(Ds, R.Ds);
+    cp(M, R.M);
+    cp(LIFT, R.LIFT);
+    return IPDG_OK;
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,61 @@
+// Device-side helpers shared by the HIP kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ipdg {
+
+// Connectivity record of one element.  nb[f]: element across face f (the
+// element itself on a boundary face).  info: bits 2f..2f+1 hold the
+// neighbour's local index of the shared face, bits 8+2f..9+2f the boundary
+// flag of face f (0 interior, 1 Dirichlet, 2 Neumann).
+struct alignas(16) Conn {
+  int nb[3];
+  int info;
+};
+
+__host__ __device__ inline int conn_fp(int info, int f) { return (info >> (2 * f)) & 3; }
+__host__ __device__ inline int conn_bc(int info, int f) { return (info >> (8 + 2 * f)) & 3; }
+
+constexpr int kBlock = 256;   // threads per block of the element kernels
+constexpr int kXcd = 8;       // accelerator complex dies of an MI355X
+
+// Block b of a launch of kXcd * per blocks -> tile index.  Blocks are
+// dispatched round-robin over the dies, so consecutive tiles (which share
+// neighbour data) are given to blocks that land on the same die and L2.
+__device__ __forceinline__ int xcd_tile(int b, int per) { return (b % kXcd) * per + b / kXcd; }
+
+inline int xcd_grid(int ntiles, int& per) {
+  per = (ntiles + kXcd - 1) / kXcd;
+  return per * kXcd;
+}
+
+// Sum of v over the block, valid in thread 0.  Fixed reduction order, so the
+// result is bitwise reproducible for a given launch shape.
+template <int NV>
+__device__ __forceinline__ void block_sum(double (&v)[NV]) {
+  __shared__ double red[kBlock / 64][NV];
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    double s = v[k];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+    v[k] = s;
+  }
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0)
+#pragma unroll
+    for (int k = 0; k < NV; ++k) red[w][k] = v[k];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      double s = red[0][k];
+#pragma unroll
+      for (int ww = 1; ww < kBlock / 64; ++ww) s += red[ww][k];
+      v[k] = s;
+    }
+  }
+}
+
+}  // namespace ipdg

@@ -1,0 +1,55 @@
+// Runtime-degree dispatch to the per-degree kernel instantiations.
+#include "kernels.hpp"
+
+namespace ipdg {
+
+#define IPDG_SWITCH(N_, CALL)      \
+  switch (N_) {                    \
+    case 1: return CALL(1);        \
+    case 2: return CALL(2);        \
+    case 3: return CALL(3);        \
+    case 4: return CALL(4);        \
+    case 5: return CALL(5);        \
+    case 6: return CALL(6);        \
+    case 7: return CALL(7);        \
+    case 8: return CALL(8);        \
+    default: return hipErrorInvalidValue; \
+  }
+
+hipError_t ax(int N, Kind kind, const ElemArgs& a, hipStream_t s) {
+#define C(n) launch_ax<n>(kind, a, s)
+  IPDG_SWITCH(N, C)
+#undef C
+}
+hipError_t diag(int N, Kind kind, const ElemArgs& a, hipStream_t s) {
+#define C(n) launch_diag<n>(kind, a, s)
+  IPDG_SWITCH(N, C)
+#undef C
+}
+hipError_t mass(int N, Kind kind, const ElemArgs& a, hipStream_t s) {
+#define C(n) launch_mass<n>(kind, a, s)
+  IPDG_SWITCH(N, C)
+#undef C
+}
+hipError_t minv(int N, Kind kind, const ElemArgs& a, hipStream_t s) {
+#define C(n) launch_minv<n>(kind, a, s)
+  IPDG_SWITCH(N, C)
+#undef C
+}
+hipError_t kgrad(int N, const KgradArgs& a, hipStream_t s) {
+#define C(n) launch_kgrad<n>(a, s)
+  IPDG_SWITCH(N, C)
+#undef C
+}
+hipError_t restrict_(int Nf, int Nc, Kind kind, const TransferArgs& a, hipStream_t s) {
+#define C(n) launch_restrict<n>(Nc, kind, a, s)
+  IPDG_SWITCH(Nf, C)
+#undef C
+}
+hipError_t prolong(int Nf, int Nc, Kind kind, const TransferArgs& a, hipStream_t s) {
+#define C(n) launch_prolong<n>(Nc, kind, a, s)
+  IPDG_SWITCH(Nf, C)
+#undef C
+}
+
+}  // namespace ipdg

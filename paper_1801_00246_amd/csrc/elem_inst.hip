@@ -1,0 +1,403 @@
+// Element kernels of one polynomial degree (compiled once per degree with
+// -DIPDG_N=<N>).  One lane owns one element; a block owns kBlock consecutive
+// elements; blocks are mapped to tiles so that neighbouring tiles run on the
+// same die (shared L2 for the neighbour gathers).
+#include "kernels.hpp"
+#include "sipdg_core.hpp"
+
+#ifndef IPDG_N
+#error "IPDG_N must be defined"
+#endif
+
+namespace ipdg {
+namespace {
+
+constexpr int N = IPDG_N;
+constexpr int Np = Tri<N>::Np;
+
+// Minimum waves per SIMD the register allocator must leave room for: the
+// operator kernel holds one element per lane, so its footprint grows with
+// Np; FP32 halves it.
+template <typename TC>
+constexpr int ax_waves() {
+  if constexpr (sizeof(TC) == 8) return N <= 2 ? 4 : (N <= 4 ? 3 : (N <= 6 ? 2 : 1));
+  else return N <= 2 ? 8 : (N <= 4 ? 5 : (N <= 6 ? 3 : 2));
+}
+
+template <typename TC, typename TX, typename TY, bool KAP>
+__global__ __launch_bounds__(kBlock) void k_ax(const TX* __restrict__ x, TY* __restrict__ y,
+                                               const TC* __restrict__ geo,
+                                               const Conn* __restrict__ conn,
+                                               const TC* __restrict__ kap,
+                                               const TC* __restrict__ ops, TC lambda, TC ctau,
+                                               int K, int per, double* __restrict__ partials,
+                                               const int* __restrict__ skip) {
+  if (skip && *skip) return;
+  const int e = xcd_tile(blockIdx.x, per) * kBlock + threadIdx.x;
+  double dot = 0.0;
+  if (e < K) {
+    TC u[Np];
+    TY* ye = y + (size_t)e * Np;
+    sipdg_element<N, TC, TX, KAP, false>(e, x, geo, conn, kap, ops, lambda, ctau, 0, u,
+                                         [&](int i, TC v) {
+                                           ye[i] = static_cast<TY>(v);
+                                           dot += static_cast<double>(u[i]) * static_cast<double>(v);
+                                         });
+  }
+  if (partials) {
+    double v[1] = {dot};
+    block_sum<1>(v);
+    if (threadIdx.x == 0) partials[blockIdx.x] = v[0];
+  }
+}
+
+template <typename TC, bool KAP>
+__global__ __launch_bounds__(kBlock) void k_diag(TC* __restrict__ d, const TC* __restrict__ geo,
+                                                 const Conn* __restrict__ conn,
+                                                 const TC* __restrict__ kap,
+                                                 const TC* __restrict__ ops, TC lambda, TC ctau,
+                                                 int K, int per) {
+  const int e = xcd_tile(blockIdx.x, per) * kBlock + threadIdx.x;
+  if (e >= K) return;
+  for (int i = 0; i < Np; ++i) {
+    TC u[Np];
+    TC di = TC(0);
+    sipdg_element<N, TC, TC, KAP, true>(e, static_cast<const TC*>(nullptr), geo, conn, kap, ops,
+                                        lambda, ctau, i, u,
+                                        [&](int j, TC v) { di = (j == i) ? v : di; });
+    d[(size_t)e * Np + i] = di;
+  }
+}
+
+// y = J M x (INV = false) or y = (J M)^{-1} x (INV = true)
+template <typename TC, typename TX, typename TY, bool INV>
+__global__ __launch_bounds__(kBlock) void k_mass(const TX* __restrict__ x, TY* __restrict__ y,
+                                                 const TC* __restrict__ geo,
+                                                 const TC* __restrict__ ops, int K, int per,
+                                                 const int* __restrict__ skip) {
+  if (skip && *skip) return;
+  using L = OpsLayout<N>;
+  const int e = xcd_tile(blockIdx.x, per) * kBlock + threadIdx.x;
+  if (e >= K) return;
+  const TC rx = geo[4 * e + 0], sx = geo[4 * e + 1], ry = geo[4 * e + 2], sy = geo[4 * e + 3];
+  const TC det = rx * sy - sx * ry;  // 1 / J
+  TC u[Np];
+#pragma unroll
+  for (int j = 0; j < Np; ++j) u[j] = static_cast<TC>(x[(size_t)e * Np + j]);
+#pragma unroll
+  for (int i = 0; i < Np; ++i) {
+    TC acc = TC(0);
+#pragma unroll
+    for (int j = 0; j < Np; ++j) acc += ops[(INV ? L::Minv : L::M) + i * Np + j] * u[j];
+    y[(size_t)e * Np + i] = static_cast<TY>(INV ? acc * det : acc / det);
+  }
+}
+
+// Restriction rc = P^T (f - Az) and prolongation z += P zc per element.
+template <int NC, typename T>
+__global__ __launch_bounds__(kBlock) void k_restrict(const T* __restrict__ f, const T* __restrict__ Az,
+                                                     T* __restrict__ rc, const T* __restrict__ P,
+                                                     int K, int per, const int* __restrict__ skip) {
+  if (skip && *skip) return;
+  constexpr int Npc = Tri<NC>::Np;
+  const int e = xcd_tile(blockIdx.x, per) * kBlock + threadIdx.x;
+  if (e >= K) return;
+  T r[Np];
+#pragma unroll
+  for (int j = 0; j < Np; ++j) r[j] = f[(size_t)e * Np + j] - Az[(size_t)e * Np + j];
+#pragma unroll
+  for (int c = 0; c < Npc; ++c) {
+    T acc = T(0);
+#pragma unroll
+    for (int j = 0; j < Np; ++j) acc += P[j * Npc + c] * r[j];
+    rc[(size_t)e * Npc + c] = acc;
+  }
+}
+
+template <int NC, typename T>
+__global__ __launch_bounds__(kBlock) void k_prolong(const T* __restrict__ zc, T* __restrict__ z,
+                                                    const T* __restrict__ P, int K, int per,
+                                                    const int* __restrict__ skip) {
+  if (skip && *skip) return;
+  constexpr int Npc = Tri<NC>::Np;
+  const int e = xcd_tile(blockIdx.x, per) * kBlock + threadIdx.x;
+  if (e >= K) return;
+  T c[Npc];
+#pragma unroll
+  for (int j = 0; j < Npc; ++j) c[j] = zc[(size_t)e * Npc + j];
+#pragma unroll
+  for (int i = 0; i < Np; ++i) {
+    T acc = z[(size_t)e * Np + i];
+#pragma unroll
+    for (int j = 0; j < Npc; ++j) acc += P[i * Npc + j] * c[j];
+    z[(size_t)e * Np + i] = acc;
+  }
+}
+
+
+// dL/dkappa_e = -w^T (dA/dkappa_e) u for the kappa-weighted form
+//   a(u,v) = sum_e k_e (grad u, grad v)_E
+//          - sum_F ({k d_n u}, <v>)_F + ({k d_n v}, <u>)_F - tau_F (<u>, <v>)_F
+// with <u> = u- - u+ and tau_F = c_tau max(k- Fs-, k+ Fs+); the Dirichlet
+// ghost takes k+ = k-.  Per element e:
+//   d/dk_e = (grad u, grad w)_E
+//          + sum_{interior f} [ -1/2 (d_n u-, <w>)_f - 1/2 (d_n w-, <u>)_f
+//                               + dtau_f (<u>, <w>)_f ]
+//          + sum_{Dirichlet f} [ -(d_n u, w)_f - (d_n w, u)_f
+//                                + 2 c_tau Fs_f (u, w)_f ]
+// where dtau_f = c_tau Fs_f when e's side attains the max (ties go to the
+// lower element id), else 0.  Face integrals use sJ_f M1D on face nodes.
+__global__ __launch_bounds__(kBlock) void k_kgrad(const double* __restrict__ u,
+                                                  const double* __restrict__ w,
+                                                  double* __restrict__ out,
+                                                  const double* __restrict__ geo,
+                                                  const Conn* __restrict__ conn,
+                                                  const double* __restrict__ kap,
+                                                  const double* __restrict__ ops, double ctau,
+                                                  int K, int per) {
+  using G = Tri<N>;
+  using L = OpsLayout<N>;
+  constexpr int Nfp = G::Nfp;
+  const int e = xcd_tile(blockIdx.x, per) * kBlock + threadIdx.x;
+  if (e >= K) return;
+  const double rx = geo[4 * e + 0], sx = geo[4 * e + 1], ry = geo[4 * e + 2], sy = geo[4 * e + 3];
+  const double J = 1.0 / (rx * sy - sx * ry);
+  const double ke = kap[e];
+  double ue[Np], we[Np];
+#pragma unroll
+  for (int j = 0; j < Np; ++j) {
+    ue[j] = u[(size_t)e * Np + j];
+    we[j] = w[(size_t)e * Np + j];
+  }
+  double ur[Np], us[Np], wr[Np], ws[Np];
+#pragma unroll
+  for (int i = 0; i < Np; ++i) {
+    double a = 0, b = 0, c = 0, d = 0;
+#pragma unroll
+    for (int j = 0; j < Np; ++j) {
+      a += ops[L::Dr + i * Np + j] * ue[j];
+      b += ops[L::Ds + i * Np + j] * ue[j];
+      c += ops[L::Dr + i * Np + j] * we[j];
+      d += ops[L::Ds + i * Np + j] * we[j];
+    }
+    ur[i] = a; us[i] = b; wr[i] = c; ws[i] = d;
+  }
+  const double grr = rx * rx + ry * ry, grs = rx * sx + ry * sy, gss = sx * sx + sy * sy;
+  double vol = 0.0;
+#pragma unroll
+  for (int i = 0; i < Np; ++i) {
+    double mwr = 0, mws = 0;
+#pragma unroll
+    for (int j = 0; j < Np; ++j) {
+      mwr += ops[L::M + i * Np + j] * wr[j];
+      mws += ops[L::M + i * Np + j] * ws[j];
+    }
+    vol += grr * ur[i] * mwr + grs * (ur[i] * mws + us[i] * mwr) + gss * us[i] * mws;
+  }
+  double tot = J * vol;
+  const Conn c = conn[e];
+  const double gx[3] = {-sx, rx + sx, -rx};
+  const double gy[3] = {-sy, ry + sy, -ry};
+  static_for<0, 3>([&](auto fc) {
+    constexpr int f = decltype(fc)::value;
+    const int bc = conn_bc(c.info, f);
+    if (bc == 2) return;
+    const double Fs = sqrt(gx[f] * gx[f] + gy[f] * gy[f]);
+    const double nx = gx[f] / Fs, ny = gy[f] / Fs;
+    const double nr = nx * rx + ny * ry, ns = nx * sx + ny * sy;
+    const double sJ = Fs * J;
+    const int nb = c.nb[f];
+    const int fp = conn_fp(c.info, f);
+    double du[Nfp], dw[Nfp], ju[Nfp], jw[Nfp];
+    static_for<0, Nfp>([&](auto kc) {
+      constexpr int k = decltype(kc)::value;
+      constexpr int vm = G::fm(f, k);
+      constexpr int m = Nfp - 1 - k;
+      constexpr int o1 = G::rot(1, m), o2 = G::rot(2, m);
+      const int o = fp == 0 ? m : (fp == 1 ? o1 : o2);
+      du[k] = nr * ur[vm] + ns * us[vm];
+      dw[k] = nr * wr[vm] + ns * ws[vm];
+      const double up = (bc == 0) ? u[(size_t)nb * Np + o] : -ue[vm];
+      const double wp = (bc == 0) ? w[(size_t)nb * Np + o] : -we[vm];
+      ju[k] = ue[vm] - up;
+      jw[k] = we[vm] - wp;
+    });
+    double t1 = 0, t2 = 0, t3 = 0;
+#pragma unroll
+    for (int p = 0; p < Nfp; ++p) {
+      double a = 0, b = 0;
+#pragma unroll
+      for (int k = 0; k < Nfp; ++k) {
+        a += ops[L::M1D + p * Nfp + k] * jw[k];
+        b += ops[L::M1D + p * Nfp + k] * ju[k];
+      }
+      t1 += du[p] * a;      // (d_n u, <w>)
+      t2 += dw[p] * b;      // (d_n w, <u>)
+      t3 += ju[p] * a;      // (<u>, <w>)
+    }
+    if (bc == 0) {
+      // neighbour face scale: grad s' of the neighbour's rotated frame
+      const double prx = geo[4 * nb + 0], psx = geo[4 * nb + 1], pry = geo[4 * nb + 2], psy = geo[4 * nb + 3];
+      const double qx = -(prx + psx), qy = -(pry + psy);
+      const double Sx = fp == 0 ? psx : (fp == 1 ? qx : prx);
+      const double Sy = fp == 0 ? psy : (fp == 1 ? qy : pry);
+      const double Fsp = sqrt(Sx * Sx + Sy * Sy);
+      const double mine = ke * Fs, other = kap[nb] * Fsp;
+      const bool owns = mine > other || (mine == other && e < nb);
+      const double dtau = owns ? ctau * Fs : 0.0;
+      tot += sJ * (-0.5 * t1 - 0.5 * t2 + dtau * t3);
+    } else {
+      // Dirichlet: <u> = 2u, <w> = 2w on the mirror ghost
+      tot += sJ * (-0.5 * t1 - 0.5 * t2 + 0.5 * ctau * Fs * t3);
+    }
+  });
+  out[e] = -tot;
+}
+
+template <typename TC, typename TX, typename TY>
+hipError_t run_ax(const ElemArgs& a, hipStream_t s) {
+  int per;
+  const int grid = xcd_grid(elem_tiles(a.K), per);
+  if (a.K == 0) return hipSuccess;
+  if (a.kap)
+    hipLaunchKernelGGL((k_ax<TC, TX, TY, true>), dim3(grid), dim3(kBlock), 0, s,
+                       static_cast<const TX*>(a.x), static_cast<TY*>(a.y),
+                       static_cast<const TC*>(a.geo), a.conn, static_cast<const TC*>(a.kap),
+                       static_cast<const TC*>(a.ops), TC(a.lambda), TC(a.ctau), a.K, per,
+                       a.partials, a.skip);
+  else
+    hipLaunchKernelGGL((k_ax<TC, TX, TY, false>), dim3(grid), dim3(kBlock), 0, s,
+                       static_cast<const TX*>(a.x), static_cast<TY*>(a.y),
+                       static_cast<const TC*>(a.geo), a.conn, static_cast<const TC*>(a.kap),
+                       static_cast<const TC*>(a.ops), TC(a.lambda), TC(a.ctau), a.K, per,
+                       a.partials, a.skip);
+  return hipGetLastError();
+}
+
+template <typename TC>
+hipError_t run_diag(const ElemArgs& a, hipStream_t s) {
+  int per;
+  const int grid = xcd_grid(elem_tiles(a.K), per);
+  if (a.K == 0) return hipSuccess;
+  if (a.kap)
+    hipLaunchKernelGGL((k_diag<TC, true>), dim3(grid), dim3(kBlock), 0, s, static_cast<TC*>(a.y),
+                       static_cast<const TC*>(a.geo), a.conn, static_cast<const TC*>(a.kap),
+                       static_cast<const TC*>(a.ops), TC(a.lambda), TC(a.ctau), a.K, per);
+  else
+    hipLaunchKernelGGL((k_diag<TC, false>), dim3(grid), dim3(kBlock), 0, s, static_cast<TC*>(a.y),
+                       static_cast<const TC*>(a.geo), a.conn, static_cast<const TC*>(a.kap),
+                       static_cast<const TC*>(a.ops), TC(a.lambda), TC(a.ctau), a.K, per);
+  return hipGetLastError();
+}
+
+template <typename TC, typename TX, typename TY, bool INV>
+hipError_t run_mass(const ElemArgs& a, hipStream_t s) {
+  int per;
+  const int grid = xcd_grid(elem_tiles(a.K), per);
+  if (a.K == 0) return hipSuccess;
+  hipLaunchKernelGGL((k_mass<TC, TX, TY, INV>), dim3(grid), dim3(kBlock), 0, s,
+                     static_cast<const TX*>(a.x), static_cast<TY*>(a.y),
+                     static_cast<const TC*>(a.geo), static_cast<const TC*>(a.ops), a.K, per, a.skip);
+  return hipGetLastError();
+}
+
+template <int NC, typename T>
+hipError_t run_restrict(const TransferArgs& a, hipStream_t s) {
+  int per;
+  const int grid = xcd_grid(elem_tiles(a.K), per);
+  if (a.K == 0) return hipSuccess;
+  hipLaunchKernelGGL((k_restrict<NC, T>), dim3(grid), dim3(kBlock), 0, s,
+                     static_cast<const T*>(a.f), static_cast<const T*>(a.Az),
+                     static_cast<T*>(a.coarse), static_cast<const T*>(a.P), a.K, per, a.skip);
+  return hipGetLastError();
+}
+
+template <int NC, typename T>
+hipError_t run_prolong(const TransferArgs& a, hipStream_t s) {
+  int per;
+  const int grid = xcd_grid(elem_tiles(a.K), per);
+  if (a.K == 0) return hipSuccess;
+  hipLaunchKernelGGL((k_prolong<NC, T>), dim3(grid), dim3(kBlock), 0, s,
+                     static_cast<const T*>(a.coarse), static_cast<T*>(a.fine),
+                     static_cast<const T*>(a.P), a.K, per, a.skip);
+  return hipGetLastError();
+}
+
+template <int NC>
+hipError_t transfer_dispatch(bool restrict_op, Kind kind, const TransferArgs& a, hipStream_t s) {
+  if (kind == Kind::F64)
+    return restrict_op ? run_restrict<NC, double>(a, s) : run_prolong<NC, double>(a, s);
+  return restrict_op ? run_restrict<NC, float>(a, s) : run_prolong<NC, float>(a, s);
+}
+
+hipError_t transfer(int Nc, bool restrict_op, Kind kind, const TransferArgs& a, hipStream_t s) {
+  if (Nc >= N || Nc < 1) return hipErrorInvalidValue;
+  switch (Nc) {
+#define IPDG_TCASE(c) \
+  case c:             \
+    if constexpr (c < N) return transfer_dispatch<c>(restrict_op, kind, a, s); \
+    break;
+    IPDG_TCASE(1) IPDG_TCASE(2) IPDG_TCASE(3) IPDG_TCASE(4) IPDG_TCASE(5) IPDG_TCASE(6) IPDG_TCASE(7)
+#undef IPDG_TCASE
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+template <>
+hipError_t launch_ax<N>(Kind kind, const ElemArgs& a, hipStream_t s) {
+  switch (kind) {
+    case Kind::F64: return run_ax<double, double, double>(a, s);
+    case Kind::F32: return run_ax<float, float, float>(a, s);
+    case Kind::F32_IN64: return run_ax<float, double, float>(a, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <>
+hipError_t launch_diag<N>(Kind kind, const ElemArgs& a, hipStream_t s) {
+  return kind == Kind::F64 ? run_diag<double>(a, s) : run_diag<float>(a, s);
+}
+
+template <>
+hipError_t launch_mass<N>(Kind kind, const ElemArgs& a, hipStream_t s) {
+  switch (kind) {
+    case Kind::F64: return run_mass<double, double, double, false>(a, s);
+    case Kind::F32: return run_mass<float, float, float, false>(a, s);
+    case Kind::F32_IN64: return run_mass<float, double, float, false>(a, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <>
+hipError_t launch_minv<N>(Kind kind, const ElemArgs& a, hipStream_t s) {
+  switch (kind) {
+    case Kind::F64: return run_mass<double, double, double, true>(a, s);
+    case Kind::F32: return run_mass<float, float, float, true>(a, s);
+    case Kind::F32_IN64: return run_mass<float, double, float, true>(a, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <>
+hipError_t launch_kgrad<N>(const KgradArgs& a, hipStream_t s) {
+  int per;
+  const int grid = xcd_grid(elem_tiles(a.K), per);
+  if (a.K == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_kgrad, dim3(grid), dim3(kBlock), 0, s, a.u, a.w, a.out, a.geo, a.conn, a.kap,
+                     a.ops, a.ctau, a.K, per);
+  return hipGetLastError();
+}
+
+template <>
+hipError_t launch_restrict<N>(int Nc, Kind kind, const TransferArgs& a, hipStream_t s) {
+  return transfer(Nc, true, kind, a, s);
+}
+
+template <>
+hipError_t launch_prolong<N>(int Nc, Kind kind, const TransferArgs& a, hipStream_t s) {
+  return transfer(Nc, false, kind, a, s);
+}
+
+}  // namespace ipdg

@@ -1,0 +1,74 @@
+// Launch interface between the host solver code and the per-degree kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "device_common.hpp"
+
+namespace ipdg {
+
+// Compute / storage precision combinations of the element kernels.
+//   F64      : FP64 arithmetic, FP64 in, FP64 out
+//   F32      : FP32 arithmetic, FP32 in, FP32 out
+//   F32_IN64 : FP32 arithmetic, FP64 in, FP32 out (mixed-precision outer CG)
+enum class Kind { F64 = 0, F32 = 1, F32_IN64 = 2 };
+
+// Type-erased arguments; geo/kap/ops are in the arithmetic precision.
+struct ElemArgs {
+  const void* x = nullptr;
+  void* y = nullptr;
+  const void* geo = nullptr;
+  const Conn* conn = nullptr;
+  const void* kap = nullptr;     // non-null => kappa-weighted operator
+  const void* ops = nullptr;
+  double lambda = 0.0, ctau = 0.0;
+  int K = 0;
+  double* partials = nullptr;    // optional: per-block sums of x.y
+  const int* skip = nullptr;     // optional: device flag, kernel is a no-op when set
+};
+
+inline int elem_tiles(int K) { return (K + kBlock - 1) / kBlock; }
+inline int elem_grid(int K) {
+  int per;
+  return xcd_grid(elem_tiles(K), per);
+}
+
+// y = A x (SIPDG operator).  Per degree, defined in the per-degree units.
+template <int N> hipError_t launch_ax(Kind kind, const ElemArgs& a, hipStream_t s);
+// y = diag(A) (x unused).
+template <int N> hipError_t launch_diag(Kind kind, const ElemArgs& a, hipStream_t s);
+// y = J M x  (block-diagonal mass)
+template <int N> hipError_t launch_mass(Kind kind, const ElemArgs& a, hipStream_t s);
+// y = (J M)^{-1} x  (block inverse mass)
+template <int N> hipError_t launch_minv(Kind kind, const ElemArgs& a, hipStream_t s);
+// dL/dkappa_e = -w^T dA/dkappa_e u  (x = u, y unused, partials unused)
+struct KgradArgs {
+  const double* u; const double* w; double* out;
+  const double* geo; const Conn* conn; const double* kap; const double* ops;
+  double ctau; int K;
+};
+template <int N> hipError_t launch_kgrad(const KgradArgs& a, hipStream_t s);
+
+// Inter-degree transfer: restriction rc = P^T (f - Az) and prolongation
+// z += P zc, P the degree-Nc -> degree-Nf interpolation (Nf x Nc per element).
+struct TransferArgs {
+  const void* f = nullptr;   // restriction: fine right-hand side
+  const void* Az = nullptr;  // restriction: A z on the fine level
+  void* coarse = nullptr;    // restriction out / prolongation in
+  void* fine = nullptr;      // prolongation in/out (z)
+  const void* P = nullptr;   // interpolation matrix in arithmetic precision
+  int K = 0;
+  const int* skip = nullptr;
+};
+template <int Nf> hipError_t launch_restrict(int Nc, Kind kind, const TransferArgs& a, hipStream_t s);
+template <int Nf> hipError_t launch_prolong(int Nc, Kind kind, const TransferArgs& a, hipStream_t s);
+
+// Runtime-degree dispatch (dispatch.cpp)
+hipError_t ax(int N, Kind kind, const ElemArgs& a, hipStream_t s);
+hipError_t diag(int N, Kind kind, const ElemArgs& a, hipStream_t s);
+hipError_t mass(int N, Kind kind, const ElemArgs& a, hipStream_t s);
+hipError_t minv(int N, Kind kind, const ElemArgs& a, hipStream_t s);
+hipError_t kgrad(int N, const KgradArgs& a, hipStream_t s);
+hipError_t restrict_(int Nf, int Nc, Kind kind, const TransferArgs& a, hipStream_t s);
+hipError_t prolong(int Nf, int Nc, Kind kind, const TransferArgs& a, hipStream_t s);
+
+}  // namespace ipdg

@@ -1,0 +1,238 @@
+// One-element evaluation of the SIPDG screened-Poisson operator.
+//
+// For element e (Sec. 5.2, Eq. ellipticOp3, with the reference-element
+// factorisation of Eq. elementOps; the jump is [u] = u+ - u-):
+//
+//   y_e = -J k_e (S_r a + S_s b) + lambda J M u - sum_f sJ_f M1D s_f
+//   a = grad r . q,  b = grad s . q,   q = grad u + l,
+//   l   = 1/2 sum_f n_f Fs_f L^f [u]_f          (lifted jump, vector field)
+//   s_f = 1/2 [k d_n u]_f + tau_f [u]_f - k_e n_f . l   (at face-f nodes)
+//
+// with S_r = M D_r, S_s = M D_s, L^f the lift of face f, Fs_f = |F|/|E| and
+// sJ_f = Fs_f J.  The paper's kernel pseudo-code takes the same steps (local
+// gradient, lifted jumps, volume term, surface term, lift, mass) in two
+// kernels; here they are fused into one pass over the element and its three
+// neighbours.  Because the metric is constant per element, S_r a + S_s b
+// expands into products of fixed reference matrices and the element's nodal
+// values:
+//   S_r a + S_s b = (g_rr K_rr + g_rs K_rs + g_ss K_ss) u
+//                 + sum_f (c^r_f Q^r_f + c^s_f Q^s_f) [u]_f
+// with K_rr = M D_r D_r, K_rs = M (D_r D_s + D_s D_r), K_ss = M D_s D_s,
+// Q^r_f = M D_r L^f, Q^s_f = M D_s L^f, g_.. = grad . . grad ., and
+// c^r_f = 1/2 grad r . g_f, c^s_f = 1/2 grad s . g_f.  Only u and O(N) face
+// values are then live at once, which keeps the one-element-per-lane mapping
+// in registers up to N = 8.
+//
+// Every geometric quantity is derived in-register from the four metric
+// terms (r_x, s_x, r_y, s_y): outward face directions g_0 = -grad s,
+// g_1 = grad r + grad s, g_2 = -grad r, Fs_f = |g_f|, n_f = g_f / Fs_f,
+// J = 1 / (r_x s_y - s_x r_y).
+//
+// The neighbour's normal derivative on the shared face is evaluated in the
+// frame whose vertex 0 is the neighbour's vertex fp (its face fp becomes face
+// 0), so the derivative rows used are always those of face 0 and all operator
+// entries are wave-uniform compile-time offsets (scalar loads), while the
+// neighbour's nodal values are gathered in rotated order.
+#pragma once
+#include "device_common.hpp"
+#include "tri.hpp"
+
+namespace ipdg {
+
+template <typename TX, typename TC>
+__host__ __device__ __forceinline__ TC ld(const TX* p) { return static_cast<TC>(*p); }
+
+// A zero the optimiser cannot see through.  Added to the operator offsets of
+// one phase (a face, a face node, an output row), it keeps that phase's
+// scalar operator loads from being hoisted to the top of the kernel, where
+// hundreds of them would be live at once and spill.  One s_mov per phase.
+__host__ __device__ __forceinline__ int opaque_zero() {
+#if defined(__HIP_DEVICE_COMPILE__)
+  int z;
+  asm volatile("s_mov_b32 %0, 0" : "=s"(z));
+  return z;
+#else
+  return 0;
+#endif
+}
+
+// Keeps the scheduler from hoisting the next phase's neighbour gathers above
+// the current one (which would hold three neighbours' values in registers).
+__host__ __device__ __forceinline__ void phase_fence() {
+#if defined(__HIP_DEVICE_COMPILE__)
+  __builtin_amdgcn_sched_barrier(0);
+#endif
+}
+
+// Computes y_e and hands each output row to out(i, y_i) as soon as it is
+// formed (so no output array stays live).  DIAG: u = unit vector e_unit on
+// this element and zero neighbours (Jacobi diagonal).  u holds the element's
+// values throughout.
+template <int N, typename TC, typename TX, bool KAP, bool DIAG, typename Out>
+__host__ __device__ __forceinline__ void sipdg_element(int e, const TX* __restrict__ x,
+                                                       const TC* __restrict__ geo,
+                                                       const Conn* __restrict__ conn,
+                                                       const TC* __restrict__ kap,
+                                                       const TC* __restrict__ ops, TC lambda,
+                                                       TC ctau, int unit, TC (&u)[Tri<N>::Np],
+                                                       Out&& out) {
+  using G = Tri<N>;
+  using L = OpsLayout<N>;
+  constexpr int Np = G::Np, Nfp = G::Nfp;
+  const TC rx = geo[4 * e + 0], sx = geo[4 * e + 1], ry = geo[4 * e + 2], sy = geo[4 * e + 3];
+  const TC J = TC(1) / (rx * sy - sx * ry);
+  const TC ke = KAP ? kap[e] : TC(1);
+  const Conn c = conn[e];
+
+#pragma unroll
+  for (int j = 0; j < Np; ++j) {
+    if constexpr (DIAG) u[j] = (j == unit) ? TC(1) : TC(0);
+    else u[j] = ld<TX, TC>(x + (size_t)e * Np + j);
+  }
+
+  const TC gx[3] = {-sx, rx + sx, -rx};
+  const TC gy[3] = {-sy, ry + sy, -ry};
+  TC Fs[3], tau[3];
+  TC jmp[3][Nfp], dnj[3][Nfp];
+
+  static_for<0, 3>([&](auto fc) {
+    constexpr int f = decltype(fc)::value;
+    phase_fence();
+    const TC* __restrict__ opf = ops + opaque_zero();
+    Fs[f] = sqrt(gx[f] * gx[f] + gy[f] * gy[f]);
+    const TC inv = TC(1) / Fs[f];
+    const TC nx = gx[f] * inv, ny = gy[f] * inv;
+    const TC nr = nx * rx + ny * ry, ns = nx * sx + ny * sy;
+    const int bc = conn_bc(c.info, f);
+    const int nb = c.nb[f];
+    const int fp = conn_fp(c.info, f);
+    // neighbour metric in the frame that puts its face fp at face 0
+    const TC prx = geo[4 * nb + 0], psx = geo[4 * nb + 1], pry = geo[4 * nb + 2], psy = geo[4 * nb + 3];
+    const TC qx = -(prx + psx), qy = -(pry + psy);
+    const TC Rx = fp == 0 ? prx : (fp == 1 ? psx : qx);
+    const TC Ry = fp == 0 ? pry : (fp == 1 ? psy : qy);
+    const TC Sx = fp == 0 ? psx : (fp == 1 ? qx : prx);
+    const TC Sy = fp == 0 ? psy : (fp == 1 ? qy : pry);
+    const TC Fsp = sqrt(Sx * Sx + Sy * Sy);
+    const TC kp = KAP ? kap[nb] : TC(1);
+    const TC nrp = nx * Rx + ny * Ry, nsp = nx * Sx + ny * Sy;
+    const bool inner = (bc == 0);
+    const bool dir = (bc == 1);
+
+    // neighbour: reference derivatives at its face-0 nodes (rotated frame),
+    // streamed over its nodal values
+    TC pr[Nfp], ps[Nfp], pv[Nfp];
+#pragma unroll
+    for (int m = 0; m < Nfp; ++m) pr[m] = ps[m] = pv[m] = TC(0);
+    if constexpr (!DIAG) {
+      const TX* xn = x + (size_t)nb * Np;
+      static_for<0, Np>([&](auto jc) {
+        constexpr int j = decltype(jc)::value;
+        constexpr int o1 = G::rot(1, j), o2 = G::rot(2, j);
+        const int o = fp == 0 ? j : (fp == 1 ? o1 : o2);
+        const TC v = ld<TX, TC>(xn + o);
+        if constexpr (j < Nfp) pv[j] = v;   // face-0 nodes are ids 0..N
+#pragma unroll
+        for (int m = 0; m < Nfp; ++m) {
+          pr[m] += opf[L::NBR + ((f * Np + j) * 2 + 0) * Nfp + m] * v;
+          ps[m] += opf[L::NBR + ((f * Np + j) * 2 + 1) * Nfp + m] * v;
+        }
+      });
+    }
+    static_for<0, Nfp>([&](auto kc) {
+      constexpr int k = decltype(kc)::value;
+      constexpr int m = Nfp - 1 - k;           // neighbour's face-0 position
+      constexpr int vm = G::fm(f, k);
+      TC dr = TC(0), ds = TC(0);
+#pragma unroll
+      for (int j = 0; j < Np; ++j) {
+        dr += opf[L::Dr + vm * Np + j] * u[j];
+        ds += opf[L::Ds + vm * Np + j] * u[j];
+      }
+      const TC own = nr * dr + ns * ds;
+      const TC dnp = nrp * pr[m] + nsp * ps[m];
+      const TC um = u[vm];
+      const TC ji = pv[m] - um;
+      const TC di = kp * dnp - ke * own;
+      jmp[f][k] = inner ? ji : (dir ? TC(-2) * um : TC(0));
+      dnj[f][k] = inner ? di : (dir ? TC(0) : TC(-2) * ke * own);
+    });
+    tau[f] = inner ? ctau * fmax(ke * Fs[f], kp * Fsp) : ctau * ke * Fs[f];
+  });
+
+  phase_fence();
+  // s_f at the nodes of face f2, including n_f2 . l there
+  TC sf[3][Nfp];
+  static_for<0, 3>([&](auto f2c) {
+    constexpr int f2 = decltype(f2c)::value;
+    TC cn[3];
+#pragma unroll
+    for (int f = 0; f < 3; ++f) cn[f] = TC(0.5) * (gx[f2] * gx[f] + gy[f2] * gy[f]) / Fs[f2];
+    static_for<0, Nfp>([&](auto pc) {
+      constexpr int p = decltype(pc)::value;
+      constexpr int i = G::fm(f2, p);
+      const TC* __restrict__ opp = ops + opaque_zero();
+      TC nl = TC(0);
+#pragma unroll
+      for (int f = 0; f < 3; ++f) {
+        TC w = TC(0);
+#pragma unroll
+        for (int k = 0; k < Nfp; ++k) w += opp[L::LIFT + i * 3 * Nfp + f * Nfp + k] * jmp[f][k];
+        nl += cn[f] * w;
+      }
+      sf[f2][p] = TC(0.5) * dnj[f2][p] + tau[f2] * jmp[f2][p] - ke * nl;
+    });
+  });
+
+  const TC grr = rx * rx + ry * ry, grs = rx * sx + ry * sy, gss = sx * sx + sy * sy;
+  TC ca[3], cb[3];
+#pragma unroll
+  for (int f = 0; f < 3; ++f) {
+    ca[f] = TC(0.5) * (rx * gx[f] + ry * gy[f]);
+    cb[f] = TC(0.5) * (sx * gx[f] + sy * gy[f]);
+  }
+  const bool has_lambda = (lambda != TC(0));
+  static_for<0, Np>([&](auto ic) {
+    constexpr int i = decltype(ic)::value;
+    const TC* __restrict__ opr = ops + opaque_zero();
+    TC trr = TC(0), trs = TC(0), tss = TC(0);
+#pragma unroll
+    for (int j = 0; j < Np; ++j) {
+      trr += opr[L::Krr + i * Np + j] * u[j];
+      trs += opr[L::Krs + i * Np + j] * u[j];
+      tss += opr[L::Kss + i * Np + j] * u[j];
+    }
+    TC acc = grr * trr + grs * trs + gss * tss;
+#pragma unroll
+    for (int f = 0; f < 3; ++f) {
+      TC qa = TC(0), qb = TC(0);
+#pragma unroll
+      for (int k = 0; k < Nfp; ++k) {
+        qa += opr[L::QR + i * 3 * Nfp + f * Nfp + k] * jmp[f][k];
+        qb += opr[L::QS + i * 3 * Nfp + f * Nfp + k] * jmp[f][k];
+      }
+      acc += ca[f] * qa + cb[f] * qb;
+    }
+    acc = -ke * acc;
+    if (has_lambda) {
+      TC m = TC(0);
+#pragma unroll
+      for (int j = 0; j < Np; ++j) m += opr[L::M + i * Np + j] * u[j];
+      acc += lambda * m;
+    }
+    acc *= J;
+    static_for<0, 3>([&](auto fc) {
+      constexpr int f = decltype(fc)::value;
+      constexpr int p = G::fpos(f, i);
+      if constexpr (p >= 0) {
+        TC t = TC(0);
+#pragma unroll
+        for (int k = 0; k < Nfp; ++k) t += opr[L::M1D + p * Nfp + k] * sf[f][k];
+        acc -= Fs[f] * J * t;
+      }
+    });
+    out(i, acc);
+  });
+}
+
+}  // namespace ipdg

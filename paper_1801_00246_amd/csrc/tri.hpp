@@ -1,0 +1,96 @@
+// Compile-time layout of the degree-N nodal triangle shared by all kernels.
+//
+// Node order: lattice (i, j), j = 0..N rows away from face 0, i = 0..N-j
+// along it.  Face f joins vertices f and (f+1)%3 (face 0: s = -1,
+// face 1: r + s = 0, face 2: r = -1); its Nfp = N+1 nodes are listed
+// counter-clockwise.  Two counter-clockwise neighbours traverse a shared edge
+// in opposite directions, so node k of one face meets node N-k of the other.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <type_traits>
+#include <utility>
+
+namespace ipdg {
+
+// Compile-time loop: calls f(std::integral_constant<int, I>) for I in [B, E),
+// so node and face tables can be evaluated as constant expressions.
+template <int B, int E, typename F>
+__host__ __device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (B < E) {
+    f(std::integral_constant<int, B>{});
+    static_for<B + 1, E>(static_cast<F&&>(f));
+  }
+}
+
+template <int N>
+struct Tri {
+  static constexpr int Np = (N + 1) * (N + 2) / 2;
+  static constexpr int Nfp = N + 1;
+
+  __host__ __device__ static constexpr int id(int i, int j) { return j * (N + 1) - (j * (j - 1)) / 2 + i; }
+  __host__ __device__ static constexpr int lat_j(int n) {
+    int j = 0;
+    while (n >= N + 1 - j) { n -= N + 1 - j; ++j; }
+    return j;
+  }
+  __host__ __device__ static constexpr int lat_i(int n) {
+    int j = 0;
+    while (n >= N + 1 - j) { n -= N + 1 - j; ++j; }
+    return n;
+  }
+  // node id of position k on face f
+  __host__ __device__ static constexpr int fm(int f, int k) {
+    return f == 0 ? id(k, 0) : (f == 1 ? id(N - k, k) : id(0, N - k));
+  }
+  // position of node n on face f, or -1
+  __host__ __device__ static constexpr int fpos(int f, int n) {
+    for (int k = 0; k <= N; ++k)
+      if (fm(f, k) == n) return k;
+    return -1;
+  }
+  // Node of the unrotated triangle that sits at node n of the frame whose
+  // vertex 0 is vertex k (barycentric lattice a'_m = a_{(m+k)%3}).  Face k of
+  // the triangle is face 0 of that frame.
+  __host__ __device__ static constexpr int rot(int k, int n) {
+    const int ip = lat_i(n), jp = lat_j(n), a0 = N - ip - jp;
+    return k == 0 ? n : (k == 1 ? id(a0, ip) : id(jp, a0));
+  }
+};
+
+// Offsets of the reference operators in one contiguous table per degree.
+//   Dr, Ds           reference derivative matrices
+//   Krr, Krs, Kss    M Dr Dr, M (Dr Ds + Ds Dr), M Ds Ds  (volume term)
+//   QR, QS           M Dr LIFT, M Ds LIFT  (Np x 3 Nfp, lifted-jump volume term)
+//   M, Minv          mass matrix and its inverse
+//   LIFT             M^{-1} E  (Np x 3 Nfp)
+//   M1D              face mass on [-1, 1]
+//   NBR              [f][j][d][m]: entry (m, j) of D_r (d = 0) or D_s
+//                    (d = 1) for the face-0 rows m = 0..N, stored column by
+//                    column (the neighbour phase streams over j) and once per
+//                    face so that the three neighbour phases read distinct
+//                    addresses
+template <int N>
+struct OpsLayout {
+  static constexpr int Np = Tri<N>::Np, Nfp = Tri<N>::Nfp;
+  static constexpr int Dr = 0;
+  static constexpr int Ds = Dr + Np * Np;
+  static constexpr int Krr = Ds + Np * Np;
+  static constexpr int Krs = Krr + Np * Np;
+  static constexpr int Kss = Krs + Np * Np;
+  static constexpr int M = Kss + Np * Np;
+  static constexpr int Minv = M + Np * Np;
+  static constexpr int QR = Minv + Np * Np;
+  static constexpr int QS = QR + Np * 3 * Nfp;
+  static constexpr int LIFT = QS + Np * 3 * Nfp;
+  static constexpr int M1D = LIFT + Np * 3 * Nfp;
+  static constexpr int NBR = M1D + Nfp * Nfp;
+  static constexpr int total = NBR + 3 * 2 * Nfp * Np;
+};
+
+inline int ops_total(int N) {
+  const int Np = (N + 1) * (N + 2) / 2, Nfp = N + 1;
+  return 7 * Np * Np + 3 * Np * 3 * Nfp + Nfp * Nfp + 6 * Nfp * Np;
+}
+
+}  // namespace ipdg

@@ -1,0 +1,151 @@
+"""GPU parity of the SIPDG operator (ipdg_apply, ipdg_mass_apply) against the
+FP64 oracle, through the C ABI.
+
+FP64 bar: 1e-11 relative (norm-wise and per entry against max |y|).
+FP32: each entry within 10 Np u32 (|A| |x|)_i, u32 = 2^-24, a summation
+bound over the ~10 Np rounded operations that form one output; the observed
+norm-wise error is printed.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle.assemble import OracleMesh, assemble, apply_rows, mass_apply
+
+torch = pytest.importorskip("torch")
+P = pytest.importorskip("paper_1801_00246_amd")
+
+pytestmark = pytest.mark.gpu
+U32 = 2.0 ** -24
+
+
+def dev(a, dtype=torch.float64):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda", dtype=dtype)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.double().cpu().numpy()
+
+
+CASES = [(N, bc, lam, kap) for N in range(1, 9)
+         for (bc, lam, kap) in (("dirichlet", 0.0, False), ("mixed", 100.0, False),
+                                ("neumann", 3.5, True))]
+
+
+@pytest.mark.parametrize("N,bc,lam,use_kappa", CASES)
+def test_apply_matches_oracle(N, bc, lam, use_kappa):
+    # 17 x 17 squares: K = 578 = 2 full 256-element tiles + a ragged tail
+    msh = synth.permuted(synth.square_mesh(17, jitter=0.2, seed=N, bc=bc), seed=100 + N)
+    kap = synth.kappa_draw(msh.K, seed=N) if use_kappa else None
+    ctau = float((N + 1) ** 2)
+    m = OracleMesh(msh.VX, msh.VY, msh.EToV, msh.EToB, N)
+    A = assemble(m, lam, ctau, kappa=kap)
+    x = synth.nodal_normal(msh.K, m.Np, seed=N)
+    yo = A @ x
+    g = P.Mesh.from_synth(N, msh, kappa=kap)
+    y = host(g.apply(dev(x), lam=lam, tau=ctau))
+    rel = np.linalg.norm(y - yo) / np.linalg.norm(yo)
+    print(f"N={N} {bc} lam={lam} kappa={use_kappa}: FP64 rel {rel:.2e}")
+    assert rel <= 1e-11
+    assert np.abs(y - yo).max() <= 1e-11 * np.abs(yo).max()
+    # default tau (<= 0 selects (N+1)^2)
+    y2 = host(g.apply(dev(x), lam=lam, tau=0.0))
+    assert np.array_equal(y, y2)
+    # FP32
+    y32 = host(g.apply(dev(x, torch.float32), lam=lam, tau=ctau))
+    x32 = x.astype(np.float32).astype(np.float64)
+    bound = 10 * m.Np * U32 * (abs(A) @ np.abs(x32)) + 1e-30
+    err = np.abs(y32 - A @ x32)
+    rel32 = np.linalg.norm(y32 - yo) / np.linalg.norm(yo)
+    print(f"            FP32 rel {rel32:.2e}, max err/bound {np.max(err / bound):.3f}")
+    assert np.all(err <= bound)
+
+
+@pytest.mark.parametrize("N", [1, 4, 8])
+def test_mass_apply_matches_oracle(N):
+    msh = synth.square_mesh(17, jitter=0.2, seed=2)
+    m = OracleMesh(msh.VX, msh.VY, msh.EToV, msh.EToB, N)
+    x = synth.nodal_normal(msh.K, m.Np, seed=3)
+    yo = mass_apply(m, x)
+    g = P.Mesh.from_synth(N, msh)
+    y = host(g.mass(dev(x)))
+    assert np.linalg.norm(y - yo) <= 1e-13 * np.linalg.norm(yo)
+    y32 = host(g.mass(dev(x, torch.float32)))
+    assert np.linalg.norm(y32 - yo) <= 1e-6 * np.linalg.norm(yo)
+
+
+@pytest.mark.parametrize("N", [1, 3, 5, 8])
+@pytest.mark.parametrize("lam", [0.0, 100.0])
+def test_full_size_sampled_rows(N, lam):
+    """524,288-element jittered mesh (the throughput workload), the launch the
+    benchmark times; the oracle recomputes 300 sampled elements one by one."""
+    msh = synth.ax_sweep_mesh(512, seed=0)
+    g = P.Mesh.from_synth(N, msh)
+    Np = g.Np
+    x = synth.nodal_normal(msh.K, Np, seed=1)
+    y = host(g.apply(dev(x), lam=lam)).reshape(msh.K, Np)
+    rng = np.random.default_rng(N)
+    sel = np.unique(np.r_[rng.integers(0, msh.K, 296), 0, 1, msh.K - 1, 2 * 512 * 255])
+    m = OracleMesh(msh.VX, msh.VY, msh.EToV, msh.EToB, N)
+    yo = apply_rows(m, lam, float((N + 1) ** 2), x, sel)
+    rel = np.linalg.norm(y[sel] - yo) / np.linalg.norm(yo)
+    print(f"N={N} lam={lam} sampled FP64 rel {rel:.2e}")
+    assert rel <= 1e-11
+
+
+@pytest.mark.parametrize("N", [2, 6])
+def test_full_size_properties(N):
+    """Symmetry and the Neumann null space at full size."""
+    msh = synth.ax_sweep_mesh(512, seed=0)
+    g = P.Mesh.from_synth(N, msh)
+    x = dev(synth.nodal_normal(msh.K, g.Np, seed=5))
+    z = dev(synth.nodal_normal(msh.K, g.Np, seed=6))
+    a = float(torch.dot(z, g.apply(x, lam=10.0)))
+    b = float(torch.dot(x, g.apply(z, lam=10.0)))
+    assert abs(a - b) <= 1e-12 * max(abs(a), 1.0) * 10
+    mn = synth.square_mesh(256, jitter=0.2, seed=1, bc="neumann")
+    gn = P.Mesh.from_synth(N, mn)
+    one = torch.ones(gn.ndof, dtype=torch.float64, device="cuda")
+    y = gn.apply(one, lam=0.0)
+    scale = float(gn.apply(dev(synth.nodal_normal(mn.K, gn.Np, 1)), lam=0.0).abs().max())
+    assert float(y.abs().max()) <= 1e-12 * scale
+
+
+def test_edge_cases():
+    # a single element, all faces Dirichlet
+    VX = np.array([0.0, 1.0, 0.0])
+    VY = np.array([0.0, 0.0, 1.0])
+    EToV = np.array([[0, 1, 2]])
+    EToB = np.ones((1, 3), np.int8)
+    for N in (1, 8):
+        m = OracleMesh(VX, VY, EToV, EToB, N)
+        x = synth.nodal_normal(1, m.Np, 7)
+        g = P.Mesh(N, VX, VY, EToV, EToB)
+        y = host(g.apply(dev(x), lam=2.0))
+        yo = assemble(m, 2.0, float((N + 1) ** 2)) @ x
+        assert np.linalg.norm(y - yo) <= 1e-12 * np.linalg.norm(yo)
+    # an empty mesh is accepted and applying to it is a no-op
+    g0 = P.Mesh(3, np.zeros(0), np.zeros(0), np.zeros((0, 3), np.int32), np.zeros((0, 3), np.int8))
+    assert g0.K == 0
+    P.ipdg.check(P.lib().ipdg_apply(g0.handle, 0.0, 0.0, P.F64, None, None, None))
+    # argument errors
+    msh = synth.square_mesh(4)
+    g = P.Mesh.from_synth(2, msh)
+    x = dev(np.zeros(g.ndof))
+    with pytest.raises(ValueError):
+        g.apply(x[:-1])
+    with pytest.raises(P.IpdgError):
+        P.ipdg.check(P.lib().ipdg_apply(g.handle, 0.0, 0.0, P.F64, x.data_ptr(), x.data_ptr(), None))
+    with pytest.raises(P.IpdgError):
+        P.Mesh(9, msh.VX, msh.VY, msh.EToV, msh.EToB)
+
+
+def test_kappa_one_equals_plain_operator():
+    msh = synth.square_mesh(17, jitter=0.2, seed=9, bc="mixed")
+    x = dev(synth.nodal_normal(msh.K, 21, 3))
+    g1 = P.Mesh.from_synth(5, msh)
+    g2 = P.Mesh.from_synth(5, msh, kappa=np.ones(msh.K))
+    a = host(g1.apply(x, lam=1.0))
+    b = host(g2.apply(x, lam=1.0))
+    assert np.linalg.norm(a - b) <= 1e-14 * np.linalg.norm(a)
