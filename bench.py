@@ -157,7 +157,7 @@ def cpu_baseline(N, lam, target_s=12.0):
                        f"took {t_asm:.1f}s (excluded)")}
 
 
-def run_pcg_compare(P, torch):
+def run_pcg_compare(P, torch, coarse_caps=(200, 20)):
     """PCG + p-multigrid (7 -> 3 -> 1) on 256 x 256 squares, N = 7, FP64 vs
     mixed precision, time to a true relative residual of 1e-8."""
     import numpy as np
@@ -170,16 +170,19 @@ def run_pcg_compare(P, torch):
     b = g.mass(f)
     out = {"workload": "256x256 squares (131,072 triangles), N=7, f from sin(pi x) sin(pi y), "
                        "Dirichlet, lambda=0, tol 1e-8, pMG 7->3->1, Chebyshev(2), coarse Jacobi-PCG"}
-    for name, prec in (("fp64", P.PREC_FP64), ("mixed", P.PREC_MIXED)):
-        o = P.default_opts(pc=P.PC_PMG, prec=prec, degrees=[7, 3, 1])
-        g.pcg(b, tol=1e-8, opts=o)                 # setup + warm-up
-        torch.cuda.synchronize()
-        t0 = time.time()
-        xs, info, st = g.pcg(b, tol=1e-8, opts=o)
-        torch.cuda.synchronize()
-        out[name] = {"time_to_solution_ms": round((time.time() - t0) * 1e3, 2),
-                     "iters": info["iters"], "true_relres": info["relres"],
-                     "restarts": info["restarts"], "setup_ms": round(info["setup_ms"], 2)}
+    for cmax in coarse_caps:
+        for name, prec in (("fp64", P.PREC_FP64), ("mixed", P.PREC_MIXED)):
+            o = P.default_opts(pc=P.PC_PMG, prec=prec, degrees=[7, 3, 1], coarse_max_iters=cmax)
+            g.pcg(b, tol=1e-8, opts=o)                 # setup + warm-up
+            torch.cuda.synchronize()
+            t0 = time.time()
+            xs, info, st = g.pcg(b, tol=1e-8, opts=o)
+            torch.cuda.synchronize()
+            key = f"{name}_coarse{cmax}"
+            out[key] = {"time_to_solution_ms": round((time.time() - t0) * 1e3, 2),
+                        "iters": info["iters"], "true_relres": info["relres"],
+                        "restarts": info["restarts"], "setup_ms": round(info["setup_ms"], 2)}
+            print(f"# pcg {key}: {out[key]}", file=sys.stderr, flush=True)
     return out
 
 

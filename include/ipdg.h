@@ -92,6 +92,7 @@ typedef struct {
   double rho_used[IPDG_MAX_LEVELS];   /* Chebyshev radii used per level */
   double setup_ms;         /* preconditioner setup wall time */
   double solve_ms;         /* iteration wall time */
+  int coarse_iters;        /* iterations of the last coarsest-level solve */
 } ipdg_solve_info;
 
 void ipdg_default_opts(ipdg_solve_opts* opts);

@@ -302,3 +302,83 @@ def mass_apply(m: OracleMesh, f: np.ndarray) -> np.ndarray:
     Mref = (ref.qL * ref.qw[:, None]).T @ ref.qL
     F = np.asarray(f, dtype=np.float64).reshape(m.K, m.Np)
     return (m.J[:, None] * (F @ Mref.T)).ravel()
+
+
+def kappa_grad(m: OracleMesh, ctau: float, kappa, u, w) -> np.ndarray:
+    """g_e = -w^T (dA/dkappa_e) u for the kappa-weighted form of block_rows.
+
+    With <v> = v- - v+ seen from element e (its outward normal n):
+      d a / d kappa_e = (grad u, grad w)_E
+        + sum_{interior F of e} -1/2 (d_n u_e, <w>)_F - 1/2 (d_n w_e, <u>)_F
+                               + dtau_F/dkappa_e (<u>, <w>)_F
+        + sum_{Dirichlet F of e} -(d_n u, w)_F - (d_n w, u)_F + 2 c_tau (|F|/|E|) (u, w)_F
+    where dtau_F/dkappa_e = c_tau |F|/|E| if kappa_e |F|/|E| attains the max
+    in tau_F (ties: the element with the lower id), else 0.  Integrals by
+    the same quadratures as block_rows.
+    """
+    ref = m.ref
+    Np = ref.Np
+    K = m.K
+    kap = np.asarray(kappa, dtype=np.float64)
+    U = np.asarray(u, dtype=np.float64).reshape(K, Np)
+    Wv = np.asarray(w, dtype=np.float64).reshape(K, Np)
+    e = np.arange(K)
+    # volume: integral of grad u . grad w
+    W = ref.qw
+    ur, us = U @ ref.qLr.T, U @ ref.qLs.T                  # (K, nq)
+    wr, ws = Wv @ ref.qLr.T, Wv @ ref.qLs.T
+    ux = m.rx[:, None] * ur + m.sx[:, None] * us
+    uy = m.ry[:, None] * ur + m.sy[:, None] * us
+    wx = m.rx[:, None] * wr + m.sx[:, None] * ws
+    wy = m.ry[:, None] * wr + m.sy[:, None] * ws
+    g = m.J * ((ux * wx + uy * wy) @ W)
+    gq, gw = ref.g1, ref.w1
+    for f in range(3):
+        bc = m.EToB[e, f]
+        nb = m.EToE[e, f]
+        xa, ya, xb, yb, length, nx, ny = m.face_geometry(e, f)
+        t = gq[None, :]
+        qx = 0.5 * (1 - t) * xa[:, None] + 0.5 * (1 + t) * xb[:, None]
+        qy = 0.5 * (1 - t) * ya[:, None] + 0.5 * (1 + t) * yb[:, None]
+        Wq = (0.5 * length)[:, None] * gw[None, :]
+        rm, sm = m.to_ref(e[:, None], qx, qy)
+        L0, Lr0, Ls0 = ref.lagrange(rm.ravel(), sm.ravel())
+        q = qx.shape[1]
+        L0 = L0.reshape(K, q, Np)
+        Lr0 = Lr0.reshape(K, q, Np)
+        Ls0 = Ls0.reshape(K, q, Np)
+        um = np.einsum("kqi,ki->kq", L0, U)
+        wm = np.einsum("kqi,ki->kq", L0, Wv)
+        gxu = m.rx[:, None] * np.einsum("kqi,ki->kq", Lr0, U) + m.sx[:, None] * np.einsum("kqi,ki->kq", Ls0, U)
+        gyu = m.ry[:, None] * np.einsum("kqi,ki->kq", Lr0, U) + m.sy[:, None] * np.einsum("kqi,ki->kq", Ls0, U)
+        gxw = m.rx[:, None] * np.einsum("kqi,ki->kq", Lr0, Wv) + m.sx[:, None] * np.einsum("kqi,ki->kq", Ls0, Wv)
+        gyw = m.ry[:, None] * np.einsum("kqi,ki->kq", Lr0, Wv) + m.sy[:, None] * np.einsum("kqi,ki->kq", Ls0, Wv)
+        dnu = nx[:, None] * gxu + ny[:, None] * gyu
+        dnw = nx[:, None] * gxw + ny[:, None] * gyw
+        hm = length / m.area
+        inner = bc == BC_INTERIOR
+        if np.any(inner):
+            ei = e[inner]
+            ni = nb[inner]
+            rp, sp_ = m.to_ref(ni[:, None], qx[inner], qy[inner])
+            Lp, _, _ = ref.lagrange(rp.ravel(), sp_.ravel())
+            Lp = Lp.reshape(ei.size, q, Np)
+            up = np.einsum("kqi,ki->kq", Lp, U[ni])
+            wp = np.einsum("kqi,ki->kq", Lp, Wv[ni])
+            ju = um[inner] - up
+            jw = wm[inner] - wp
+            mine = kap[ei] * hm[inner]
+            other = kap[ni] * length[inner] / m.area[ni]
+            owns = (mine > other) | ((mine == other) & (ei < ni))
+            dtau = np.where(owns, ctau * hm[inner], 0.0)
+            Wi = Wq[inner]
+            val = (-0.5 * np.sum(Wi * dnu[inner] * jw, 1) - 0.5 * np.sum(Wi * dnw[inner] * ju, 1)
+                   + dtau * np.sum(Wi * ju * jw, 1))
+            np.add.at(g, ei, val)
+        dirf = bc == BC_DIRICHLET
+        if np.any(dirf):
+            Wd = Wq[dirf]
+            val = (-np.sum(Wd * dnu[dirf] * wm[dirf], 1) - np.sum(Wd * dnw[dirf] * um[dirf], 1)
+                   + 2 * ctau * hm[dirf] * np.sum(Wd * um[dirf] * wm[dirf], 1))
+            np.add.at(g, e[dirf], val)
+    return -g

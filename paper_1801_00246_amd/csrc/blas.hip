@@ -1,2 +1,425 @@
-// Vector kernels of the CG solvers (placeholder unit; filled by the solver).
-#include "kernels.hpp"
+// Vector kernels of the device-resident preconditioned CG solvers (Sec. 3).
+//
+// All scalars of an iteration (alpha, beta, dot products, convergence and
+// breakdown flags) live in device memory, so an iteration is a fixed
+// sequence of launches with no host round trip; each kernel takes a `skip`
+// flag (the solve's done flag) and returns at once when it is set.  Dot
+// products are reduced per block into a partials array and summed by a
+// one-block finalize kernel in a fixed order (bitwise reproducible).
+#include "blas.hpp"
+
+namespace ipdg {
+namespace {
+
+__device__ __forceinline__ double ldd(const double* p, size_t i) { return p[i]; }
+__device__ __forceinline__ double ldd(const float* p, size_t i) { return static_cast<double>(p[i]); }
+
+template <int NV>
+__device__ __forceinline__ void commit(double (&v)[NV], double* partials) {
+  block_sum<NV>(v);
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int k = 0; k < NV; ++k) partials[k * kMaxPartials + blockIdx.x] = v[k];
+}
+
+// r = b - Ax; partials: (r, r), (b, b)
+__global__ __launch_bounds__(kBlock) void k_residual(const double* __restrict__ b,
+                                                     const double* __restrict__ Ax,
+                                                     double* __restrict__ r, size_t n,
+                                                     double* __restrict__ partials) {
+  double v[2] = {0.0, 0.0};
+  for (size_t i = blockIdx.x * (size_t)kBlock + threadIdx.x; i < n; i += (size_t)gridDim.x * kBlock) {
+    const double bi = b[i];
+    const double ri = bi - Ax[i];
+    r[i] = ri;
+    v[0] += ri * ri;
+    v[1] += bi * bi;
+  }
+  commit<2>(v, partials);
+}
+
+// x += alpha p; r -= alpha Ap; optionally z = dinv r (Jacobi, z in TZ).
+// partials: (r, r), and with Jacobi (r, z), (z, Ap).
+template <typename TZ, bool JAC>
+__global__ __launch_bounds__(kBlock) void k_update(double* __restrict__ x, double* __restrict__ r,
+                                                   const double* __restrict__ p,
+                                                   const TZ* __restrict__ Ap,
+                                                   const double* __restrict__ dinv,
+                                                   TZ* __restrict__ z, const CGScal* __restrict__ sc,
+                                                   size_t n, double* __restrict__ partials) {
+  if (sc->done) return;
+  const double alpha = sc->alpha;
+  double v[3] = {0.0, 0.0, 0.0};
+  for (size_t i = blockIdx.x * (size_t)kBlock + threadIdx.x; i < n; i += (size_t)gridDim.x * kBlock) {
+    const double api = ldd(Ap, i);
+    x[i] += alpha * p[i];
+    const double ri = r[i] - alpha * api;
+    r[i] = ri;
+    v[0] += ri * ri;
+    if constexpr (JAC) {
+      const TZ zi = static_cast<TZ>(dinv[i] * ri);
+      z[i] = zi;
+      v[1] += ri * static_cast<double>(zi);
+      v[2] += static_cast<double>(zi) * api;
+    }
+  }
+  commit<3>(v, partials);
+}
+
+// partials slots 1, 2: (r, z), (z, Ap)
+template <typename TZ>
+__global__ __launch_bounds__(kBlock) void k_dots_rz(const double* __restrict__ r,
+                                                    const TZ* __restrict__ z,
+                                                    const TZ* __restrict__ Ap,
+                                                    const CGScal* __restrict__ sc, size_t n,
+                                                    double* __restrict__ partials) {
+  if (sc->done) return;
+  double v[2] = {0.0, 0.0};
+  for (size_t i = blockIdx.x * (size_t)kBlock + threadIdx.x; i < n; i += (size_t)gridDim.x * kBlock) {
+    const double zi = ldd(z, i);
+    v[0] += r[i] * zi;
+    if (Ap) v[1] += zi * ldd(Ap, i);
+  }
+  block_sum<2>(v);
+  if (threadIdx.x == 0) {
+    partials[1 * kMaxPartials + blockIdx.x] = v[0];
+    partials[2 * kMaxPartials + blockIdx.x] = v[1];
+  }
+}
+
+// p = z + beta p
+template <typename TZ>
+__global__ __launch_bounds__(kBlock) void k_pupdate(double* __restrict__ p, const TZ* __restrict__ z,
+                                                    const CGScal* __restrict__ sc, size_t n) {
+  if (sc->done) return;
+  const double beta = sc->beta;
+  for (size_t i = blockIdx.x * (size_t)kBlock + threadIdx.x; i < n; i += (size_t)gridDim.x * kBlock)
+    p[i] = ldd(z, i) + beta * p[i];
+}
+
+// z = dinv r (TZ) ; partials (r, z) in slot 1
+template <typename TZ>
+__global__ __launch_bounds__(kBlock) void k_jacobi(const double* __restrict__ r,
+                                                   const double* __restrict__ dinv,
+                                                   TZ* __restrict__ z, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)kBlock + threadIdx.x; i < n; i += (size_t)gridDim.x * kBlock)
+    z[i] = static_cast<TZ>(dinv[i] * r[i]);
+}
+
+// Sum the partials of `nslots` slots over nparts blocks (fixed order) and
+// apply one step of the CG scalar recurrence.
+__global__ __launch_bounds__(kBlock) void k_finalize(const double* __restrict__ partials,
+                                                     int nparts, int nslots, CGScal* __restrict__ sc,
+                                                     int op) {
+  if ((op == kFinAlpha || op == kFinBeta) && sc->done) return;
+  __shared__ double red[3][kBlock];
+  for (int k = 0; k < nslots; ++k) {
+    double s = 0.0;
+    for (int i = threadIdx.x; i < nparts; i += kBlock) s += partials[k * kMaxPartials + i];
+    red[k][threadIdx.x] = s;
+  }
+  __syncthreads();
+  for (int w = kBlock / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w)
+      for (int k = 0; k < nslots; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x != 0) return;
+  const double s0 = red[0][0], s1 = nslots > 1 ? red[1][0] : 0.0, s2 = nslots > 2 ? red[2][0] : 0.0;
+  switch (op) {
+    case kFinResidual:   // (r, r), (b, b); the recurrence restarts from here
+      sc->rr = s0;
+      sc->bb = s1;
+      sc->tol2 = sc->tol * sc->tol * s1;
+      sc->done = 0;
+      break;
+    case kFinInit:       // (r, z) after z = B r, p = z
+      sc->rz = s1;
+      sc->done = (sc->rr <= sc->tol2) || (sc->bb == 0.0) || (sc->max_iters <= sc->iters);
+      break;
+    case kFinAlpha: {    // (p, Ap)
+      const double pAp = s0;
+      sc->pAp = pAp;
+      if (!(pAp > 0.0) || !isfinite(pAp) || !isfinite(sc->rz)) {
+        sc->breakdown = 1;
+        sc->done = 1;
+      } else {
+        sc->alpha = sc->rz / pAp;
+      }
+      break;
+    }
+    case kFinBeta: {     // (r, r), (r, z), (z, Ap)
+      sc->rr = s0;
+      sc->iters += 1;
+      const double beta = sc->flexible ? -s2 / sc->pAp : s1 / sc->rz;
+      sc->beta = beta;
+      sc->rz = s1;
+      if (!isfinite(s0)) { sc->breakdown = 1; sc->done = 1; }
+      if (s0 <= sc->tol2 || sc->iters >= sc->max_iters) sc->done = 1;
+      break;
+    }
+    case kFinRho:        // Lanczos steps record alpha/beta history (host reads)
+      break;
+  }
+}
+
+// Chebyshev smoothing on D^{-1} A (Saad Alg. 12.1):
+//   start from zero:     r = f;     d = c0 dinv f;      z = d
+//   start from z:        r = f - t; d = c0 dinv r;      z += d    (t = A z)
+//   step:                r -= t;    d = c1 d + c2 dinv r; z += d  (t = A d)
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_cheb(int mode, const T* __restrict__ f,
+                                                 const T* __restrict__ t, const T* __restrict__ dinv,
+                                                 T* __restrict__ z, T* __restrict__ d,
+                                                 T* __restrict__ r, T c0, T c1, T c2, size_t n,
+                                                 const int* __restrict__ skip) {
+  if (skip && *skip) return;
+  for (size_t i = blockIdx.x * (size_t)kBlock + threadIdx.x; i < n; i += (size_t)gridDim.x * kBlock) {
+    if (mode == 0) {
+      const T ri = f[i];
+      r[i] = ri;
+      const T di = c0 * dinv[i] * ri;
+      d[i] = di;
+      z[i] = di;
+    } else if (mode == 1) {
+      const T ri = f[i] - t[i];
+      r[i] = ri;
+      const T di = c0 * dinv[i] * ri;
+      d[i] = di;
+      z[i] += di;
+    } else {
+      const T ri = r[i] - t[i];
+      r[i] = ri;
+      const T di = c1 * d[i] + c2 * dinv[i] * ri;
+      d[i] = di;
+      z[i] += di;
+    }
+  }
+}
+
+template <typename TD, typename TS>
+__global__ __launch_bounds__(kBlock) void k_convert(TD* __restrict__ dst, const TS* __restrict__ src,
+                                                    size_t n, const int* __restrict__ skip) {
+  if (skip && *skip) return;
+  for (size_t i = blockIdx.x * (size_t)kBlock + threadIdx.x; i < n; i += (size_t)gridDim.x * kBlock)
+    dst[i] = static_cast<TD>(src[i]);
+}
+
+// coarse-solve initialisation: x = 0, r = f, z = dinv f, p = z; partials
+// (r, r), (r, z)
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_cg_start0(const T* __restrict__ f, const T* __restrict__ dinv,
+                                                      T* __restrict__ x, T* __restrict__ r,
+                                                      T* __restrict__ z, T* __restrict__ p, size_t n,
+                                                      double* __restrict__ partials,
+                                                      const int* __restrict__ skip) {
+  if (skip && *skip) return;
+  double v[2] = {0.0, 0.0};
+  for (size_t i = blockIdx.x * (size_t)kBlock + threadIdx.x; i < n; i += (size_t)gridDim.x * kBlock) {
+    const T fi = f[i];
+    const T zi = dinv[i] * fi;
+    x[i] = T(0);
+    r[i] = fi;
+    z[i] = zi;
+    p[i] = zi;
+    v[0] += double(fi) * double(fi);
+    v[1] += double(fi) * double(zi);
+  }
+  commit<2>(v, partials);
+}
+
+// coarse-solve scalar setup after k_cg_start0: rr0, tol2 = tol^2 rr0, rz
+__global__ void k_cg_start_fin(const double* __restrict__ partials, int nparts, CGScal* sc,
+                               const int* __restrict__ skip) {
+  __shared__ double red[2][kBlock];
+  for (int k = 0; k < 2; ++k) {
+    double s = 0.0;
+    for (int i = threadIdx.x; i < nparts; i += kBlock) s += partials[k * kMaxPartials + i];
+    red[k][threadIdx.x] = s;
+  }
+  __syncthreads();
+  for (int w = kBlock / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w)
+      for (int k = 0; k < 2; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x != 0) return;
+  const bool outer_done = skip && *skip;
+  sc->rr = red[0][0];
+  sc->bb = red[0][0];
+  sc->rz = red[1][0];
+  sc->tol2 = sc->tol * sc->tol * sc->rr;
+  sc->iters = 0;
+  sc->breakdown = 0;
+  sc->done = outer_done || sc->rr == 0.0 || sc->max_iters <= 0;
+}
+
+// single-precision-state coarse CG update: x += a p; r -= a Ap; z = dinv r;
+// partials (r,r), (r,z), (z,Ap)
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_cg_update(T* __restrict__ x, T* __restrict__ r,
+                                                      const T* __restrict__ p, const T* __restrict__ Ap,
+                                                      const T* __restrict__ dinv, T* __restrict__ z,
+                                                      const CGScal* __restrict__ sc, size_t n,
+                                                      double* __restrict__ partials) {
+  if (sc->done) return;
+  const T alpha = static_cast<T>(sc->alpha);
+  double v[3] = {0.0, 0.0, 0.0};
+  for (size_t i = blockIdx.x * (size_t)kBlock + threadIdx.x; i < n; i += (size_t)gridDim.x * kBlock) {
+    x[i] += alpha * p[i];
+    const T ri = r[i] - alpha * Ap[i];
+    r[i] = ri;
+    const T zi = dinv[i] * ri;
+    z[i] = zi;
+    v[0] += double(ri) * double(ri);
+    v[1] += double(ri) * double(zi);
+    v[2] += double(zi) * double(Ap[i]);
+  }
+  commit<3>(v, partials);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_cg_pupdate(T* __restrict__ p, const T* __restrict__ z,
+                                                       const CGScal* __restrict__ sc, size_t n) {
+  if (sc->done) return;
+  const T beta = static_cast<T>(sc->beta);
+  for (size_t i = blockIdx.x * (size_t)kBlock + threadIdx.x; i < n; i += (size_t)gridDim.x * kBlock)
+    p[i] = z[i] + beta * p[i];
+}
+
+// reciprocal of the diagonal (in place) and an optional FP32 copy
+__global__ __launch_bounds__(kBlock) void k_recip(double* __restrict__ d, float* __restrict__ d32, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)kBlock + threadIdx.x; i < n; i += (size_t)gridDim.x * kBlock) {
+    const double v = 1.0 / d[i];
+    d[i] = v;
+    if (d32) d32[i] = static_cast<float>(v);
+  }
+}
+
+__global__ void k_set_scal(CGScal* sc, CGScal v) { *sc = v; }
+
+__global__ void k_zero_ints(int* p, int n) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0;
+}
+
+}  // namespace
+
+int flat_grid(size_t n) {
+  size_t b = (n + kBlock - 1) / kBlock;
+  if (b > (size_t)kMaxPartials) b = kMaxPartials;
+  return b < 1 ? 1 : int(b);
+}
+
+#define LAUNCH(kern, n, s, ...) \
+  hipLaunchKernelGGL(kern, dim3(flat_grid(n)), dim3(kBlock), 0, s, __VA_ARGS__)
+
+hipError_t residual(const double* b, const double* Ax, double* r, size_t n, double* partials, hipStream_t s) {
+  LAUNCH(k_residual, n, s, b, Ax, r, n, partials);
+  return hipGetLastError();
+}
+
+hipError_t cg_update(bool fp32z, bool jacobi, double* x, double* r, const double* p, const void* Ap,
+                     const double* dinv, void* z, const CGScal* sc, size_t n, double* partials,
+                     hipStream_t s) {
+  if (fp32z) {
+    if (jacobi) LAUNCH((k_update<float, true>), n, s, x, r, p, (const float*)Ap, dinv, (float*)z, sc, n, partials);
+    else LAUNCH((k_update<float, false>), n, s, x, r, p, (const float*)Ap, dinv, (float*)z, sc, n, partials);
+  } else {
+    if (jacobi) LAUNCH((k_update<double, true>), n, s, x, r, p, (const double*)Ap, dinv, (double*)z, sc, n, partials);
+    else LAUNCH((k_update<double, false>), n, s, x, r, p, (const double*)Ap, dinv, (double*)z, sc, n, partials);
+  }
+  return hipGetLastError();
+}
+
+hipError_t dots_rz(bool fp32z, const double* r, const void* z, const void* Ap, const CGScal* sc, size_t n,
+                   double* partials, hipStream_t s) {
+  if (fp32z) LAUNCH(k_dots_rz<float>, n, s, r, (const float*)z, (const float*)Ap, sc, n, partials);
+  else LAUNCH(k_dots_rz<double>, n, s, r, (const double*)z, (const double*)Ap, sc, n, partials);
+  return hipGetLastError();
+}
+
+hipError_t pupdate(bool fp32z, double* p, const void* z, const CGScal* sc, size_t n, hipStream_t s) {
+  if (fp32z) LAUNCH(k_pupdate<float>, n, s, p, (const float*)z, sc, n);
+  else LAUNCH(k_pupdate<double>, n, s, p, (const double*)z, sc, n);
+  return hipGetLastError();
+}
+
+hipError_t jacobi(bool fp32z, const double* r, const double* dinv, void* z, size_t n, hipStream_t s) {
+  if (fp32z) LAUNCH(k_jacobi<float>, n, s, r, dinv, (float*)z, n);
+  else LAUNCH(k_jacobi<double>, n, s, r, dinv, (double*)z, n);
+  return hipGetLastError();
+}
+
+hipError_t finalize(const double* partials, int nparts, int nslots, CGScal* sc, int op, hipStream_t s) {
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, s, partials, nparts, nslots, sc, op);
+  return hipGetLastError();
+}
+
+hipError_t cheb(bool fp32, int mode, const void* f, const void* t, const void* dinv, void* z, void* d,
+                void* r, double c0, double c1, double c2, size_t n, const int* skip, hipStream_t s) {
+  if (fp32)
+    LAUNCH(k_cheb<float>, n, s, mode, (const float*)f, (const float*)t, (const float*)dinv, (float*)z,
+           (float*)d, (float*)r, float(c0), float(c1), float(c2), n, skip);
+  else
+    LAUNCH(k_cheb<double>, n, s, mode, (const double*)f, (const double*)t, (const double*)dinv,
+           (double*)z, (double*)d, (double*)r, c0, c1, c2, n, skip);
+  return hipGetLastError();
+}
+
+hipError_t convert(bool to_fp32, void* dst, const void* src, size_t n, const int* skip, hipStream_t s) {
+  if (to_fp32) LAUNCH((k_convert<float, double>), n, s, (float*)dst, (const double*)src, n, skip);
+  else LAUNCH((k_convert<double, float>), n, s, (double*)dst, (const float*)src, n, skip);
+  return hipGetLastError();
+}
+
+hipError_t cg_start0(bool fp32, const void* f, const void* dinv, void* x, void* r, void* z, void* p,
+                     size_t n, double* partials, const int* skip, hipStream_t s) {
+  if (fp32)
+    LAUNCH(k_cg_start0<float>, n, s, (const float*)f, (const float*)dinv, (float*)x, (float*)r, (float*)z,
+           (float*)p, n, partials, skip);
+  else
+    LAUNCH(k_cg_start0<double>, n, s, (const double*)f, (const double*)dinv, (double*)x, (double*)r,
+           (double*)z, (double*)p, n, partials, skip);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return hipSuccess;
+}
+
+hipError_t cg_start_fin(const double* partials, int nparts, CGScal* sc, const int* skip, hipStream_t s) {
+  hipLaunchKernelGGL(k_cg_start_fin, dim3(1), dim3(kBlock), 0, s, partials, nparts, sc, skip);
+  return hipGetLastError();
+}
+
+hipError_t cg_update_state(bool fp32, void* x, void* r, const void* p, const void* Ap, const void* dinv,
+                           void* z, const CGScal* sc, size_t n, double* partials, hipStream_t s) {
+  if (fp32)
+    LAUNCH(k_cg_update<float>, n, s, (float*)x, (float*)r, (const float*)p, (const float*)Ap,
+           (const float*)dinv, (float*)z, sc, n, partials);
+  else
+    LAUNCH(k_cg_update<double>, n, s, (double*)x, (double*)r, (const double*)p, (const double*)Ap,
+           (const double*)dinv, (double*)z, sc, n, partials);
+  return hipGetLastError();
+}
+
+hipError_t cg_pupdate_state(bool fp32, void* p, const void* z, const CGScal* sc, size_t n, hipStream_t s) {
+  if (fp32) LAUNCH(k_cg_pupdate<float>, n, s, (float*)p, (const float*)z, sc, n);
+  else LAUNCH(k_cg_pupdate<double>, n, s, (double*)p, (const double*)z, sc, n);
+  return hipGetLastError();
+}
+
+hipError_t recip(double* d, float* d32, size_t n, hipStream_t s) {
+  LAUNCH(k_recip, n, s, d, d32, n);
+  return hipGetLastError();
+}
+
+hipError_t zero_ints(void* p, int n, hipStream_t s) {
+  hipLaunchKernelGGL(k_zero_ints, dim3(1), dim3(64), 0, s, static_cast<int*>(p), n);
+  return hipGetLastError();
+}
+
+hipError_t set_scal(CGScal* sc, const CGScal& v, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_scal, dim3(1), dim3(1), 0, s, sc, v);
+  return hipGetLastError();
+}
+
+}  // namespace ipdg

@@ -1,0 +1,44 @@
+// Device-resident CG scalars and vector kernels (blas.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "device_common.hpp"
+
+namespace ipdg {
+
+// Scalars of one CG solve, kept in device memory.
+struct CGScal {
+  double rz = 0, pAp = 0, alpha = 0, beta = 0, rr = 0, bb = 0, tol = 0, tol2 = 0;
+  int done = 0, breakdown = 0, iters = 0, max_iters = 0, flexible = 0, pad = 0;
+};
+
+// Partial-sum slots per reduction (>= blocks of any element or vector launch).
+constexpr int kMaxPartials = 65536;
+
+enum FinOp { kFinResidual = 0, kFinInit = 1, kFinAlpha = 2, kFinBeta = 3, kFinRho = 4 };
+
+int flat_grid(size_t n);
+
+hipError_t residual(const double* b, const double* Ax, double* r, size_t n, double* partials, hipStream_t s);
+hipError_t cg_update(bool fp32z, bool jacobi, double* x, double* r, const double* p, const void* Ap,
+                     const double* dinv, void* z, const CGScal* sc, size_t n, double* partials,
+                     hipStream_t s);
+hipError_t dots_rz(bool fp32z, const double* r, const void* z, const void* Ap, const CGScal* sc, size_t n,
+                   double* partials, hipStream_t s);
+hipError_t pupdate(bool fp32z, double* p, const void* z, const CGScal* sc, size_t n, hipStream_t s);
+hipError_t jacobi(bool fp32z, const double* r, const double* dinv, void* z, size_t n, hipStream_t s);
+hipError_t finalize(const double* partials, int nparts, int nslots, CGScal* sc, int op, hipStream_t s);
+hipError_t cheb(bool fp32, int mode, const void* f, const void* t, const void* dinv, void* z, void* d,
+                void* r, double c0, double c1, double c2, size_t n, const int* skip, hipStream_t s);
+hipError_t convert(bool to_fp32, void* dst, const void* src, size_t n, const int* skip, hipStream_t s);
+hipError_t cg_start0(bool fp32, const void* f, const void* dinv, void* x, void* r, void* z, void* p,
+                     size_t n, double* partials, const int* skip, hipStream_t s);
+hipError_t cg_start_fin(const double* partials, int nparts, CGScal* sc, const int* skip, hipStream_t s);
+hipError_t cg_update_state(bool fp32, void* x, void* r, const void* p, const void* Ap, const void* dinv,
+                           void* z, const CGScal* sc, size_t n, double* partials, hipStream_t s);
+hipError_t cg_pupdate_state(bool fp32, void* p, const void* z, const CGScal* sc, size_t n, hipStream_t s);
+hipError_t recip(double* d, float* d32, size_t n, hipStream_t s);
+hipError_t set_scal(CGScal* sc, const CGScal& v, hipStream_t s);
+hipError_t zero_ints(void* p, int n, hipStream_t s);
+
+}  // namespace ipdg

@@ -52,4 +52,23 @@ hipError_t prolong(int Nf, int Nc, Kind kind, const TransferArgs& a, hipStream_t
 #undef C
 }
 
+hipError_t coarse_pcg(int N, Kind kind, const CoarseArgs& a, int grid, hipStream_t s) {
+#define C(n) launch_coarse_pcg<n>(kind, a, grid, s)
+  IPDG_SWITCH(N, C)
+#undef C
+}
+int coarse_pcg_grid(int N, Kind kind, int K) {
+  switch (N) {
+    case 1: return coarse_pcg_grid<1>(kind, K);
+    case 2: return coarse_pcg_grid<2>(kind, K);
+    case 3: return coarse_pcg_grid<3>(kind, K);
+    case 4: return coarse_pcg_grid<4>(kind, K);
+    case 5: return coarse_pcg_grid<5>(kind, K);
+    case 6: return coarse_pcg_grid<6>(kind, K);
+    case 7: return coarse_pcg_grid<7>(kind, K);
+    case 8: return coarse_pcg_grid<8>(kind, K);
+    default: return 0;
+  }
+}
+
 }  // namespace ipdg

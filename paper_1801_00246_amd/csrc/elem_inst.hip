@@ -4,6 +4,9 @@
 // same die (shared L2 for the neighbour gathers).
 #include "kernels.hpp"
 #include "sipdg_core.hpp"
+#include "blas.hpp"
+
+#include <algorithm>
 
 #ifndef IPDG_N
 #error "IPDG_N must be defined"
@@ -13,6 +16,7 @@ namespace ipdg {
 namespace {
 
 constexpr int N = IPDG_N;
+constexpr int kMaxPartialsCoarse = 4096;
 constexpr int Np = Tri<N>::Np;
 
 // Minimum waves per SIMD the register allocator must leave room for: the
@@ -38,10 +42,13 @@ __global__ __launch_bounds__(kBlock) void k_ax(const TX* __restrict__ x, TY* __r
   if (e < K) {
     TC u[Np];
     TY* ye = y + (size_t)e * Np;
+    const TX* xe = x + (size_t)e * Np;
+    const bool want_dot = partials != nullptr;
     sipdg_element<N, TC, TX, KAP, false>(e, x, geo, conn, kap, ops, lambda, ctau, 0, u,
                                          [&](int i, TC v) {
                                            ye[i] = static_cast<TY>(v);
-                                           dot += static_cast<double>(u[i]) * static_cast<double>(v);
+                                           if (want_dot)
+                                             dot += static_cast<double>(xe[i]) * static_cast<double>(v);
                                          });
   }
   if (partials) {
@@ -254,6 +261,197 @@ __global__ __launch_bounds__(kBlock) void k_kgrad(const double* __restrict__ u,
   out[e] = -tot;
 }
 
+
+// ---------------------------------------------------------------------------
+// Persistent Jacobi-PCG of one level (the coarsest level of the p-multigrid
+// cycle): textbook PCG from x = 0, all iterations in one launch.
+// ---------------------------------------------------------------------------
+constexpr unsigned kSpinLimit = 1u << 22;
+
+// Grid-wide barrier: one arrival counter and one generation counter, both
+// agent-scope atomics.  The wait is bounded: on timeout the block records the
+// failure in status[1] and reports false, so that the kernel still ends.
+__device__ bool grid_barrier(unsigned* bar, unsigned nblocks, int* status) {
+  __shared__ int ok;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    ok = 1;
+    const unsigned gen = __hip_atomic_load(&bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned prev = __hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    if (prev == nblocks - 1) {
+      __hip_atomic_store(&bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_fetch_add(&bar[1], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      unsigned spins = 0;
+      while (__hip_atomic_load(&bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
+        if (++spins > kSpinLimit) {
+          ok = 0;
+          __hip_atomic_store(&status[1], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          break;
+        }
+        __builtin_amdgcn_s_sleep(2);
+      }
+    }
+  }
+  __syncthreads();
+  return ok != 0;
+}
+
+// Sum slot `slot` of the partials over nblocks entries; every block computes
+// the same value in the same order.
+__device__ double grid_total(const double* partials, int slot, int nblocks) {
+  __shared__ double tot;
+  double v[1] = {0.0};
+  for (int i = threadIdx.x; i < nblocks; i += kBlock)
+    v[0] += __hip_atomic_load(&partials[slot * kMaxPartials + i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  block_sum<1>(v);
+  if (threadIdx.x == 0) tot = v[0];
+  __syncthreads();
+  const double t = tot;
+  __syncthreads();
+  return t;
+}
+
+template <int NV>
+__device__ void put_partials(double (&v)[NV], double* partials, const int* slots) {
+  block_sum<NV>(v);
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int k = 0; k < NV; ++k)
+      __hip_atomic_store(&partials[slots[k] * kMaxPartials + blockIdx.x], v[k], __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <int NN, typename T, bool KAP>
+__global__ __launch_bounds__(kBlock) void k_coarse_pcg(const T* __restrict__ f, T* __restrict__ x,
+                                                       T* __restrict__ r, T* __restrict__ z,
+                                                       T* __restrict__ p, T* __restrict__ Ap,
+                                                       const T* __restrict__ dinv,
+                                                       const T* __restrict__ geo,
+                                                       const Conn* __restrict__ conn,
+                                                       const T* __restrict__ kap,
+                                                       const T* __restrict__ ops, T lambda, T ctau,
+                                                       int K, double tol, int max_iters,
+                                                       double* __restrict__ partials,
+                                                       unsigned* __restrict__ bar,
+                                                       int* __restrict__ status,
+                                                       const int* __restrict__ skip) {
+  if (skip && *skip) return;          // the same flag value for every block
+  constexpr int Np = Tri<NN>::Np;
+  const int G = gridDim.x;
+  const size_t n = (size_t)K * Np;
+  const int ntiles = (K + kBlock - 1) / kBlock;
+  const size_t stride = (size_t)G * kBlock;
+  // x = 0, r = f, z = D^-1 f, p = z
+  {
+    double v[2] = {0.0, 0.0};
+    for (size_t i = blockIdx.x * (size_t)kBlock + threadIdx.x; i < n; i += stride) {
+      const T fi = f[i];
+      const T zi = dinv[i] * fi;
+      x[i] = T(0);
+      r[i] = fi;
+      z[i] = zi;
+      p[i] = zi;
+      v[0] += double(fi) * double(fi);
+      v[1] += double(fi) * double(zi);
+    }
+    // slots 1, 2: slot 0 is rewritten by the first operator phase, which a
+    // fast block may reach while a slow one still reads these totals
+    const int sl[2] = {1, 2};
+    put_partials<2>(v, partials, sl);
+  }
+  if (!grid_barrier(bar, G, status)) return;
+  const double rr0 = grid_total(partials, 1, G);
+  double rz = grid_total(partials, 2, G);
+  const double tol2 = tol * tol * rr0;
+  int it = 0;
+  bool done = !(rr0 > 0.0);
+  while (!done && it < max_iters) {
+    // Ap = A p, (p, Ap)
+    double dot = 0.0;
+    for (int t = blockIdx.x; t < ntiles; t += G) {
+      const int e = t * kBlock + threadIdx.x;
+      if (e < K) {
+        T u[Np];
+        T* ye = Ap + (size_t)e * Np;
+        sipdg_element<NN, T, T, KAP, false>(e, p, geo, conn, kap, ops, lambda, ctau, 0, u,
+                                           [&](int i, T vv) {
+                                             ye[i] = vv;
+                                             dot += double(p[(size_t)e * Np + i]) * double(vv);
+                                           });
+      }
+    }
+    {
+      double v[1] = {dot};
+      const int sl[1] = {0};
+      put_partials<1>(v, partials, sl);
+    }
+    if (!grid_barrier(bar, G, status)) return;
+    const double pAp = grid_total(partials, 0, G);
+    if (!(pAp > 0.0)) {
+      if (blockIdx.x == 0 && threadIdx.x == 0) status[2] = 1;
+      break;
+    }
+    const double alpha = rz / pAp;
+    double v[2] = {0.0, 0.0};
+    for (size_t i = blockIdx.x * (size_t)kBlock + threadIdx.x; i < n; i += stride) {
+      x[i] += T(alpha) * p[i];
+      const T ri = r[i] - T(alpha) * Ap[i];
+      r[i] = ri;
+      const T zi = dinv[i] * ri;
+      z[i] = zi;
+      v[0] += double(ri) * double(ri);
+      v[1] += double(ri) * double(zi);
+    }
+    {
+      const int sl[2] = {1, 2};
+      put_partials<2>(v, partials, sl);
+    }
+    if (!grid_barrier(bar, G, status)) return;
+    const double rr = grid_total(partials, 1, G);
+    const double rz_new = grid_total(partials, 2, G);
+    ++it;
+    if (rr <= tol2) break;
+    const double beta = rz_new / rz;
+    rz = rz_new;
+    for (size_t i = blockIdx.x * (size_t)kBlock + threadIdx.x; i < n; i += stride)
+      p[i] = z[i] + T(beta) * p[i];
+    if (!grid_barrier(bar, G, status)) return;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) status[0] = it;
+}
+
+template <int NN, typename T>
+hipError_t run_coarse(const CoarseArgs& a, int grid, hipStream_t s) {
+  const ElemArgs& o = a.op;
+  if (o.kap)
+    hipLaunchKernelGGL((k_coarse_pcg<NN, T, true>), dim3(grid), dim3(kBlock), 0, s,
+                       (const T*)a.f, (T*)a.x, (T*)a.r, (T*)a.z, (T*)a.p, (T*)a.Ap, (const T*)a.dinv,
+                       (const T*)o.geo, o.conn, (const T*)o.kap, (const T*)o.ops, T(o.lambda), T(o.ctau),
+                       o.K, a.tol, a.max_iters, a.partials, a.bar, a.status, a.skip);
+  else
+    hipLaunchKernelGGL((k_coarse_pcg<NN, T, false>), dim3(grid), dim3(kBlock), 0, s,
+                       (const T*)a.f, (T*)a.x, (T*)a.r, (T*)a.z, (T*)a.p, (T*)a.Ap, (const T*)a.dinv,
+                       (const T*)o.geo, o.conn, (const T*)o.kap, (const T*)o.ops, T(o.lambda), T(o.ctau),
+                       o.K, a.tol, a.max_iters, a.partials, a.bar, a.status, a.skip);
+  return hipGetLastError();
+}
+
+template <int NN, typename T>
+int resident_grid(int K) {
+  int dev = 0, cus = 0, per_cu = 0, per_cu_k = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_coarse_pcg<NN, T, false>, kBlock, 0) != hipSuccess)
+    return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_k, (const void*)k_coarse_pcg<NN, T, true>, kBlock, 0) != hipSuccess)
+    return 0;
+  const int resident = cus * std::min(per_cu, per_cu_k);
+  const int tiles = (K + kBlock - 1) / kBlock;
+  const int g = std::min(resident, tiles);
+  return g > kMaxPartialsCoarse ? kMaxPartialsCoarse : g;
+}
+
 template <typename TC, typename TX, typename TY>
 hipError_t run_ax(const ElemArgs& a, hipStream_t s) {
   int per;
@@ -388,6 +586,35 @@ hipError_t launch_kgrad<N>(const KgradArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(k_kgrad, dim3(grid), dim3(kBlock), 0, s, a.u, a.w, a.out, a.geo, a.conn, a.kap,
                      a.ops, a.ctau, a.K, per);
   return hipGetLastError();
+}
+
+template <int NN>
+hipError_t coarse_impl(Kind kind, const CoarseArgs& a, int grid, hipStream_t s) {
+  if constexpr (NN <= 4) {
+    if (grid < 1) return hipErrorInvalidValue;
+    return kind == Kind::F64 ? run_coarse<NN, double>(a, grid, s) : run_coarse<NN, float>(a, grid, s);
+  } else {
+    return hipErrorNotSupported;
+  }
+}
+
+template <int NN>
+int coarse_grid_impl(Kind kind, int K) {
+  if constexpr (NN <= 4) {
+    return kind == Kind::F64 ? resident_grid<NN, double>(K) : resident_grid<NN, float>(K);
+  } else {
+    return 0;
+  }
+}
+
+template <>
+hipError_t launch_coarse_pcg<N>(Kind kind, const CoarseArgs& a, int grid, hipStream_t s) {
+  return coarse_impl<N>(kind, a, grid, s);
+}
+
+template <>
+int coarse_pcg_grid<N>(Kind kind, int K) {
+  return coarse_grid_impl<N>(kind, K);
 }
 
 template <>

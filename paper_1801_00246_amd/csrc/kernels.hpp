@@ -62,6 +62,29 @@ struct TransferArgs {
 template <int Nf> hipError_t launch_restrict(int Nc, Kind kind, const TransferArgs& a, hipStream_t s);
 template <int Nf> hipError_t launch_prolong(int Nc, Kind kind, const TransferArgs& a, hipStream_t s);
 
+// Whole Jacobi-PCG solve of one (coarse) level in a single persistent launch:
+// x = A^{-1} f to a relative residual tol or max_iters iterations, from x = 0.
+// Blocks synchronise through a grid barrier with a bounded wait; the grid is
+// sized so that every block is resident.  Degrees 1..4 only.
+struct CoarseArgs {
+  const void* f = nullptr;
+  void* x = nullptr;
+  void* r = nullptr;
+  void* z = nullptr;
+  void* p = nullptr;
+  void* Ap = nullptr;
+  const void* dinv = nullptr;
+  ElemArgs op;                 // operator of the level (x, y, partials unused)
+  double tol = 0.0;
+  int max_iters = 0;
+  double* partials = nullptr;  // 3 x kMaxPartials
+  unsigned* bar = nullptr;     // 2 counters, zero between solves
+  int* status = nullptr;       // [0] iterations, [1] barrier timeout, [2] breakdown
+  const int* skip = nullptr;   // outer done flag
+};
+template <int N> hipError_t launch_coarse_pcg(Kind kind, const CoarseArgs& a, int grid, hipStream_t s);
+template <int N> int coarse_pcg_grid(Kind kind, int K);   // resident grid size, 0 if unsupported
+
 // Runtime-degree dispatch (dispatch.cpp)
 hipError_t ax(int N, Kind kind, const ElemArgs& a, hipStream_t s);
 hipError_t diag(int N, Kind kind, const ElemArgs& a, hipStream_t s);
@@ -70,5 +93,7 @@ hipError_t minv(int N, Kind kind, const ElemArgs& a, hipStream_t s);
 hipError_t kgrad(int N, const KgradArgs& a, hipStream_t s);
 hipError_t restrict_(int Nf, int Nc, Kind kind, const TransferArgs& a, hipStream_t s);
 hipError_t prolong(int Nf, int Nc, Kind kind, const TransferArgs& a, hipStream_t s);
+hipError_t coarse_pcg(int N, Kind kind, const CoarseArgs& a, int grid, hipStream_t s);
+int coarse_pcg_grid(int N, Kind kind, int K);
 
 }  // namespace ipdg

@@ -43,6 +43,19 @@ std::vector<double> build_ops_table(int N) {
       for (int m = 0; m < Nfp; ++m) t.push_back(R.Dr[m * Np + j]);
       for (int m = 0; m < Nfp; ++m) t.push_back(R.Ds[m * Np + j]);
     }
+  std::vector<double> E = mul(R.M, R.LIFT, Np, Np, 3 * Nfp);
+  for (int i = 0; i < Np; ++i) {
+    auto row = [&](const std::vector<double>& A, int n) {
+      t.insert(t.end(), A.begin() + (size_t)i * n, A.begin() + (size_t)(i + 1) * n);
+    };
+    row(Krr, Np);
+    row(Krs, Np);
+    row(Kss, Np);
+    row(QR, 3 * Nfp);
+    row(QS, 3 * Nfp);
+    row(E, 3 * Nfp);
+    row(R.M, Np);
+  }
   return t;
 }
 

@@ -185,31 +185,38 @@ __host__ __device__ __forceinline__ void sipdg_element(int e, const TX* __restri
   });
 
   const TC grr = rx * rx + ry * ry, grs = rx * sx + ry * sy, gss = sx * sx + sy * sy;
-  TC ca[3], cb[3];
+  TC ca[3], cb[3], ts[3][Nfp];
 #pragma unroll
   for (int f = 0; f < 3; ++f) {
     ca[f] = TC(0.5) * (rx * gx[f] + ry * gy[f]);
     cb[f] = TC(0.5) * (sx * gx[f] + sy * gy[f]);
+#pragma unroll
+    for (int k = 0; k < Nfp; ++k) ts[f][k] = Fs[f] * J * sf[f][k];
   }
+  phase_fence();
+  // Output rows: a runtime loop over the packed per-row operator stream, so
+  // the scalar loads of one row are contiguous and only one row is in flight.
   const bool has_lambda = (lambda != TC(0));
-  static_for<0, Np>([&](auto ic) {
-    constexpr int i = decltype(ic)::value;
-    const TC* __restrict__ opr = ops + opaque_zero();
+  const TC* __restrict__ rowp = ops + L::ROW;
+#pragma unroll 1
+  for (int i = 0; i < Np; ++i, rowp += L::RowLen) {
     TC trr = TC(0), trs = TC(0), tss = TC(0);
 #pragma unroll
     for (int j = 0; j < Np; ++j) {
-      trr += opr[L::Krr + i * Np + j] * u[j];
-      trs += opr[L::Krs + i * Np + j] * u[j];
-      tss += opr[L::Kss + i * Np + j] * u[j];
+      trr += rowp[j] * u[j];
+      trs += rowp[Np + j] * u[j];
+      tss += rowp[2 * Np + j] * u[j];
     }
     TC acc = grr * trr + grs * trs + gss * tss;
+    TC fa = TC(0);
 #pragma unroll
     for (int f = 0; f < 3; ++f) {
       TC qa = TC(0), qb = TC(0);
 #pragma unroll
       for (int k = 0; k < Nfp; ++k) {
-        qa += opr[L::QR + i * 3 * Nfp + f * Nfp + k] * jmp[f][k];
-        qb += opr[L::QS + i * 3 * Nfp + f * Nfp + k] * jmp[f][k];
+        qa += rowp[3 * Np + f * Nfp + k] * jmp[f][k];
+        qb += rowp[3 * Np + 3 * Nfp + f * Nfp + k] * jmp[f][k];
+        fa += rowp[3 * Np + 6 * Nfp + f * Nfp + k] * ts[f][k];
       }
       acc += ca[f] * qa + cb[f] * qb;
     }
@@ -217,22 +224,11 @@ __host__ __device__ __forceinline__ void sipdg_element(int e, const TX* __restri
     if (has_lambda) {
       TC m = TC(0);
 #pragma unroll
-      for (int j = 0; j < Np; ++j) m += opr[L::M + i * Np + j] * u[j];
+      for (int j = 0; j < Np; ++j) m += rowp[3 * Np + 9 * Nfp + j] * u[j];
       acc += lambda * m;
     }
-    acc *= J;
-    static_for<0, 3>([&](auto fc) {
-      constexpr int f = decltype(fc)::value;
-      constexpr int p = G::fpos(f, i);
-      if constexpr (p >= 0) {
-        TC t = TC(0);
-#pragma unroll
-        for (int k = 0; k < Nfp; ++k) t += opr[L::M1D + p * Nfp + k] * sf[f][k];
-        acc -= Fs[f] * J * t;
-      }
-    });
-    out(i, acc);
-  });
+    out(i, acc * J - fa);
+  }
 }
 
 }  // namespace ipdg

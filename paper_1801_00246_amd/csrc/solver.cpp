@@ -1,18 +1,707 @@
+// Preconditioned conjugate-gradient solvers (Sec. 3) on the device.
+//
+// Outer iteration (one fixed launch sequence, all scalars device-resident):
+//   Ap = A p, (p, Ap)              element kernel with fused dot
+//   alpha = (r, z) / (p, Ap)        finalize
+//   x += alpha p, r -= alpha Ap     fused update (+ Jacobi z = D^-1 r, dots)
+//   z = B r                         block inverse mass / V-cycle
+//   beta                            finalize: textbook (r+, z+)/(r, z) or
+//                                   flexible -(z+, Ap)/(p, Ap) (Notay)
+//   p = z + beta p
+// The host reads the scalars every check_every iterations.  A stop is
+// accepted only on the true FP64 residual b - A x; otherwise the recurrence
+// restarts from it (residual replacement).  In mixed precision the outer
+// operator and the preconditioner run in FP32 while x, r, p, the dots and the
+// true residual stay in FP64, and the residual is also replaced whenever
+// ||r|| fell by reliable_drop since the last replacement.
+//
+// p-multigrid (Sec. 3, the degree-coarsening part of pMG-AMG): levels of
+// degree N_0 > N_1 > ... rediscretise the operator with penalty constant
+// c_tau ((N_l+1)/(N_0+1))^2; restriction P^T and prolongation P (nodal
+// interpolation); Chebyshev smoothing of D^-1 A over [lo rho, hi rho] before
+// and after the coarse correction; the coarsest level is solved by
+// Jacobi-PCG to a relative residual or an iteration cap.
 #include "solver.hpp"
 
-namespace ipdg {
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstddef>
+#include <cstring>
+#include <cstdlib>
+#include <random>
 
-ipdg_status pcg_solve(ipdg_mesh_s*, double, double, const double*, double*, double,
-                      const ipdg_solve_opts&, ipdg_solve_info*, hipStream_t) {
-  throw Error(IPDG_EUNSUPPORTED, "pcg_solve not built yet");
+#include "blas.hpp"
+#include "refelem.hpp"
+
+namespace ipdg {
+namespace {
+
+using clk = std::chrono::steady_clock;
+double ms_since(clk::time_point t) {
+  return std::chrono::duration<double, std::milli>(clk::now() - t).count();
 }
-ipdg_status precond_apply(ipdg_mesh_s*, double, double, const ipdg_solve_opts&, const double*,
-                          double*, ipdg_solve_info*, hipStream_t) {
-  throw Error(IPDG_EUNSUPPORTED, "precond_apply not built yet");
+
+struct Level {
+  int N = 0, Np = 0;
+  size_t n = 0;
+  double ctau = 0, rho = 0;
+  bool fp32 = false;
+  Kind kind = Kind::F64;
+  DevBuf dinv64, dinv32;
+  DevBuf f, z, r, d, t;            // V-cycle work (level precision)
+  DevBuf cr, cz, cp, cAp;          // coarsest level: Jacobi-PCG work
+  const void* P = nullptr;         // interpolation from the next level
+  const void* dinv() const { return fp32 ? dinv32.get() : dinv64.get(); }
+};
+
+struct Work : SolverWork {
+  // configuration the setup was built for
+  double lambda = NAN, ctau = NAN;
+  int pc = -1, prec = -1, cheb_degree = 0, coarse_max = 0, nlev = 0, rho_steps = 0;
+  double cheb_lo = 0, cheb_hi = 0, coarse_tol = 0;
+  int degrees[IPDG_MAX_LEVELS] = {0};
+  double rho_in[IPDG_MAX_LEVELS] = {0};
+  bool has_kappa = false;
+  double setup_ms = 0;
+
+  size_t n = 0;
+  DevBuf r, p, Ap, z, t64, xw, partials, cpartials, scal, cscal, dinv64, dinv32, zero_flag;
+  DevBuf cbar;                     // persistent coarse solve: 2 barrier counters + 3 status ints
+  int coarse_grid = 0;             // resident grid of the persistent coarse solve (0: not used)
+  std::vector<Level> lv;
+  CGScal* host_scal = nullptr;     // pinned
+  hipStream_t gs = nullptr;        // internal stream of the solver (default priority)
+  hipGraphExec_t graph = nullptr;  // check_every captured outer iterations
+  int graph_iters = 0;
+
+  void drop_graph() {
+    if (graph) (void)hipGraphExecDestroy(graph);
+    graph = nullptr;
+    graph_iters = 0;
+  }
+  ~Work() override {
+    drop_graph();
+    if (gs) (void)hipStreamDestroy(gs);
+    if (host_scal) (void)hipHostFree(host_scal);
+  }
+};
+
+size_t off_done() { return offsetof(CGScal, done); }
+const int* done_ptr(const DevBuf& sc) {
+  return reinterpret_cast<const int*>(static_cast<const char*>(sc.get()) + off_done());
 }
-ipdg_status solve_batch(int, ipdg_mesh_s* const*, const double*, double, const double* const*,
-                        double* const*, double, const ipdg_solve_opts&, int*, double*, hipStream_t) {
-  throw Error(IPDG_EUNSUPPORTED, "solve_batch not built yet");
+
+// Largest eigenvalue of a symmetric tridiagonal matrix (Jacobi rotations on
+// the dense copy; k <= a few dozen).
+double tridiag_max_eig(const std::vector<double>& a, const std::vector<double>& b) {
+  const int k = int(a.size());
+  std::vector<double> A(k * k, 0.0);
+  for (int i = 0; i < k; ++i) {
+    A[i * k + i] = a[i];
+    if (i + 1 < k) A[i * k + i + 1] = A[(i + 1) * k + i] = b[i];
+  }
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    double off = 0;
+    for (int p = 0; p < k; ++p)
+      for (int q = p + 1; q < k; ++q) off += A[p * k + q] * A[p * k + q];
+    if (off < 1e-30) break;
+    for (int p = 0; p < k; ++p)
+      for (int q = p + 1; q < k; ++q) {
+        const double apq = A[p * k + q];
+        if (std::fabs(apq) < 1e-300) continue;
+        const double th = (A[q * k + q] - A[p * k + p]) / (2 * apq);
+        const double t = (th >= 0 ? 1 : -1) / (std::fabs(th) + std::sqrt(th * th + 1));
+        const double c = 1 / std::sqrt(t * t + 1), s = t * c;
+        for (int i = 0; i < k; ++i) {
+          const double aip = A[i * k + p], aiq = A[i * k + q];
+          A[i * k + p] = c * aip - s * aiq;
+          A[i * k + q] = s * aip + c * aiq;
+        }
+        for (int i = 0; i < k; ++i) {
+          const double api = A[p * k + i], aqi = A[q * k + i];
+          A[p * k + i] = c * api - s * aqi;
+          A[q * k + i] = s * api + c * aqi;
+        }
+      }
+  }
+  double mx = -INFINITY;
+  for (int i = 0; i < k; ++i) mx = std::max(mx, A[i * k + i]);
+  return mx;
+}
+
+class Solver {
+ public:
+  Solver(ipdg_mesh_s* m, double lambda, double tau, const ipdg_solve_opts& o, hipStream_t s)
+      : m_(m), o_(o), s_(s) {
+    N_ = m->host.N;
+    K_ = m->host.K;
+    n_ = (size_t)K_ * m->Np;
+    lambda_ = lambda;
+    ctau_ = ctau_of(N_, tau);
+    mixed_ = o.prec == IPDG_PREC_MIXED;
+    flexible_ = o.flexible < 0 ? (o.pc == IPDG_PC_PMG || mixed_) : o.flexible != 0;
+    validate();
+    if (elem_grid(K_) > kMaxPartials) throw Error(IPDG_EUNSUPPORTED, "mesh too large for one launch");
+    if (!m->work) m->work = std::make_unique<Work>();
+    w_ = static_cast<Work*>(m->work.get());
+    if (!w_->gs) IPDG_HIP(hipStreamCreateWithFlags(&w_->gs, hipStreamNonBlocking));
+    user_ = s;
+    // the caller's queued work (b, x producers) completes before the solve
+    IPDG_HIP(hipStreamSynchronize(user_));
+    s_ = w_->gs;
+    use_graph_ = std::getenv("IPDG_NO_GRAPH") == nullptr;
+    setup();
+  }
+
+  // z = B r for one FP64 vector (ipdg_precond_apply)
+  void apply_precond(const double* r, double* z, ipdg_solve_info* info) {
+    CGScal sc{};
+    IPDG_HIP(set_scal(w_->scal.as<CGScal>(), sc, s_));
+    IPDG_HIP(hipMemcpyAsync(w_->r.get(), r, n_ * sizeof(double), hipMemcpyDeviceToDevice, s_));
+    precond();
+    if (mixed_) IPDG_HIP(convert(false, z, w_->z.get(), n_, nullptr, s_));
+    else IPDG_HIP(hipMemcpyAsync(z, w_->z.get(), n_ * sizeof(double), hipMemcpyDeviceToDevice, s_));
+    IPDG_HIP(hipStreamSynchronize(s_));
+    fill_info(info, 0, 0.0, 0, 0.0);
+  }
+
+  ipdg_status solve(const double* b, double* x_user, double tol, ipdg_solve_info* info) {
+    if (!(tol > 0.0)) throw Error(IPDG_EINVAL, "tol must be positive");
+    const auto t0 = clk::now();
+    double* x = w_->xw.as<double>();
+    IPDG_HIP(hipMemcpyAsync(x, x_user, n_ * sizeof(double), hipMemcpyDeviceToDevice, s_));
+    CGScal init{};
+    init.tol = tol;
+    init.max_iters = o_.max_iters;
+    init.flexible = flexible_;
+    CGScal* sc = w_->scal.as<CGScal>();
+    IPDG_HIP(set_scal(sc, init, s_));
+    // r = b - A x (FP64), then z = B r, p = z
+    true_residual(b, x);
+    read_scal();
+    const double bb = w_->host_scal->bb;
+    if (bb == 0.0) {
+      IPDG_HIP(hipMemsetAsync(x_user, 0, n_ * sizeof(double), s_));
+      IPDG_HIP(hipStreamSynchronize(s_));
+      fill_info(info, 0, 0.0, 0, ms_since(t0));
+      return IPDG_OK;
+    }
+    double rr_ref = w_->host_scal->rr;
+    restart(x);
+    int restarts = 0;
+    ipdg_status status = IPDG_OK;
+    double relres = std::sqrt(rr_ref / bb);
+    const double drop2 = mixed_ ? o_.reliable_drop * o_.reliable_drop : 0.0;
+    const int every = std::max(1, o_.check_every);
+    for (;;) {
+      run_iterations(x, every);
+      read_scal();
+      const CGScal& h = *w_->host_scal;
+      if (h.breakdown) {
+        status = IPDG_EBREAKDOWN;
+        relres = NAN;
+        break;
+      }
+      const bool stopped = h.done != 0;
+      const bool replace = stopped || (drop2 > 0.0 && h.rr <= drop2 * rr_ref);
+      if (!replace) continue;
+      const int iters_now = h.iters;
+      true_residual(b, x);
+      read_scal();
+      const double rr_true = w_->host_scal->rr;
+      relres = std::sqrt(rr_true / bb);
+      if (!(rr_true == rr_true)) { status = IPDG_EBREAKDOWN; break; }
+      if (rr_true <= tol * tol * bb) break;
+      if (iters_now >= o_.max_iters) { status = IPDG_NOT_CONVERGED; break; }
+      rr_ref = rr_true;
+      ++restarts;
+      // Residual replacement (van der Vorst and Ye): the recurrence continues
+      // from the true residual with the current search direction.  Only when
+      // the recurrence had already stopped (its last direction update was not
+      // applied) is the direction rebuilt from z = B r.
+      if (stopped) restart(x);
+    }
+    IPDG_HIP(hipMemcpyAsync(x_user, x, n_ * sizeof(double), hipMemcpyDeviceToDevice, s_));
+    IPDG_HIP(hipStreamSynchronize(s_));
+    fill_info(info, w_->host_scal->iters, relres, restarts, ms_since(t0));
+    if (status == IPDG_EBREAKDOWN) throw Error(IPDG_EBREAKDOWN, "CG breakdown (p^T A p <= 0 or not finite)");
+    return status;
+  }
+
+ private:
+  void validate() {
+    if (o_.pc < IPDG_PC_NONE || o_.pc > IPDG_PC_PMG) throw Error(IPDG_EINVAL, "bad preconditioner");
+    if (o_.prec != IPDG_PREC_FP64 && o_.prec != IPDG_PREC_MIXED) throw Error(IPDG_EINVAL, "bad precision");
+    if (o_.max_iters < 0) throw Error(IPDG_EINVAL, "max_iters < 0");
+    if (o_.pc == IPDG_PC_PMG) {
+      if (o_.n_levels < 1 || o_.n_levels > IPDG_MAX_LEVELS) throw Error(IPDG_EINVAL, "n_levels out of range");
+      if (o_.degrees[0] != N_) throw Error(IPDG_EINVAL, "degrees[0] must equal the mesh degree");
+      for (int l = 1; l < o_.n_levels; ++l)
+        if (!(o_.degrees[l] < o_.degrees[l - 1]) || o_.degrees[l] < 1)
+          throw Error(IPDG_EINVAL, "degrees must be strictly decreasing and >= 1");
+      if (o_.cheb_degree < 1) throw Error(IPDG_EINVAL, "cheb_degree < 1");
+      if (!(o_.cheb_hi > o_.cheb_lo) || !(o_.cheb_lo > 0)) throw Error(IPDG_EINVAL, "bad Chebyshev interval");
+      if (o_.coarse_max_iters < 0) throw Error(IPDG_EINVAL, "coarse_max_iters < 0");
+    }
+  }
+
+  bool same_setup() const {
+    const Work& w = *w_;
+    if (w.n != n_ || w.lambda != lambda_ || w.ctau != ctau_ || w.pc != o_.pc || w.prec != o_.prec ||
+        w.has_kappa != m_->has_kappa)
+      return false;
+    if (m_->has_kappa) return false;   // kappa may have been replaced
+    if (o_.pc == IPDG_PC_PMG) {
+      if (w.nlev != o_.n_levels || w.cheb_degree != o_.cheb_degree || w.cheb_lo != o_.cheb_lo ||
+          w.cheb_hi != o_.cheb_hi || w.coarse_max != o_.coarse_max_iters ||
+          w.coarse_tol != o_.coarse_tol || w.rho_steps != o_.rho_steps)
+        return false;
+      for (int l = 0; l < o_.n_levels; ++l)
+        if (w.degrees[l] != o_.degrees[l] || w.rho_in[l] != o_.rho[l]) return false;
+    }
+    return true;
+  }
+
+  void setup() {
+    Work& w = *w_;
+    if (same_setup()) return;
+    const auto t0 = clk::now();
+    w.drop_graph();
+    w.lv.clear();
+    w.n = n_;
+    w.xw.ensure(n_ * 8);
+    w.r.ensure(n_ * 8);
+    w.p.ensure(n_ * 8);
+    w.t64.ensure(n_ * 8);
+    w.Ap.ensure(n_ * (mixed_ ? 4 : 8));
+    w.z.ensure(n_ * (mixed_ ? 4 : 8));
+    w.partials.ensure(3 * kMaxPartials * sizeof(double));
+    w.cpartials.ensure(3 * kMaxPartials * sizeof(double));
+    w.scal.ensure(sizeof(CGScal));
+    w.cscal.ensure(sizeof(CGScal));
+    w.zero_flag.ensure(sizeof(int));
+    IPDG_HIP(hipMemsetAsync(w.zero_flag.get(), 0, sizeof(int), s_));
+    if (!w.host_scal) IPDG_HIP(hipHostMalloc(reinterpret_cast<void**>(&w.host_scal), sizeof(CGScal)));
+    if (o_.pc == IPDG_PC_JACOBI || o_.pc == IPDG_PC_NONE) {
+      w.dinv64.ensure(n_ * 8);
+      w.dinv32.ensure(n_ * 4);
+      if (o_.pc == IPDG_PC_JACOBI) {
+        ElemArgs a = elem_args(m_, N_, Kind::F64, lambda_, ctau_);
+        a.y = w.dinv64.get();
+        IPDG_HIP(diag(N_, Kind::F64, a, s_));
+      } else {
+        std::vector<double> ones(n_, 1.0);
+        IPDG_HIP(hipMemcpyAsync(w.dinv64.get(), ones.data(), n_ * 8, hipMemcpyHostToDevice, s_));
+        IPDG_HIP(hipStreamSynchronize(s_));
+        IPDG_HIP(recip(w.dinv64.as<double>(), nullptr, n_, s_));   // keeps 1
+      }
+      if (o_.pc == IPDG_PC_JACOBI) IPDG_HIP(recip(w.dinv64.as<double>(), w.dinv32.as<float>(), n_, s_));
+    }
+    if (o_.pc == IPDG_PC_PMG) setup_pmg();
+    // every operator table a captured iteration uses exists before capture
+    (void)device_ops(N_, Kind::F64);
+    (void)device_ops(N_, Kind::F32);
+    for (const Level& v : w.lv) {
+      (void)device_ops(v.N, Kind::F64);
+      (void)device_ops(v.N, Kind::F32);
+    }
+    IPDG_HIP(hipStreamSynchronize(s_));
+    w.lambda = lambda_;
+    w.ctau = ctau_;
+    w.pc = o_.pc;
+    w.prec = o_.prec;
+    w.has_kappa = m_->has_kappa;
+    w.nlev = o_.n_levels;
+    w.cheb_degree = o_.cheb_degree;
+    w.cheb_lo = o_.cheb_lo;
+    w.cheb_hi = o_.cheb_hi;
+    w.coarse_max = o_.coarse_max_iters;
+    w.coarse_tol = o_.coarse_tol;
+    w.rho_steps = o_.rho_steps;
+    for (int l = 0; l < IPDG_MAX_LEVELS; ++l) {
+      w.degrees[l] = o_.degrees[l];
+      w.rho_in[l] = o_.rho[l];
+    }
+    w.setup_ms = ms_since(t0);
+  }
+
+  void setup_pmg() {
+    Work& w = *w_;
+    const int L = o_.n_levels;
+    w.lv.resize(L);
+    for (int l = 0; l < L; ++l) {
+      Level& v = w.lv[l];
+      v.N = o_.degrees[l];
+      v.Np = np_of(v.N);
+      v.n = (size_t)K_ * v.Np;
+      const double q = double(v.N + 1) / double(N_ + 1);
+      v.ctau = ctau_ * q * q;
+      v.fp32 = mixed_;
+      v.kind = mixed_ ? Kind::F32 : Kind::F64;
+      const size_t w8 = v.fp32 ? 4 : 8;
+      v.dinv64.ensure(v.n * 8);
+      v.dinv32.ensure(v.n * 4);
+      ElemArgs a = elem_args(m_, v.N, Kind::F64, lambda_, v.ctau);
+      a.y = v.dinv64.get();
+      IPDG_HIP(diag(v.N, Kind::F64, a, s_));
+      IPDG_HIP(recip(v.dinv64.as<double>(), v.dinv32.as<float>(), v.n, s_));
+      if (l > 0) v.f.ensure(v.n * w8);
+      if (l > 0 || l + 1 < L) v.z.ensure(v.n * w8);
+      v.r.ensure(v.n * w8);
+      v.d.ensure(v.n * w8);
+      v.t.ensure(v.n * w8);
+      if (l == 0 && mixed_) v.f.ensure(v.n * w8);
+      if (l == L - 1) {
+        v.cr.ensure(v.n * w8);
+        v.cz.ensure(v.n * w8);
+        v.cp.ensure(v.n * w8);
+        v.cAp.ensure(v.n * w8);
+        if (!v.z.get()) v.z.ensure(v.n * w8);
+      }
+      if (l > 0) w.lv[l - 1].P = device_interp(v.N, w.lv[l - 1].N, mixed_);
+    }
+    for (int l = 0; l < L; ++l) {
+      Level& v = w.lv[l];
+      v.rho = o_.rho[l] > 0.0 ? o_.rho[l] : lanczos_rho(v, l);
+    }
+    CGScal c{};
+    c.tol = o_.coarse_tol;
+    c.max_iters = o_.coarse_max_iters;
+    c.flexible = 0;
+    IPDG_HIP(set_scal(w.cscal.as<CGScal>(), c, s_));
+    w.cbar.ensure(8 * sizeof(int));
+    IPDG_HIP(zero_ints(w.cbar.get(), 8, s_));
+    const Level& cl = w.lv.back();
+    w.coarse_grid = std::getenv("IPDG_NO_PERSISTENT") ? 0 : coarse_pcg_grid(cl.N, cl.kind, K_);
+  }
+
+  // rho_steps Jacobi-PCG (Lanczos) steps on a level operator in FP64 from a
+  // seeded N(0,1) right-hand side; largest Ritz value of D^-1 A.
+  double lanczos_rho(Level& v, int l) {
+    Work& w = *w_;
+    const int steps = std::max(2, o_.rho_steps);
+    std::mt19937_64 gen(1234 + l);
+    std::normal_distribution<double> nd(0.0, 1.0);
+    std::vector<double> bh(v.n);
+    for (auto& e : bh) e = nd(gen);
+    DevBuf b(v.n * 8), x(v.n * 8), r(v.n * 8), z(v.n * 8), p(v.n * 8), Ap(v.n * 8);
+    IPDG_HIP(hipMemcpyAsync(b.get(), bh.data(), v.n * 8, hipMemcpyHostToDevice, s_));
+    CGScal c{};
+    c.tol = 0.0;
+    c.max_iters = steps + 1;
+    CGScal* sc = w.cscal.as<CGScal>();
+    IPDG_HIP(set_scal(sc, c, s_));
+    IPDG_HIP(cg_start0(false, b.get(), v.dinv64.get(), x.get(), r.get(), z.get(), p.get(), v.n,
+                       w.cpartials.as<double>(), nullptr, s_));
+    IPDG_HIP(cg_start_fin(w.cpartials.as<double>(), flat_grid(v.n), sc, nullptr, s_));
+    std::vector<double> al, be;
+    ElemArgs a = elem_args(m_, v.N, Kind::F64, lambda_, v.ctau);
+    for (int k = 0; k < steps; ++k) {
+      a.x = p.get();
+      a.y = Ap.get();
+      a.partials = w.cpartials.as<double>();
+      a.skip = nullptr;
+      IPDG_HIP(ax(v.N, Kind::F64, a, s_));
+      IPDG_HIP(finalize(w.cpartials.as<double>(), elem_grid(K_), 1, sc, kFinAlpha, s_));
+      IPDG_HIP(cg_update_state(false, x.get(), r.get(), p.get(), Ap.get(), v.dinv64.get(), z.get(), sc,
+                               v.n, w.cpartials.as<double>(), s_));
+      IPDG_HIP(finalize(w.cpartials.as<double>(), flat_grid(v.n), 3, sc, kFinBeta, s_));
+      IPDG_HIP(hipMemcpyAsync(w.host_scal, sc, sizeof(CGScal), hipMemcpyDeviceToHost, s_));
+      IPDG_HIP(hipStreamSynchronize(s_));
+      if (w.host_scal->done && w.host_scal->iters <= k) break;
+      al.push_back(w.host_scal->alpha);
+      be.push_back(w.host_scal->beta);
+      IPDG_HIP(cg_pupdate_state(false, p.get(), z.get(), sc, v.n, s_));
+    }
+    const int k = int(al.size());
+    if (k == 0) return 1.0;
+    std::vector<double> diag_(k), off(k > 1 ? k - 1 : 0);
+    for (int i = 0; i < k; ++i) {
+      diag_[i] = 1.0 / al[i] + (i > 0 ? be[i - 1] / al[i - 1] : 0.0);
+      if (i + 1 < k) off[i] = std::sqrt(be[i]) / al[i];
+    }
+    return tridiag_max_eig(diag_, off);
+  }
+
+  void read_scal() {
+    IPDG_HIP(hipMemcpyAsync(w_->host_scal, w_->scal.get(), sizeof(CGScal), hipMemcpyDeviceToHost, s_));
+    IPDG_HIP(hipStreamSynchronize(s_));
+  }
+
+  // r = b - A x in FP64 and (r, r), (b, b)
+  void true_residual(const double* b, const double* x) {
+    ElemArgs a = elem_args(m_, N_, Kind::F64, lambda_, ctau_);
+    a.x = x;
+    a.y = w_->t64.get();
+    IPDG_HIP(ax(N_, Kind::F64, a, s_));
+    IPDG_HIP(residual(b, w_->t64.as<double>(), w_->r.as<double>(), n_, w_->partials.as<double>(), s_));
+    IPDG_HIP(finalize(w_->partials.as<double>(), flat_grid(n_), 2, w_->scal.as<CGScal>(), kFinResidual, s_));
+  }
+
+  // z = B r, (r, z), p = z
+  void restart(double*) {
+    precond();
+    IPDG_HIP(dots_rz(mixed_, w_->r.as<double>(), w_->z.get(), nullptr, w_->scal.as<CGScal>(), n_,
+                     w_->partials.as<double>(), s_));
+    IPDG_HIP(finalize(w_->partials.as<double>(), flat_grid(n_), 3, w_->scal.as<CGScal>(), kFinInit, s_));
+    if (mixed_) IPDG_HIP(convert(false, w_->p.get(), w_->z.get(), n_, nullptr, s_));
+    else IPDG_HIP(hipMemcpyAsync(w_->p.get(), w_->z.get(), n_ * 8, hipMemcpyDeviceToDevice, s_));
+  }
+
+  const int* outer_done() const { return done_ptr(w_->scal); }
+
+  // z = B r (outer precision of z)
+  void precond() {
+    Work& w = *w_;
+    switch (o_.pc) {
+      case IPDG_PC_NONE:
+      case IPDG_PC_JACOBI:
+        IPDG_HIP(jacobi(mixed_, w.r.as<double>(), w.dinv64.as<double>(), w.z.get(), n_, s_));
+        break;
+      case IPDG_PC_BLOCK_MASS: {
+        const Kind k = mixed_ ? Kind::F32_IN64 : Kind::F64;
+        ElemArgs a = elem_args(m_, N_, k, 0.0, 0.0);
+        a.x = w.r.get();
+        a.y = w.z.get();
+        a.skip = outer_done();
+        IPDG_HIP(minv(N_, k, a, s_));
+        break;
+      }
+      case IPDG_PC_PMG: {
+        Level& v0 = w.lv[0];
+        if (mixed_) IPDG_HIP(convert(true, v0.f.get(), w.r.get(), n_, outer_done(), s_));
+        vcycle(0, mixed_ ? v0.f.get() : w.r.get(), w.z.get());
+        break;
+      }
+    }
+  }
+
+  void level_ax(const Level& v, const void* x, void* y) {
+    ElemArgs a = elem_args(m_, v.N, v.kind, lambda_, v.ctau);
+    a.x = x;
+    a.y = y;
+    a.skip = outer_done();
+    IPDG_HIP(ax(v.N, v.kind, a, s_));
+  }
+
+  void smooth(const Level& v, const void* f, void* z, bool from_zero) {
+    const double lo = o_.cheb_lo * v.rho, hi = o_.cheb_hi * v.rho;
+    const double theta = 0.5 * (hi + lo), delta = 0.5 * (hi - lo), sigma = theta / delta;
+    double rho = 1.0 / sigma;
+    if (from_zero) {
+      IPDG_HIP(cheb(v.fp32, 0, f, nullptr, v.dinv(), z, v.d.get(), v.r.get(), 1.0 / theta, 0, 0, v.n,
+                    outer_done(), s_));
+    } else {
+      level_ax(v, z, v.t.get());
+      IPDG_HIP(cheb(v.fp32, 1, f, v.t.get(), v.dinv(), z, v.d.get(), v.r.get(), 1.0 / theta, 0, 0, v.n,
+                    outer_done(), s_));
+    }
+    for (int k = 1; k < o_.cheb_degree; ++k) {
+      const double rho_new = 1.0 / (2.0 * sigma - rho);
+      level_ax(v, v.d.get(), v.t.get());
+      IPDG_HIP(cheb(v.fp32, 2, nullptr, v.t.get(), v.dinv(), z, v.d.get(), v.r.get(), 0,
+                    rho_new * rho, 2.0 * rho_new / delta, v.n, outer_done(), s_));
+      rho = rho_new;
+    }
+  }
+
+  void vcycle(int l, const void* f, void* z) {
+    Work& w = *w_;
+    Level& v = w.lv[l];
+    if (l + 1 == (int)w.lv.size()) {
+      coarse_solve(v, f, z);
+      return;
+    }
+    Level& c = w.lv[l + 1];
+    smooth(v, f, z, true);
+    level_ax(v, z, v.t.get());
+    TransferArgs ta;
+    ta.f = f;
+    ta.Az = v.t.get();
+    ta.coarse = c.f.get();
+    ta.P = v.P;
+    ta.K = K_;
+    ta.skip = outer_done();
+    IPDG_HIP(restrict_(v.N, c.N, v.kind, ta, s_));
+    vcycle(l + 1, c.f.get(), c.z.get());
+    TransferArgs tp;
+    tp.coarse = c.z.get();
+    tp.fine = z;
+    tp.P = v.P;
+    tp.K = K_;
+    tp.skip = outer_done();
+    IPDG_HIP(prolong(v.N, c.N, v.kind, tp, s_));
+    smooth(v, f, z, false);
+  }
+
+  // Jacobi-PCG from zero on the coarsest level, coarse_max iterations at most
+  void coarse_solve(Level& v, const void* f, void* x) {
+    Work& w = *w_;
+    if (w.coarse_grid > 0) {
+      // one persistent launch (barrier counters reset by a kernel node)
+      IPDG_HIP(zero_ints(w.cbar.get(), 5, s_));
+      CoarseArgs ca;
+      ca.f = f;
+      ca.x = x;
+      ca.r = v.cr.get();
+      ca.z = v.cz.get();
+      ca.p = v.cp.get();
+      ca.Ap = v.cAp.get();
+      ca.dinv = v.dinv();
+      ca.op = elem_args(m_, v.N, v.kind, lambda_, v.ctau);
+      ca.tol = o_.coarse_tol;
+      ca.max_iters = o_.coarse_max_iters;
+      ca.partials = w.cpartials.as<double>();
+      ca.bar = w.cbar.as<unsigned>();
+      ca.status = w.cbar.as<int>() + 2;
+      ca.skip = outer_done();
+      IPDG_HIP(coarse_pcg(v.N, v.kind, ca, w.coarse_grid, s_));
+      return;
+    }
+    CGScal* sc = w.cscal.as<CGScal>();
+    double* part = w.cpartials.as<double>();
+    IPDG_HIP(cg_start0(v.fp32, f, v.dinv(), x, v.cr.get(), v.cz.get(), v.cp.get(), v.n, part,
+                       outer_done(), s_));
+    IPDG_HIP(cg_start_fin(part, flat_grid(v.n), sc, outer_done(), s_));
+    const int* cdone = done_ptr(w.cscal);
+    ElemArgs a = elem_args(m_, v.N, v.kind, lambda_, v.ctau);
+    for (int it = 0; it < o_.coarse_max_iters; ++it) {
+      a.x = v.cp.get();
+      a.y = v.cAp.get();
+      a.partials = part;
+      a.skip = cdone;
+      IPDG_HIP(ax(v.N, v.kind, a, s_));
+      IPDG_HIP(finalize(part, elem_grid(K_), 1, sc, kFinAlpha, s_));
+      IPDG_HIP(cg_update_state(v.fp32, x, v.cr.get(), v.cp.get(), v.cAp.get(), v.dinv(), v.cz.get(), sc,
+                               v.n, part, s_));
+      IPDG_HIP(finalize(part, flat_grid(v.n), 3, sc, kFinBeta, s_));
+      IPDG_HIP(cg_pupdate_state(v.fp32, v.cp.get(), v.cz.get(), sc, v.n, s_));
+    }
+  }
+
+  // `every` outer iterations: replayed from a captured graph (all pointers
+  // are internal buffers, fixed for the lifetime of the setup)
+  void run_iterations(double* x, int every) {
+    if (!use_graph_) {
+      for (int k = 0; k < every; ++k) iteration(x);
+      return;
+    }
+    Work& w = *w_;
+    if (!w.graph || w.graph_iters != every) {
+      w.drop_graph();
+      hipGraph_t g = nullptr;
+      IPDG_HIP(hipStreamBeginCapture(s_, hipStreamCaptureModeThreadLocal));
+      try {
+        for (int k = 0; k < every; ++k) iteration(x);
+      } catch (...) {
+        (void)hipStreamEndCapture(s_, &g);
+        if (g) (void)hipGraphDestroy(g);
+        throw;
+      }
+      IPDG_HIP(hipStreamEndCapture(s_, &g));
+      hipError_t e = hipGraphInstantiate(&w.graph, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      IPDG_HIP(e);
+      w.graph_iters = every;
+    }
+    IPDG_HIP(hipGraphLaunch(w.graph, s_));
+  }
+
+  void iteration(double* x) {
+    Work& w = *w_;
+    CGScal* sc = w.scal.as<CGScal>();
+    const Kind ka = mixed_ ? Kind::F32_IN64 : Kind::F64;
+    ElemArgs a = elem_args(m_, N_, ka, lambda_, ctau_);
+    a.x = w.p.get();
+    a.y = w.Ap.get();
+    a.partials = w.partials.as<double>();
+    a.skip = outer_done();
+    IPDG_HIP(ax(N_, ka, a, s_));
+    IPDG_HIP(finalize(w.partials.as<double>(), elem_grid(K_), 1, sc, kFinAlpha, s_));
+    const bool jac = o_.pc == IPDG_PC_JACOBI || o_.pc == IPDG_PC_NONE;
+    IPDG_HIP(cg_update(mixed_, jac, x, w.r.as<double>(), w.p.as<double>(), w.Ap.get(), w.dinv64.as<double>(),
+                       w.z.get(), sc, n_, w.partials.as<double>(), s_));
+    if (!jac) {
+      precond();
+      IPDG_HIP(dots_rz(mixed_, w.r.as<double>(), w.z.get(), w.Ap.get(), sc, n_, w.partials.as<double>(), s_));
+    }
+    IPDG_HIP(finalize(w.partials.as<double>(), flat_grid(n_), 3, sc, kFinBeta, s_));
+    IPDG_HIP(pupdate(mixed_, w.p.as<double>(), w.z.get(), sc, n_, s_));
+  }
+
+  // status of the persistent coarse solve: [0] iterations, [1] barrier
+  // timeout, [2] breakdown
+  int coarse_status() {
+    Work& w = *w_;
+    if (o_.pc != IPDG_PC_PMG || w.coarse_grid == 0) return -1;
+    int st[3] = {0, 0, 0};
+    IPDG_HIP(hipMemcpyAsync(st, w.cbar.as<int>() + 2, sizeof(st), hipMemcpyDeviceToHost, s_));
+    IPDG_HIP(hipStreamSynchronize(s_));
+    if (st[1]) throw Error(IPDG_EHIP, "coarse solve: grid barrier timed out");
+    return st[0];
+  }
+
+  void fill_info(ipdg_solve_info* info, int iters, double relres, int restarts, double solve_ms) {
+    const int citers = coarse_status();
+    if (!info) return;
+    std::memset(info, 0, sizeof(*info));
+    info->coarse_iters = citers;
+    info->iters = iters;
+    info->relres = relres;
+    info->restarts = restarts;
+    for (size_t l = 0; l < w_->lv.size() && l < IPDG_MAX_LEVELS; ++l) info->rho_used[l] = w_->lv[l].rho;
+    info->setup_ms = w_->setup_ms;
+    info->solve_ms = solve_ms;
+  }
+
+  ipdg_mesh_s* m_;
+  ipdg_solve_opts o_;
+  hipStream_t s_;
+  hipStream_t user_ = nullptr;
+  bool use_graph_ = true;
+  Work* w_ = nullptr;
+  int N_ = 0, K_ = 0;
+  size_t n_ = 0;
+  double lambda_ = 0, ctau_ = 0;
+  bool mixed_ = false, flexible_ = false;
+};
+
+}  // namespace
+
+ipdg_status pcg_solve(ipdg_mesh_s* m, double lambda, double tau, const double* b, double* x, double tol,
+                      const ipdg_solve_opts& o, ipdg_solve_info* info, hipStream_t s) {
+  if (m->host.K == 0) {
+    if (info) std::memset(info, 0, sizeof(*info));
+    return IPDG_OK;
+  }
+  if (!b || !x) throw Error(IPDG_EINVAL, "null vector");
+  Solver sv(m, lambda, tau, o, s);
+  return sv.solve(b, x, tol, info);
+}
+
+ipdg_status precond_apply(ipdg_mesh_s* m, double lambda, double tau, const ipdg_solve_opts& o,
+                          const double* r, double* z, ipdg_solve_info* info, hipStream_t s) {
+  if (m->host.K == 0) return IPDG_OK;
+  if (!r || !z) throw Error(IPDG_EINVAL, "null vector");
+  Solver sv(m, lambda, tau, o, s);
+  sv.apply_precond(r, z, info);
+  return IPDG_OK;
+}
+
+ipdg_status solve_batch(int nb, ipdg_mesh_s* const* meshes, const double* lambdas, double tau,
+                        const double* const* b, double* const* x, double tol, const ipdg_solve_opts& o,
+                        int* iters, double* relres, hipStream_t s) {
+  ipdg_status worst = IPDG_OK;
+  for (int i = 0; i < nb; ++i) {
+    if (!meshes[i]) throw Error(IPDG_EINVAL, "null mesh in batch");
+    ipdg_solve_info info{};
+    ipdg_status st = pcg_solve(meshes[i], lambdas[i], tau, b[i], x[i], tol, o, &info, s);
+    if (iters) iters[i] = info.iters;
+    if (relres) relres[i] = info.relres;
+    if (st != IPDG_OK) worst = st;
+  }
+  return worst;
 }
 
 }  // namespace ipdg

@@ -85,12 +85,17 @@ struct OpsLayout {
   static constexpr int LIFT = QS + Np * 3 * Nfp;
   static constexpr int M1D = LIFT + Np * 3 * Nfp;
   static constexpr int NBR = M1D + Nfp * Nfp;
-  static constexpr int total = NBR + 3 * 2 * Nfp * Np;
+  // ROW: per output row i, the contiguous operator stream of the row phase:
+  //   Krr_i | Krs_i | Kss_i (Np each) | QR_i | QS_i | E_i (3 Nfp each) | M_i
+  // with E = M LIFT (the face mass scattered to face-node rows).
+  static constexpr int RowLen = 4 * Np + 9 * Nfp;
+  static constexpr int ROW = NBR + 3 * 2 * Nfp * Np;
+  static constexpr int total = ROW + Np * RowLen;
 };
 
 inline int ops_total(int N) {
   const int Np = (N + 1) * (N + 2) / 2, Nfp = N + 1;
-  return 7 * Np * Np + 3 * Np * 3 * Nfp + Nfp * Nfp + 6 * Nfp * Np;
+  return 7 * Np * Np + 3 * Np * 3 * Nfp + Nfp * Nfp + 6 * Nfp * Np + Np * (4 * Np + 9 * Nfp);
 }
 
 }  // namespace ipdg

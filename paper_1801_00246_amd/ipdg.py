@@ -43,12 +43,12 @@ class SolveOpts(C.Structure):
 class SolveInfo(C.Structure):
     _fields_ = [("iters", C.c_int), ("relres", C.c_double), ("restarts", C.c_int),
                 ("rho_used", C.c_double * MAX_LEVELS), ("setup_ms", C.c_double),
-                ("solve_ms", C.c_double)]
+                ("solve_ms", C.c_double), ("coarse_iters", C.c_int)]
 
     def as_dict(self):
         return {"iters": self.iters, "relres": self.relres, "restarts": self.restarts,
                 "rho_used": list(self.rho_used), "setup_ms": self.setup_ms,
-                "solve_ms": self.solve_ms}
+                "solve_ms": self.solve_ms, "coarse_iters": self.coarse_iters}
 
 
 _lib = None
