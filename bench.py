@@ -186,6 +186,40 @@ def run_pcg_compare(P, torch, coarse_caps=(200, 20)):
     return out
 
 
+def run_batch_compare(P, torch, nb=64, prec=None, tol=1e-8):
+    """Batched Helmholtz: nb independent (lambda_i M - Lap) u_i = M f_i on
+    n_i x n_i squares (n_i ~ U{32..128}), N_i ~ U{4..8}, lambda_i = 10^U(0,3),
+    f ~ N(0,1) nodal, Dirichlet, block inverse-mass PCG to 1e-8; one batched
+    call (one graph launch per check interval) vs nb serial solves."""
+    import synth
+    ns, Ns, lams, fseeds = synth.batch_draws(nb, seed=4)
+    meshes, bs = [], []
+    for n, N, fs in zip(ns, Ns, fseeds):
+        msh = synth.square_mesh(int(n))
+        g = P.Mesh.from_synth(int(N), msh)
+        f = torch.from_numpy(synth.nodal_normal(msh.K, g.Np, seed=int(fs))).to("cuda")
+        meshes.append(g)
+        bs.append(g.mass(f))
+    o = P.default_opts(pc=P.PC_BLOCK_MASS, prec=P.PREC_FP64 if prec is None else prec)
+    torch.cuda.synchronize()
+    t0 = time.time()
+    xs, iters, rel, st = P.solve_batch(meshes, lams, bs, tol=tol, opts=o)
+    torch.cuda.synchronize()
+    t_batch = time.time() - t0
+    t0 = time.time()
+    serial_iters = []
+    for g, lam, b in zip(meshes, lams, bs):
+        _, info, _ = g.pcg(b, lam=float(lam), tol=tol, opts=o)
+        serial_iters.append(info["iters"])
+    torch.cuda.synchronize()
+    t_serial = time.time() - t0
+    dofs = sum(g.ndof for g in meshes)
+    return {"workload": f"{nb} solves, n~U{{32..128}}, N~U{{4..8}}, lambda=10^U(0,3), block-mass PCG",
+            "total_dofs": dofs, "batched_s": round(t_batch, 3), "serial_s": round(t_serial, 3),
+            "speedup": round(t_serial / t_batch, 2), "iters_max": max(iters), "iters_sum": sum(iters),
+            "max_relres": max(rel), "status": st}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -198,6 +232,8 @@ def main():
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--no-pcg", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--batch", action="store_true", help="also run the 64-solve batched Helmholtz leg")
+    ap.add_argument("--sweep-orders", default="1,2,3,4,5,6,7,8")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
@@ -231,7 +267,7 @@ def main():
         line["cpu_baseline"] = cpu_baseline(N, args.lam)
     if not args.no_sweep:
         sweep = []
-        for Ns in range(1, 9):
+        for Ns in [int(v) for v in args.sweep_orders.split(",")]:
             for dname, dts, ws in (("f64", torch.float64, 8), ("f32", torch.float32, 4)):
                 for lam in (0.0, 100.0):
                     msw, _ = time_applies(P, torch, msh, Ns, dts, lam, 50, 5, args.rotate_gb * 1e9)
@@ -247,6 +283,9 @@ def main():
             line["pcg"] = run_pcg_compare(P, torch)
         except P.IpdgError as e:
             line["pcg"] = {"error": str(e)}
+    if args.batch:
+        line["batch"] = run_batch_compare(P, torch)
+        print(f"# batch: {line['batch']}", file=sys.stderr, flush=True)
     print(json.dumps(line), flush=True)
 
 

@@ -1,7 +1,35 @@
 // Runtime-degree dispatch to the per-degree kernel instantiations.
 #include "kernels.hpp"
 
+#include <atomic>
+#include <cstdlib>
+
 namespace ipdg {
+
+namespace {
+// default: staged for the bandwidth-bound degrees
+std::atomic<int> g_variant[2][9] = {{0, 1, 1, 1, 1, 0, 0, 0, 0}, {0, 1, 1, 1, 1, 0, 0, 0, 0}};
+bool env_read = false;
+}  // namespace
+
+int ax_variant(int N, bool fp32) {
+  if (!env_read) {
+    env_read = true;
+    if (const char* v = std::getenv("IPDG_AX_VARIANT")) {
+      const int k = std::atoi(v);
+      for (int n = 1; n <= 8; ++n) {
+        g_variant[0][n] = n <= 5 ? k : 0;
+        g_variant[1][n] = n <= 5 ? k : 0;
+      }
+    }
+  }
+  if (N < 1 || N > 8) return 0;
+  return g_variant[fp32 ? 1 : 0][N].load();
+}
+
+void set_ax_variant(int N, bool fp32, int v) {
+  if (N >= 1 && N <= 8) g_variant[fp32 ? 1 : 0][N] = (N <= 5) ? v : 0;
+}
 
 #define IPDG_SWITCH(N_, CALL)      \
   switch (N_) {                    \

@@ -28,7 +28,14 @@ constexpr int ax_waves() {
   else return N <= 2 ? 8 : (N <= 4 ? 5 : (N <= 6 ? 3 : 2));
 }
 
-template <typename TC, typename TX, typename TY, bool KAP>
+// LDS pitch (elements) of the staging buffer: odd in 8-byte words, so that
+// both the cooperative copy and the per-lane accesses avoid bank conflicts.
+constexpr int kPitch = kBlock + 1;
+
+// STAGE: the block's own inputs and outputs go through LDS, so that global
+// loads and stores are fully coalesced (lane t touches word t of the block's
+// contiguous chunk) instead of Np-strided per lane.
+template <typename TC, typename TX, typename TY, bool KAP, bool STAGE>
 __global__ __launch_bounds__(kBlock) void k_ax(const TX* __restrict__ x, TY* __restrict__ y,
                                                const TC* __restrict__ geo,
                                                const Conn* __restrict__ conn,
@@ -37,19 +44,52 @@ __global__ __launch_bounds__(kBlock) void k_ax(const TX* __restrict__ x, TY* __r
                                                int K, int per, double* __restrict__ partials,
                                                const int* __restrict__ skip) {
   if (skip && *skip) return;
-  const int e = xcd_tile(blockIdx.x, per) * kBlock + threadIdx.x;
+  const int e0 = xcd_tile(blockIdx.x, per) * kBlock;
+  const int e = e0 + threadIdx.x;
+  const bool want_dot = partials != nullptr;
   double dot = 0.0;
-  if (e < K) {
-    TC u[Np];
-    TY* ye = y + (size_t)e * Np;
-    const TX* xe = x + (size_t)e * Np;
-    const bool want_dot = partials != nullptr;
-    sipdg_element<N, TC, TX, KAP, false>(e, x, geo, conn, kap, ops, lambda, ctau, 0, u,
-                                         [&](int i, TC v) {
-                                           ye[i] = static_cast<TY>(v);
-                                           if (want_dot)
-                                             dot += static_cast<double>(xe[i]) * static_cast<double>(v);
-                                         });
+  if constexpr (STAGE) {
+    __shared__ TC buf[Np * kPitch];
+    const int ne = K - e0 < kBlock ? K - e0 : kBlock;
+    if (ne > 0) {
+      const TX* src = x + (size_t)e0 * Np;
+      for (int t = threadIdx.x; t < ne * Np; t += kBlock) {
+        const int le = t / Np, j = t - le * Np;
+        buf[j * kPitch + le] = static_cast<TC>(src[t]);
+      }
+    }
+    __syncthreads();
+    if (e < K) {
+      TC u[Np];
+      const TX* xe = x + (size_t)e * Np;
+      sipdg_element_own<N, TC, TX, KAP, false>(
+          e, x, geo, conn, kap, ops, lambda, ctau, 0, u,
+          [&](int i, TC v) {
+            buf[i * kPitch + threadIdx.x] = v;
+            if (want_dot) dot += static_cast<double>(xe[i]) * static_cast<double>(v);
+          },
+          [&](int j) { return buf[j * kPitch + threadIdx.x]; });
+    }
+    __syncthreads();
+    if (ne > 0) {
+      TY* dst = y + (size_t)e0 * Np;
+      for (int t = threadIdx.x; t < ne * Np; t += kBlock) {
+        const int le = t / Np, j = t - le * Np;
+        dst[t] = static_cast<TY>(buf[j * kPitch + le]);
+      }
+    }
+  } else {
+    if (e < K) {
+      TC u[Np];
+      TY* ye = y + (size_t)e * Np;
+      const TX* xe = x + (size_t)e * Np;
+      sipdg_element<N, TC, TX, KAP, false>(e, x, geo, conn, kap, ops, lambda, ctau, 0, u,
+                                           [&](int i, TC v) {
+                                             ye[i] = static_cast<TY>(v);
+                                             if (want_dot)
+                                               dot += static_cast<double>(xe[i]) * static_cast<double>(v);
+                                           });
+    }
   }
   if (partials) {
     double v[1] = {dot};
@@ -276,22 +316,30 @@ __device__ bool grid_barrier(unsigned* bar, unsigned nblocks, int* status) {
   __syncthreads();
   if (threadIdx.x == 0) {
     ok = 1;
-    const unsigned gen = __hip_atomic_load(&bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-    const unsigned prev = __hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    // one agent-scope release fence for this block's writes, relaxed polling,
+    // one acquire fence after the wait (an acquire on every poll would
+    // invalidate the caches on each turn of the spin)
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    const unsigned gen = __hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned prev = __hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (prev == nblocks - 1) {
+      // the last arrival takes in every other block's writes before it
+      // releases the waiters
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
       __hip_atomic_store(&bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_fetch_add(&bar[1], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_fetch_add(&bar[1], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     } else {
       unsigned spins = 0;
-      while (__hip_atomic_load(&bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
+      while (__hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gen) {
         if (++spins > kSpinLimit) {
           ok = 0;
           __hip_atomic_store(&status[1], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           break;
         }
-        __builtin_amdgcn_s_sleep(2);
+        __builtin_amdgcn_s_sleep(1);
       }
     }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   }
   __syncthreads();
   return ok != 0;
@@ -452,23 +500,33 @@ int resident_grid(int K) {
   return g > kMaxPartialsCoarse ? kMaxPartialsCoarse : g;
 }
 
+// degrees whose operator kernel is built with the LDS-staged variant too
+constexpr bool kHasStage = N <= 5;
+
+template <typename TC, typename TX, typename TY, bool KAP, bool STAGE>
+void launch_ax_variant(const ElemArgs& a, int grid, int per, hipStream_t s) {
+  hipLaunchKernelGGL((k_ax<TC, TX, TY, KAP, STAGE>), dim3(grid), dim3(kBlock), 0, s,
+                     static_cast<const TX*>(a.x), static_cast<TY*>(a.y),
+                     static_cast<const TC*>(a.geo), a.conn, static_cast<const TC*>(a.kap),
+                     static_cast<const TC*>(a.ops), TC(a.lambda), TC(a.ctau), a.K, per, a.partials,
+                     a.skip);
+}
+
 template <typename TC, typename TX, typename TY>
 hipError_t run_ax(const ElemArgs& a, hipStream_t s) {
   int per;
   const int grid = xcd_grid(elem_tiles(a.K), per);
   if (a.K == 0) return hipSuccess;
-  if (a.kap)
-    hipLaunchKernelGGL((k_ax<TC, TX, TY, true>), dim3(grid), dim3(kBlock), 0, s,
-                       static_cast<const TX*>(a.x), static_cast<TY*>(a.y),
-                       static_cast<const TC*>(a.geo), a.conn, static_cast<const TC*>(a.kap),
-                       static_cast<const TC*>(a.ops), TC(a.lambda), TC(a.ctau), a.K, per,
-                       a.partials, a.skip);
-  else
-    hipLaunchKernelGGL((k_ax<TC, TX, TY, false>), dim3(grid), dim3(kBlock), 0, s,
-                       static_cast<const TX*>(a.x), static_cast<TY*>(a.y),
-                       static_cast<const TC*>(a.geo), a.conn, static_cast<const TC*>(a.kap),
-                       static_cast<const TC*>(a.ops), TC(a.lambda), TC(a.ctau), a.K, per,
-                       a.partials, a.skip);
+  const bool stage = kHasStage && ax_variant(N, sizeof(TC) == 4) == 1;
+  if constexpr (kHasStage) {
+    if (stage) {
+      if (a.kap) launch_ax_variant<TC, TX, TY, true, true>(a, grid, per, s);
+      else launch_ax_variant<TC, TX, TY, false, true>(a, grid, per, s);
+      return hipGetLastError();
+    }
+  }
+  if (a.kap) launch_ax_variant<TC, TX, TY, true, false>(a, grid, per, s);
+  else launch_ax_variant<TC, TX, TY, false, false>(a, grid, per, s);
   return hipGetLastError();
 }
 

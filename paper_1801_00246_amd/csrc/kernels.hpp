@@ -32,6 +32,12 @@ inline int elem_grid(int K) {
   return xcd_grid(elem_tiles(K), per);
 }
 
+// Operator kernel variant per (degree, precision): 0 = direct per-lane
+// loads/stores, 1 = LDS-staged coalesced loads/stores (degrees <= 5).
+// Set by set_ax_variant (autotuner or IPDG_AX_VARIANT), default table below.
+int ax_variant(int N, bool fp32);
+void set_ax_variant(int N, bool fp32, int v);
+
 // y = A x (SIPDG operator).  Per degree, defined in the per-degree units.
 template <int N> hipError_t launch_ax(Kind kind, const ElemArgs& a, hipStream_t s);
 // y = diag(A) (x unused).

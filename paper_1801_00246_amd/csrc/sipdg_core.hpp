@@ -68,14 +68,16 @@ __host__ __device__ __forceinline__ void phase_fence() {
 // formed (so no output array stays live).  DIAG: u = unit vector e_unit on
 // this element and zero neighbours (Jacobi diagonal).  u holds the element's
 // values throughout.
-template <int N, typename TC, typename TX, bool KAP, bool DIAG, typename Out>
-__host__ __device__ __forceinline__ void sipdg_element(int e, const TX* __restrict__ x,
-                                                       const TC* __restrict__ geo,
-                                                       const Conn* __restrict__ conn,
-                                                       const TC* __restrict__ kap,
-                                                       const TC* __restrict__ ops, TC lambda,
-                                                       TC ctau, int unit, TC (&u)[Tri<N>::Np],
-                                                       Out&& out) {
+// As above, with the element's own nodal values supplied by own(j) (e.g. from
+// a block-wide staging buffer).
+template <int N, typename TC, typename TX, bool KAP, bool DIAG, typename Out, typename Own>
+__host__ __device__ __forceinline__ void sipdg_element_own(int e, const TX* __restrict__ x,
+                                                           const TC* __restrict__ geo,
+                                                           const Conn* __restrict__ conn,
+                                                           const TC* __restrict__ kap,
+                                                           const TC* __restrict__ ops, TC lambda,
+                                                           TC ctau, int unit, TC (&u)[Tri<N>::Np],
+                                                           Out&& out, Own&& own) {
   using G = Tri<N>;
   using L = OpsLayout<N>;
   constexpr int Np = G::Np, Nfp = G::Nfp;
@@ -87,7 +89,7 @@ __host__ __device__ __forceinline__ void sipdg_element(int e, const TX* __restri
 #pragma unroll
   for (int j = 0; j < Np; ++j) {
     if constexpr (DIAG) u[j] = (j == unit) ? TC(1) : TC(0);
-    else u[j] = ld<TX, TC>(x + (size_t)e * Np + j);
+    else u[j] = own(j);
   }
 
   const TC gx[3] = {-sx, rx + sx, -rx};
@@ -230,5 +232,18 @@ __host__ __device__ __forceinline__ void sipdg_element(int e, const TX* __restri
     out(i, acc * J - fa);
   }
 }
+
+template <int N, typename TC, typename TX, bool KAP, bool DIAG, typename Out>
+__host__ __device__ __forceinline__ void sipdg_element(int e, const TX* __restrict__ x,
+                                                       const TC* __restrict__ geo,
+                                                       const Conn* __restrict__ conn,
+                                                       const TC* __restrict__ kap,
+                                                       const TC* __restrict__ ops, TC lambda,
+                                                       TC ctau, int unit, TC (&u)[Tri<N>::Np],
+                                                       Out&& out) {
+  sipdg_element_own<N, TC, TX, KAP, DIAG>(e, x, geo, conn, kap, ops, lambda, ctau, unit, u, out,
+                                          [&](int j) { return ld<TX, TC>(x + (size_t)e * Tri<N>::Np + j); });
+}
+
 
 }  // namespace ipdg

@@ -166,67 +166,118 @@ class Solver {
     fill_info(info, 0, 0.0, 0, 0.0);
   }
 
-  ipdg_status solve(const double* b, double* x_user, double tol, ipdg_solve_info* info) {
+  // ---- phases of one solve (shared by solve() and the batched solver) ----
+  struct Run {
+    const double* b = nullptr;
+    double* x_user = nullptr;
+    double tol = 0, bb = 0, rr_ref = 0, relres = 0;
+    int restarts = 0;
+    ipdg_status status = IPDG_OK;
+    bool finished = false;
+    clk::time_point t0;
+  };
+
+  // enqueue: x copy, scalars, r = b - A x; the scalars are copied to the host
+  void start(Run& R, const double* b, double* x_user, double tol) {
     if (!(tol > 0.0)) throw Error(IPDG_EINVAL, "tol must be positive");
-    const auto t0 = clk::now();
+    R = Run();
+    R.b = b;
+    R.x_user = x_user;
+    R.tol = tol;
+    R.t0 = clk::now();
     double* x = w_->xw.as<double>();
     IPDG_HIP(hipMemcpyAsync(x, x_user, n_ * sizeof(double), hipMemcpyDeviceToDevice, s_));
     CGScal init{};
     init.tol = tol;
     init.max_iters = o_.max_iters;
     init.flexible = flexible_;
-    CGScal* sc = w_->scal.as<CGScal>();
-    IPDG_HIP(set_scal(sc, init, s_));
-    // r = b - A x (FP64), then z = B r, p = z
+    IPDG_HIP(set_scal(w_->scal.as<CGScal>(), init, s_));
     true_residual(b, x);
-    read_scal();
-    const double bb = w_->host_scal->bb;
-    if (bb == 0.0) {
-      IPDG_HIP(hipMemsetAsync(x_user, 0, n_ * sizeof(double), s_));
-      IPDG_HIP(hipStreamSynchronize(s_));
-      fill_info(info, 0, 0.0, 0, ms_since(t0));
-      return IPDG_OK;
+    copy_scal();
+  }
+
+  // after the stream has reached the end of start(): z = B r, p = z
+  void after_start(Run& R) {
+    R.bb = w_->host_scal->bb;
+    if (R.bb == 0.0) {
+      IPDG_HIP(hipMemsetAsync(R.x_user, 0, n_ * sizeof(double), s_));
+      mark_done();
+      R.finished = true;
+      return;
     }
-    double rr_ref = w_->host_scal->rr;
-    restart(x);
-    int restarts = 0;
-    ipdg_status status = IPDG_OK;
-    double relres = std::sqrt(rr_ref / bb);
+    R.rr_ref = w_->host_scal->rr;
+    R.relres = std::sqrt(R.rr_ref / R.bb);
+    restart(w_->xw.as<double>());
+  }
+
+  // after `every` iterations and a copy of the scalars: decide to continue,
+  // replace the residual, stop or fail.  Returns true when finished.
+  bool after_step(Run& R) {
+    const CGScal& h = *w_->host_scal;
+    double* x = w_->xw.as<double>();
+    if (h.breakdown) {
+      R.status = IPDG_EBREAKDOWN;
+      R.relres = NAN;
+      mark_done();
+      return R.finished = true;
+    }
     const double drop2 = mixed_ ? o_.reliable_drop * o_.reliable_drop : 0.0;
-    const int every = std::max(1, o_.check_every);
-    for (;;) {
-      run_iterations(x, every);
-      read_scal();
-      const CGScal& h = *w_->host_scal;
-      if (h.breakdown) {
-        status = IPDG_EBREAKDOWN;
-        relres = NAN;
-        break;
-      }
-      const bool stopped = h.done != 0;
-      const bool replace = stopped || (drop2 > 0.0 && h.rr <= drop2 * rr_ref);
-      if (!replace) continue;
-      const int iters_now = h.iters;
-      true_residual(b, x);
-      read_scal();
-      const double rr_true = w_->host_scal->rr;
-      relres = std::sqrt(rr_true / bb);
-      if (!(rr_true == rr_true)) { status = IPDG_EBREAKDOWN; break; }
-      if (rr_true <= tol * tol * bb) break;
-      if (iters_now >= o_.max_iters) { status = IPDG_NOT_CONVERGED; break; }
-      rr_ref = rr_true;
-      ++restarts;
+    const bool stopped = h.done != 0;
+    const bool replace = stopped || (drop2 > 0.0 && h.rr <= drop2 * R.rr_ref);
+    if (!replace) return false;
+    const int iters_now = h.iters;
+    true_residual(R.b, x);
+    read_scal();
+    const double rr_true = w_->host_scal->rr;
+    R.relres = std::sqrt(rr_true / R.bb);
+    if (!(rr_true == rr_true)) R.status = IPDG_EBREAKDOWN;
+    else if (rr_true <= R.tol * R.tol * R.bb) R.status = IPDG_OK;
+    else if (iters_now >= o_.max_iters) R.status = IPDG_NOT_CONVERGED;
+    else {
+      R.rr_ref = rr_true;
+      ++R.restarts;
       // Residual replacement (van der Vorst and Ye): the recurrence continues
       // from the true residual with the current search direction.  Only when
       // the recurrence had already stopped (its last direction update was not
       // applied) is the direction rebuilt from z = B r.
       if (stopped) restart(x);
+      return false;
     }
-    IPDG_HIP(hipMemcpyAsync(x_user, x, n_ * sizeof(double), hipMemcpyDeviceToDevice, s_));
+    mark_done();
+    return R.finished = true;
+  }
+
+  void finish(Run& R, ipdg_solve_info* info) {
+    if (R.bb != 0.0)
+      IPDG_HIP(hipMemcpyAsync(R.x_user, w_->xw.get(), n_ * sizeof(double), hipMemcpyDeviceToDevice, s_));
     IPDG_HIP(hipStreamSynchronize(s_));
-    fill_info(info, w_->host_scal->iters, relres, restarts, ms_since(t0));
-    if (status == IPDG_EBREAKDOWN) throw Error(IPDG_EBREAKDOWN, "CG breakdown (p^T A p <= 0 or not finite)");
-    return status;
+    fill_info(info, R.bb != 0.0 ? w_->host_scal->iters : 0, R.bb != 0.0 ? R.relres : 0.0, R.restarts,
+              ms_since(R.t0));
+    if (R.status == IPDG_EBREAKDOWN) throw Error(IPDG_EBREAKDOWN, "CG breakdown (p^T A p <= 0 or not finite)");
+  }
+
+  ipdg_status solve(const double* b, double* x_user, double tol, ipdg_solve_info* info) {
+    Run R;
+    start(R, b, x_user, tol);
+    IPDG_HIP(hipStreamSynchronize(s_));
+    after_start(R);
+    const int every = std::max(1, o_.check_every);
+    while (!R.finished) {
+      run_iterations(w_->xw.as<double>(), every);
+      read_scal();
+      after_step(R);
+    }
+    finish(R, info);
+    return R.status;
+  }
+
+  // `every` outer iterations enqueued on this solve's stream (no graph)
+  void enqueue_iterations(int every) {
+    for (int k = 0; k < every; ++k) iteration(w_->xw.as<double>());
+  }
+  hipStream_t stream() const { return s_; }
+  void copy_scal() {
+    IPDG_HIP(hipMemcpyAsync(w_->host_scal, w_->scal.get(), sizeof(CGScal), hipMemcpyDeviceToHost, s_));
   }
 
  private:
@@ -425,8 +476,17 @@ class Solver {
   }
 
   void read_scal() {
-    IPDG_HIP(hipMemcpyAsync(w_->host_scal, w_->scal.get(), sizeof(CGScal), hipMemcpyDeviceToHost, s_));
+    copy_scal();
     IPDG_HIP(hipStreamSynchronize(s_));
+  }
+
+  // keep a finished solve's kernels idle (its iterations may still be replayed
+  // inside a batched graph)
+  void mark_done() {
+    CGScal d{};
+    d.done = 1;
+    d.iters = w_->host_scal->iters;
+    IPDG_HIP(set_scal(w_->scal.as<CGScal>(), d, s_));
   }
 
   // r = b - A x in FP64 and (r, r), (b, b)
@@ -692,15 +752,88 @@ ipdg_status precond_apply(ipdg_mesh_s* m, double lambda, double tau, const ipdg_
 ipdg_status solve_batch(int nb, ipdg_mesh_s* const* meshes, const double* lambdas, double tau,
                         const double* const* b, double* const* x, double tol, const ipdg_solve_opts& o,
                         int* iters, double* relres, hipStream_t s) {
-  ipdg_status worst = IPDG_OK;
+  // Every solve keeps its own device state and stream; one captured graph
+  // holds `check_every` iterations of all of them as parallel branches
+  // (fork/join on a batch stream), so a single graph launch advances the
+  // whole batch.  Finished solves' kernels are no-ops (done flag).
   for (int i = 0; i < nb; ++i) {
     if (!meshes[i]) throw Error(IPDG_EINVAL, "null mesh in batch");
-    ipdg_solve_info info{};
-    ipdg_status st = pcg_solve(meshes[i], lambdas[i], tau, b[i], x[i], tol, o, &info, s);
-    if (iters) iters[i] = info.iters;
-    if (relres) relres[i] = info.relres;
-    if (st != IPDG_OK) worst = st;
+    if (!b[i] || !x[i]) throw Error(IPDG_EINVAL, "null vector in batch");
+    for (int j = 0; j < i; ++j)
+      if (meshes[j] == meshes[i]) throw Error(IPDG_EINVAL, "a mesh handle appears twice in the batch");
   }
+  std::vector<std::unique_ptr<Solver>> sv;
+  std::vector<Solver::Run> runs(nb);
+  std::vector<int> active;
+  for (int i = 0; i < nb; ++i) {
+    if (meshes[i]->host.K == 0) continue;
+    sv.emplace_back(new Solver(meshes[i], lambdas[i], tau, o, s));
+    active.push_back(i);
+  }
+  const int na = int(sv.size());
+  for (int k = 0; k < na; ++k) sv[k]->start(runs[k], b[active[k]], x[active[k]], tol);
+  for (int k = 0; k < na; ++k) IPDG_HIP(hipStreamSynchronize(sv[k]->stream()));
+  for (int k = 0; k < na; ++k) sv[k]->after_start(runs[k]);
+  const int every = std::max(1, o.check_every);
+  hipStream_t ms = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::vector<hipEvent_t> ev(na + 1, nullptr);
+  auto cleanup = [&]() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    for (auto e : ev)
+      if (e) (void)hipEventDestroy(e);
+    if (ms) (void)hipStreamDestroy(ms);
+  };
+  try {
+    IPDG_HIP(hipStreamCreateWithFlags(&ms, hipStreamNonBlocking));
+    for (auto& e : ev) IPDG_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    for (int k = 0; k < na; ++k) IPDG_HIP(hipStreamSynchronize(sv[k]->stream()));
+    hipGraph_t g = nullptr;
+    IPDG_HIP(hipStreamBeginCapture(ms, hipStreamCaptureModeThreadLocal));
+    IPDG_HIP(hipEventRecord(ev[na], ms));
+    for (int k = 0; k < na; ++k) {
+      IPDG_HIP(hipStreamWaitEvent(sv[k]->stream(), ev[na], 0));
+      sv[k]->enqueue_iterations(every);
+      IPDG_HIP(hipEventRecord(ev[k], sv[k]->stream()));
+      IPDG_HIP(hipStreamWaitEvent(ms, ev[k], 0));
+    }
+    IPDG_HIP(hipStreamEndCapture(ms, &g));
+    hipError_t e = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    IPDG_HIP(e);
+    int left = 0;
+    for (int k = 0; k < na; ++k) left += !runs[k].finished;
+    while (left > 0) {
+      IPDG_HIP(hipGraphLaunch(exec, ms));
+      IPDG_HIP(hipStreamSynchronize(ms));
+      for (int k = 0; k < na; ++k)
+        if (!runs[k].finished) sv[k]->copy_scal();
+      for (int k = 0; k < na; ++k) IPDG_HIP(hipStreamSynchronize(sv[k]->stream()));
+      left = 0;
+      for (int k = 0; k < na; ++k)
+        if (!runs[k].finished) left += !sv[k]->after_step(runs[k]);
+      // residual replacements were enqueued on the solves' own streams; the
+      // next graph launch must start after them
+      for (int k = 0; k < na; ++k) IPDG_HIP(hipStreamSynchronize(sv[k]->stream()));
+    }
+  } catch (...) {
+    cleanup();
+    throw;
+  }
+  cleanup();
+  ipdg_status worst = IPDG_OK;
+  for (int k = 0; k < na; ++k) {
+    ipdg_solve_info info{};
+    sv[k]->finish(runs[k], &info);
+    if (iters) iters[active[k]] = info.iters;
+    if (relres) relres[active[k]] = info.relres;
+    if (runs[k].status != IPDG_OK) worst = runs[k].status;
+  }
+  for (int i = 0; i < nb; ++i)
+    if (meshes[i]->host.K == 0) {
+      if (iters) iters[i] = 0;
+      if (relres) relres[i] = 0.0;
+    }
   return worst;
 }
 
