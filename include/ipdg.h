@@ -69,7 +69,9 @@ typedef struct {
   int flexible;            /* 1: flexible CG beta = -(z+, Ap)/(p, Ap);
                               -1: automatic (flexible for PMG or MIXED) */
   /* p-multigrid (pc == IPDG_PC_PMG): degrees[0] must equal the mesh degree,
-     strictly decreasing, last level solved by Jacobi-PCG. */
+     strictly decreasing, last level solved by Jacobi-PCG.  n_levels == 0
+     chooses the levels by halving the degree down to 1 (7, 3, 1 or
+     8, 4, 2, 1), also per mesh in a batch of mixed degrees. */
   int n_levels;
   int degrees[IPDG_MAX_LEVELS];
   int cheb_degree;         /* Chebyshev steps per smoothing (>= 1) */
@@ -82,6 +84,11 @@ typedef struct {
   int coarse_max_iters;    /* and iteration cap (tol 0 => exactly this many) */
   double reliable_drop;    /* mixed: recompute r = b - A64 x when |r| fell by
                               this factor since the last recompute */
+  int coarse_persistent;   /* 1: run the coarsest-level Jacobi-PCG as one
+                              persistent launch with grid-wide barriers
+                              (degrees 1..4, single solves only); 0 (default):
+                              one short kernel sequence per iteration inside
+                              the captured graph, converged iterations skipped */
 } ipdg_solve_opts;
 
 /* Result record of a solve (all fields written). */
@@ -143,8 +150,13 @@ ipdg_status ipdg_precond_apply(ipdg_mesh mesh, double lambda, double tau,
                                ipdg_solve_info* info, void* hip_stream);
 
 /* nb independent solves (lambda_i M - Lap) x_i = b_i, one mesh each (Sec. 3:
- * per-component velocity Helmholtz solves), advanced together.  iters and
- * relres are HOST arrays of nb entries (may be NULL). */
+ * per-component velocity Helmholtz solves), advanced together: one graph
+ * launch runs check_every iterations of every unfinished solve.  b and x are
+ * HOST arrays of nb device FP64 vector pointers; iters and relres are HOST
+ * arrays of nb entries (may be NULL).  Each mesh handle may appear once.
+ * With IPDG_PC_PMG the coarsest level runs as ordinary launches (never the
+ * persistent single-launch form, whose grids could not all be resident).
+ * Returns IPDG_NOT_CONVERGED if any solve stopped at max_iters. */
 ipdg_status ipdg_helmholtz_solve_batch(int nb, const ipdg_mesh* meshes, const double* lambdas,
                                        double tau, const double* const* b, double* const* x,
                                        double tol, const ipdg_solve_opts* opts, int* iters,

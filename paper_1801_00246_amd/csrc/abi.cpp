@@ -72,6 +72,7 @@ void ipdg_default_opts(ipdg_solve_opts* o) {
   o->coarse_tol = 1e-2;
   o->coarse_max_iters = 200;
   o->reliable_drop = 1e-3;
+  o->coarse_persistent = 0;
 }
 
 const char* ipdg_last_error(void) { return g_last_error.c_str(); }

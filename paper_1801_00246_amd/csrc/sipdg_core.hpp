@@ -159,7 +159,8 @@ __host__ __device__ __forceinline__ void sipdg_element_own(int e, const TX* __re
       jmp[f][k] = inner ? ji : (dir ? TC(-2) * um : TC(0));
       dnj[f][k] = inner ? di : (dir ? TC(0) : TC(-2) * ke * own);
     });
-    tau[f] = inner ? ctau * fmax(ke * Fs[f], kp * Fsp) : ctau * ke * Fs[f];
+    // branch-free: a boundary face takes the element's own side only
+    tau[f] = ctau * fmax(ke * Fs[f], TC(inner ? 1 : 0) * (kp * Fsp));
   });
 
   phase_fence();

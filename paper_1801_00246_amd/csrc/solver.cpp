@@ -132,9 +132,22 @@ double tridiag_max_eig(const std::vector<double>& a, const std::vector<double>& 
 
 class Solver {
  public:
-  Solver(ipdg_mesh_s* m, double lambda, double tau, const ipdg_solve_opts& o, hipStream_t s)
-      : m_(m), o_(o), s_(s) {
+  // persistent: the coarsest pMG level may run as one persistent launch
+  // (off when several solves share the device at once, since their grids
+  // would not all be resident together)
+  Solver(ipdg_mesh_s* m, double lambda, double tau, const ipdg_solve_opts& o, hipStream_t s,
+         bool persistent = true)
+      : m_(m), o_(o), s_(s), persistent_(persistent) {
     N_ = m->host.N;
+    if (o_.pc == IPDG_PC_PMG && o_.n_levels == 0) {
+      // automatic levels: halve the degree down to 1 (7 -> 3 -> 1, 8 -> 4 -> 2 -> 1)
+      int L = 0;
+      for (int d = N_; L < IPDG_MAX_LEVELS; d /= 2) {
+        o_.degrees[L++] = d;
+        if (d == 1) break;
+      }
+      o_.n_levels = L;
+    }
     K_ = m->host.K;
     n_ = (size_t)K_ * m->Np;
     lambda_ = lambda;
@@ -294,6 +307,8 @@ class Solver {
       if (o_.cheb_degree < 1) throw Error(IPDG_EINVAL, "cheb_degree < 1");
       if (!(o_.cheb_hi > o_.cheb_lo) || !(o_.cheb_lo > 0)) throw Error(IPDG_EINVAL, "bad Chebyshev interval");
       if (o_.coarse_max_iters < 0) throw Error(IPDG_EINVAL, "coarse_max_iters < 0");
+      if (o_.coarse_persistent != 0 && o_.coarse_persistent != 1)
+        throw Error(IPDG_EINVAL, "coarse_persistent must be 0 or 1");
     }
   }
 
@@ -316,7 +331,10 @@ class Solver {
 
   void setup() {
     Work& w = *w_;
-    if (same_setup()) return;
+    if (same_setup()) {
+      select_coarse();
+      return;
+    }
     const auto t0 = clk::now();
     w.drop_graph();
     w.lv.clear();
@@ -423,8 +441,21 @@ class Solver {
     IPDG_HIP(set_scal(w.cscal.as<CGScal>(), c, s_));
     w.cbar.ensure(8 * sizeof(int));
     IPDG_HIP(zero_ints(w.cbar.get(), 8, s_));
+    w.coarse_grid = -1;
+    select_coarse();
+  }
+
+  // persistent single-launch coarse solve or ordinary launches; a change
+  // invalidates the captured iteration graph
+  void select_coarse() {
+    Work& w = *w_;
+    if (o_.pc != IPDG_PC_PMG || w.lv.empty()) return;
     const Level& cl = w.lv.back();
-    w.coarse_grid = std::getenv("IPDG_NO_PERSISTENT") ? 0 : coarse_pcg_grid(cl.N, cl.kind, K_);
+    const int g = (persistent_ && o_.coarse_persistent == 1) ? coarse_pcg_grid(cl.N, cl.kind, K_) : 0;
+    if (g != w.coarse_grid) {
+      w.drop_graph();
+      w.coarse_grid = g;
+    }
   }
 
   // rho_steps Jacobi-PCG (Lanczos) steps on a level operator in FP64 from a
@@ -694,7 +725,13 @@ class Solver {
   // timeout, [2] breakdown
   int coarse_status() {
     Work& w = *w_;
-    if (o_.pc != IPDG_PC_PMG || w.coarse_grid == 0) return -1;
+    if (o_.pc != IPDG_PC_PMG || w.lv.empty()) return -1;
+    if (w.coarse_grid == 0) {
+      CGScal c{};
+      IPDG_HIP(hipMemcpyAsync(&c, w.cscal.get(), sizeof(c), hipMemcpyDeviceToHost, s_));
+      IPDG_HIP(hipStreamSynchronize(s_));
+      return c.iters;
+    }
     int st[3] = {0, 0, 0};
     IPDG_HIP(hipMemcpyAsync(st, w.cbar.as<int>() + 2, sizeof(st), hipMemcpyDeviceToHost, s_));
     IPDG_HIP(hipStreamSynchronize(s_));
@@ -720,6 +757,7 @@ class Solver {
   hipStream_t s_;
   hipStream_t user_ = nullptr;
   bool use_graph_ = true;
+  bool persistent_ = true;
   Work* w_ = nullptr;
   int N_ = 0, K_ = 0;
   size_t n_ = 0;
@@ -767,7 +805,7 @@ ipdg_status solve_batch(int nb, ipdg_mesh_s* const* meshes, const double* lambda
   std::vector<int> active;
   for (int i = 0; i < nb; ++i) {
     if (meshes[i]->host.K == 0) continue;
-    sv.emplace_back(new Solver(meshes[i], lambdas[i], tau, o, s));
+    sv.emplace_back(new Solver(meshes[i], lambdas[i], tau, o, s, /*persistent=*/false));
     active.push_back(i);
   }
   const int na = int(sv.size());

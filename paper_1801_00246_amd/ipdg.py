@@ -37,7 +37,7 @@ class SolveOpts(C.Structure):
                 ("cheb_lo", C.c_double), ("cheb_hi", C.c_double),
                 ("rho", C.c_double * MAX_LEVELS), ("rho_steps", C.c_int),
                 ("coarse_tol", C.c_double), ("coarse_max_iters", C.c_int),
-                ("reliable_drop", C.c_double)]
+                ("reliable_drop", C.c_double), ("coarse_persistent", C.c_int)]
 
 
 class SolveInfo(C.Structure):

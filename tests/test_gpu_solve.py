@@ -200,3 +200,61 @@ def test_batch_matches_individual_solves():
         assert true_relres(A, xh, bh) <= 1e-8
         xi, info, _ = meshes[i].pcg(b, lam=lams[i], tol=1e-8, opts=P.default_opts(pc=P.PC_BLOCK_MASS))
         assert np.linalg.norm(host(xi) - xh) <= 1e-12 * np.linalg.norm(xh)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_batch_pmg_auto_levels(prec):
+    """Batch of mixed degrees with p-multigrid on automatically halved levels
+    (the coarse levels run as ordinary launches inside the batch graph)."""
+    draws = [(10, 4, 1.0), (12, 7, 30.0), (8, 8, 1000.0), (14, 5, 3.0), (9, 6, 100.0)]
+    pr = P.PREC_FP64 if prec == "fp64" else P.PREC_MIXED
+    o = P.default_opts(pc=P.PC_PMG, prec=pr)
+    meshes, bs, As, lams = [], [], [], []
+    for i, (n, N, lam) in enumerate(draws):
+        msh = synth.square_mesh(n, jitter=0.15, seed=60 + i)
+        m = OracleMesh(msh.VX, msh.VY, msh.EToV, msh.EToB, N)
+        b = mass_apply(m, synth.nodal_normal(msh.K, m.Np, seed=50 + i))
+        As.append(assemble(m, lam, float((N + 1) ** 2)))
+        meshes.append(P.Mesh.from_synth(N, msh))
+        bs.append(dev(b))
+        lams.append(lam)
+    xs, iters, rel, st = P.solve_batch(meshes, lams, bs, tol=1e-8, opts=o)
+    assert st == 0
+    for i, (A, b, x) in enumerate(zip(As, bs, xs)):
+        xh = host(x)
+        assert true_relres(A, xh, host(b)) <= 1e-8
+        assert rel[i] <= 1e-8
+        # the same solve alone: the same preconditioner up to rounding
+        # (reduction order), so about the same count
+        _, info, _ = meshes[i].pcg(b, lam=lams[i], tol=1e-8, opts=o)
+        assert abs(info["iters"] - iters[i]) <= max(2, info["iters"] // 10)
+
+
+def test_pmg_auto_levels_halve_degree():
+    g_N = {7: [7, 3, 1], 8: [8, 4, 2, 1], 2: [2, 1], 1: [1]}
+    for N, levels in g_N.items():
+        msh = synth.square_mesh(6)
+        g = P.Mesh.from_synth(N, msh)
+        b = dev(np.ones(msh.K * g.Np))
+        _, info, st = g.pcg(b, tol=1e-8, opts=P.default_opts(pc=P.PC_PMG))
+        assert st == 0
+        used = [r for r in info["rho_used"] if r > 0]
+        assert len(used) == len(levels)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_persistent_coarse_solve_matches_kernel_sequence(prec):
+    """The single-launch coarsest-level solve (grid barriers) and the kernel
+    sequence compute the same Jacobi-PCG; the outer solves agree."""
+    msh, m, A, b, _ = problem(n=24, N=5, lam=2.0, jitter=0.1, seed=8)
+    g = P.Mesh.from_synth(5, msh)
+    pr = P.PREC_FP64 if prec == "fp64" else P.PREC_MIXED
+    res = []
+    for pers in (0, 1):
+        o = P.default_opts(pc=P.PC_PMG, prec=pr, degrees=[5, 2, 1], coarse_persistent=pers)
+        x, info, st = g.pcg(dev(b), lam=2.0, tol=1e-9, opts=o)
+        assert st == 0
+        assert true_relres(A, host(x), b) <= 1e-9
+        assert info["coarse_iters"] > 0
+        res.append(info)
+    assert abs(res[0]["iters"] - res[1]["iters"]) <= 1
