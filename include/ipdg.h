@@ -62,8 +62,10 @@ typedef enum { IPDG_PREC_FP64 = 0, IPDG_PREC_MIXED = 1 } ipdg_prec;
 /* Options of the PCG solvers.  ipdg_default_opts() fills every field. */
 typedef struct {
   ipdg_pc pc;              /* preconditioner */
-  ipdg_prec prec;          /* FP64 throughout, or FP32 operator/preconditioner
-                              inside FP64 CG recurrences, dots and residuals */
+  ipdg_prec prec;          /* FP64 throughout, or an FP32 preconditioner (its
+                              operator applications, smoothing, transfers and
+                              coarse solve) inside FP64 CG: the outer operator,
+                              recurrences, dots and residuals stay FP64 */
   int max_iters;           /* outer iteration limit */
   int check_every;         /* host polls convergence every this many iterations */
   int flexible;            /* 1: flexible CG beta = -(z+, Ap)/(p, Ap);
@@ -82,8 +84,9 @@ typedef struct {
   int rho_steps;
   double coarse_tol;       /* coarsest Jacobi-PCG relative tolerance */
   int coarse_max_iters;    /* and iteration cap (tol 0 => exactly this many) */
-  double reliable_drop;    /* mixed: recompute r = b - A64 x when |r| fell by
-                              this factor since the last recompute */
+  double reliable_drop;    /* > 0: also recompute r = b - A x in FP64 whenever
+                              |r| fell by this factor since the last recompute
+                              (default 0: only when the recurrence stops) */
   int coarse_persistent;   /* 1: run the coarsest-level Jacobi-PCG as one
                               persistent launch with grid-wide barriers
                               (degrees 1..4, single solves only); 0 (default):

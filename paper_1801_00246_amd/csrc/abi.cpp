@@ -71,7 +71,7 @@ void ipdg_default_opts(ipdg_solve_opts* o) {
   o->rho_steps = 20;
   o->coarse_tol = 1e-2;
   o->coarse_max_iters = 200;
-  o->reliable_drop = 1e-3;
+  o->reliable_drop = 0.0;
   o->coarse_persistent = 0;
 }
 

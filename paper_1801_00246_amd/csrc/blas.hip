@@ -43,7 +43,7 @@ __global__ __launch_bounds__(kBlock) void k_residual(const double* __restrict__ 
 template <typename TZ, bool JAC>
 __global__ __launch_bounds__(kBlock) void k_update(double* __restrict__ x, double* __restrict__ r,
                                                    const double* __restrict__ p,
-                                                   const TZ* __restrict__ Ap,
+                                                   const double* __restrict__ Ap,
                                                    const double* __restrict__ dinv,
                                                    TZ* __restrict__ z, const CGScal* __restrict__ sc,
                                                    size_t n, double* __restrict__ partials) {
@@ -51,7 +51,7 @@ __global__ __launch_bounds__(kBlock) void k_update(double* __restrict__ x, doubl
   const double alpha = sc->alpha;
   double v[3] = {0.0, 0.0, 0.0};
   for (size_t i = blockIdx.x * (size_t)kBlock + threadIdx.x; i < n; i += (size_t)gridDim.x * kBlock) {
-    const double api = ldd(Ap, i);
+    const double api = Ap[i];
     x[i] += alpha * p[i];
     const double ri = r[i] - alpha * api;
     r[i] = ri;
@@ -70,7 +70,7 @@ __global__ __launch_bounds__(kBlock) void k_update(double* __restrict__ x, doubl
 template <typename TZ>
 __global__ __launch_bounds__(kBlock) void k_dots_rz(const double* __restrict__ r,
                                                     const TZ* __restrict__ z,
-                                                    const TZ* __restrict__ Ap,
+                                                    const double* __restrict__ Ap,
                                                     const CGScal* __restrict__ sc, size_t n,
                                                     double* __restrict__ partials) {
   if (sc->done) return;
@@ -78,7 +78,7 @@ __global__ __launch_bounds__(kBlock) void k_dots_rz(const double* __restrict__ r
   for (size_t i = blockIdx.x * (size_t)kBlock + threadIdx.x; i < n; i += (size_t)gridDim.x * kBlock) {
     const double zi = ldd(z, i);
     v[0] += r[i] * zi;
-    if (Ap) v[1] += zi * ldd(Ap, i);
+    if (Ap) v[1] += zi * Ap[i];
   }
   block_sum<2>(v);
   if (threadIdx.x == 0) {
@@ -244,14 +244,17 @@ __global__ void k_cg_start_fin(const double* __restrict__ partials, int nparts, 
     __syncthreads();
   }
   if (threadIdx.x != 0) return;
-  const bool outer_done = skip && *skip;
+  if (skip && *skip) {     // outer solve finished: keep the last solve's record
+    sc->done = 1;
+    return;
+  }
   sc->rr = red[0][0];
   sc->bb = red[0][0];
   sc->rz = red[1][0];
   sc->tol2 = sc->tol * sc->tol * sc->rr;
   sc->iters = 0;
   sc->breakdown = 0;
-  sc->done = outer_done || sc->rr == 0.0 || sc->max_iters <= 0;
+  sc->done = sc->rr == 0.0 || sc->max_iters <= 0;
 }
 
 // single-precision-state coarse CG update: x += a p; r -= a Ap; z = dinv r;
@@ -318,23 +321,23 @@ hipError_t residual(const double* b, const double* Ax, double* r, size_t n, doub
   return hipGetLastError();
 }
 
-hipError_t cg_update(bool fp32z, bool jacobi, double* x, double* r, const double* p, const void* Ap,
+hipError_t cg_update(bool fp32z, bool jacobi, double* x, double* r, const double* p, const double* Ap,
                      const double* dinv, void* z, const CGScal* sc, size_t n, double* partials,
                      hipStream_t s) {
   if (fp32z) {
-    if (jacobi) LAUNCH((k_update<float, true>), n, s, x, r, p, (const float*)Ap, dinv, (float*)z, sc, n, partials);
-    else LAUNCH((k_update<float, false>), n, s, x, r, p, (const float*)Ap, dinv, (float*)z, sc, n, partials);
+    if (jacobi) LAUNCH((k_update<float, true>), n, s, x, r, p, Ap, dinv, (float*)z, sc, n, partials);
+    else LAUNCH((k_update<float, false>), n, s, x, r, p, Ap, dinv, (float*)z, sc, n, partials);
   } else {
-    if (jacobi) LAUNCH((k_update<double, true>), n, s, x, r, p, (const double*)Ap, dinv, (double*)z, sc, n, partials);
-    else LAUNCH((k_update<double, false>), n, s, x, r, p, (const double*)Ap, dinv, (double*)z, sc, n, partials);
+    if (jacobi) LAUNCH((k_update<double, true>), n, s, x, r, p, Ap, dinv, (double*)z, sc, n, partials);
+    else LAUNCH((k_update<double, false>), n, s, x, r, p, Ap, dinv, (double*)z, sc, n, partials);
   }
   return hipGetLastError();
 }
 
-hipError_t dots_rz(bool fp32z, const double* r, const void* z, const void* Ap, const CGScal* sc, size_t n,
+hipError_t dots_rz(bool fp32z, const double* r, const void* z, const double* Ap, const CGScal* sc, size_t n,
                    double* partials, hipStream_t s) {
-  if (fp32z) LAUNCH(k_dots_rz<float>, n, s, r, (const float*)z, (const float*)Ap, sc, n, partials);
-  else LAUNCH(k_dots_rz<double>, n, s, r, (const double*)z, (const double*)Ap, sc, n, partials);
+  if (fp32z) LAUNCH(k_dots_rz<float>, n, s, r, (const float*)z, Ap, sc, n, partials);
+  else LAUNCH(k_dots_rz<double>, n, s, r, (const double*)z, Ap, sc, n, partials);
   return hipGetLastError();
 }
 

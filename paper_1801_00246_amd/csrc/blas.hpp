@@ -20,10 +20,10 @@ enum FinOp { kFinResidual = 0, kFinInit = 1, kFinAlpha = 2, kFinBeta = 3, kFinRh
 int flat_grid(size_t n);
 
 hipError_t residual(const double* b, const double* Ax, double* r, size_t n, double* partials, hipStream_t s);
-hipError_t cg_update(bool fp32z, bool jacobi, double* x, double* r, const double* p, const void* Ap,
+hipError_t cg_update(bool fp32z, bool jacobi, double* x, double* r, const double* p, const double* Ap,
                      const double* dinv, void* z, const CGScal* sc, size_t n, double* partials,
                      hipStream_t s);
-hipError_t dots_rz(bool fp32z, const double* r, const void* z, const void* Ap, const CGScal* sc, size_t n,
+hipError_t dots_rz(bool fp32z, const double* r, const void* z, const double* Ap, const CGScal* sc, size_t n,
                    double* partials, hipStream_t s);
 hipError_t pupdate(bool fp32z, double* p, const void* z, const CGScal* sc, size_t n, hipStream_t s);
 hipError_t jacobi(bool fp32z, const double* r, const double* dinv, void* z, size_t n, hipStream_t s);

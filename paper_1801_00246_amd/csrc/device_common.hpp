@@ -30,6 +30,7 @@ inline int xcd_grid(int ntiles, int& per) {
   return per * kXcd;
 }
 
+#ifdef __HIPCC__
 // Sum of v over the block, valid in thread 0.  Fixed reduction order, so the
 // result is bitwise reproducible for a given launch shape.
 template <int NV>
@@ -57,5 +58,6 @@ __device__ __forceinline__ void block_sum(double (&v)[NV]) {
     }
   }
 }
+#endif  // __HIPCC__
 
 }  // namespace ipdg

@@ -7,8 +7,10 @@
 namespace ipdg {
 
 namespace {
-// default: staged for the bandwidth-bound degrees
-std::atomic<int> g_variant[2][9] = {{0, 1, 1, 1, 1, 0, 0, 0, 0}, {0, 1, 1, 1, 1, 0, 0, 0, 0}};
+// Operator kernel variant per precision (FP64, FP32) and degree; bits:
+// 1 = LDS-staged inputs/outputs, 2 = raised occupancy (degrees <= 5).
+// Defaults from measured sweeps of the 524,288-element operator workload.
+std::atomic<int> g_variant[2][9] = {{0, 0, 0, 0, 0, 0, 0, 0, 0}, {0, 2, 2, 0, 0, 1, 0, 0, 0}};
 bool env_read = false;
 }  // namespace
 

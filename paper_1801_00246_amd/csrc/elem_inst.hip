@@ -19,13 +19,14 @@ constexpr int N = IPDG_N;
 constexpr int kMaxPartialsCoarse = 4096;
 constexpr int Np = Tri<N>::Np;
 
-// Minimum waves per SIMD the register allocator must leave room for: the
-// operator kernel holds one element per lane, so its footprint grows with
-// Np; FP32 halves it.
+// Occupancy-raised variant: waves per SIMD the register allocator must leave
+// room for (one more than the unconstrained allocation gives; 0 = none).
+// The operator kernel holds one element per lane, so its footprint grows
+// with Np; FP32 halves it.
 template <typename TC>
-constexpr int ax_waves() {
-  if constexpr (sizeof(TC) == 8) return N <= 2 ? 4 : (N <= 4 ? 3 : (N <= 6 ? 2 : 1));
-  else return N <= 2 ? 8 : (N <= 4 ? 5 : (N <= 6 ? 3 : 2));
+constexpr int ax_boost_waves() {
+  if constexpr (sizeof(TC) == 8) return N <= 2 ? 5 : (N <= 4 ? 4 : 3);
+  else return N <= 1 ? 0 : (N <= 2 ? 8 : (N <= 3 ? 7 : (N <= 4 ? 6 : 5)));
 }
 
 // LDS pitch (elements) of the staging buffer: odd in 8-byte words, so that
@@ -35,8 +36,9 @@ constexpr int kPitch = kBlock + 1;
 // STAGE: the block's own inputs and outputs go through LDS, so that global
 // loads and stores are fully coalesced (lane t touches word t of the block's
 // contiguous chunk) instead of Np-strided per lane.
-template <typename TC, typename TX, typename TY, bool KAP, bool STAGE>
-__global__ __launch_bounds__(kBlock) void k_ax(const TX* __restrict__ x, TY* __restrict__ y,
+template <typename TC, typename TX, typename TY, bool KAP, bool STAGE, int WAVES>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WAVES > 0 ? WAVES : 1)))
+void k_ax(const TX* __restrict__ x, TY* __restrict__ y,
                                                const TC* __restrict__ geo,
                                                const Conn* __restrict__ conn,
                                                const TC* __restrict__ kap,
@@ -385,6 +387,7 @@ __global__ __launch_bounds__(kBlock) void k_coarse_pcg(const T* __restrict__ f, 
                                                        int* __restrict__ status,
                                                        const int* __restrict__ skip) {
   if (skip && *skip) return;          // the same flag value for every block
+  if (blockIdx.x == 0 && threadIdx.x == 0) status[2] = 0;
   constexpr int Np = Tri<NN>::Np;
   const int G = gridDim.x;
   const size_t n = (size_t)K * Np;
@@ -503,9 +506,9 @@ int resident_grid(int K) {
 // degrees whose operator kernel is built with the LDS-staged variant too
 constexpr bool kHasStage = N <= 5;
 
-template <typename TC, typename TX, typename TY, bool KAP, bool STAGE>
+template <typename TC, typename TX, typename TY, bool KAP, bool STAGE, int WAVES>
 void launch_ax_variant(const ElemArgs& a, int grid, int per, hipStream_t s) {
-  hipLaunchKernelGGL((k_ax<TC, TX, TY, KAP, STAGE>), dim3(grid), dim3(kBlock), 0, s,
+  hipLaunchKernelGGL((k_ax<TC, TX, TY, KAP, STAGE, WAVES>), dim3(grid), dim3(kBlock), 0, s,
                      static_cast<const TX*>(a.x), static_cast<TY*>(a.y),
                      static_cast<const TC*>(a.geo), a.conn, static_cast<const TC*>(a.kap),
                      static_cast<const TC*>(a.ops), TC(a.lambda), TC(a.ctau), a.K, per, a.partials,
@@ -517,16 +520,29 @@ hipError_t run_ax(const ElemArgs& a, hipStream_t s) {
   int per;
   const int grid = xcd_grid(elem_tiles(a.K), per);
   if (a.K == 0) return hipSuccess;
-  const bool stage = kHasStage && ax_variant(N, sizeof(TC) == 4) == 1;
+  // variant bits: 1 = LDS-staged inputs/outputs, 2 = raised occupancy
+  const int v = ax_variant(N, sizeof(TC) == 4);
+  constexpr int W = ax_boost_waves<TC>();
   if constexpr (kHasStage) {
-    if (stage) {
-      if (a.kap) launch_ax_variant<TC, TX, TY, true, true>(a, grid, per, s);
-      else launch_ax_variant<TC, TX, TY, false, true>(a, grid, per, s);
-      return hipGetLastError();
+    switch (v & 3) {
+      case 1:
+        if (a.kap) launch_ax_variant<TC, TX, TY, true, true, 0>(a, grid, per, s);
+        else launch_ax_variant<TC, TX, TY, false, true, 0>(a, grid, per, s);
+        return hipGetLastError();
+      case 2:
+        if (a.kap) launch_ax_variant<TC, TX, TY, true, false, W>(a, grid, per, s);
+        else launch_ax_variant<TC, TX, TY, false, false, W>(a, grid, per, s);
+        return hipGetLastError();
+      case 3:
+        if (a.kap) launch_ax_variant<TC, TX, TY, true, true, W>(a, grid, per, s);
+        else launch_ax_variant<TC, TX, TY, false, true, W>(a, grid, per, s);
+        return hipGetLastError();
+      default:
+        break;
     }
   }
-  if (a.kap) launch_ax_variant<TC, TX, TY, true, false>(a, grid, per, s);
-  else launch_ax_variant<TC, TX, TY, false, false>(a, grid, per, s);
+  if (a.kap) launch_ax_variant<TC, TX, TY, true, false, 0>(a, grid, per, s);
+  else launch_ax_variant<TC, TX, TY, false, false, 0>(a, grid, per, s);
   return hipGetLastError();
 }
 
@@ -606,7 +622,7 @@ hipError_t launch_ax<N>(Kind kind, const ElemArgs& a, hipStream_t s) {
   switch (kind) {
     case Kind::F64: return run_ax<double, double, double>(a, s);
     case Kind::F32: return run_ax<float, float, float>(a, s);
-    case Kind::F32_IN64: return run_ax<float, double, float>(a, s);
+    case Kind::F32_IN64: break;   // not used: operators read their own precision
   }
   return hipErrorInvalidValue;
 }

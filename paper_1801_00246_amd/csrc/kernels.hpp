@@ -9,7 +9,8 @@ namespace ipdg {
 // Compute / storage precision combinations of the element kernels.
 //   F64      : FP64 arithmetic, FP64 in, FP64 out
 //   F32      : FP32 arithmetic, FP32 in, FP32 out
-//   F32_IN64 : FP32 arithmetic, FP64 in, FP32 out (mixed-precision outer CG)
+//   F32_IN64 : FP32 arithmetic, FP64 in, FP32 out (block inverse mass applied
+//              to the FP64 residual in mixed precision; not an operator kind)
 enum class Kind { F64 = 0, F32 = 1, F32_IN64 = 2 };
 
 // Type-erased arguments; geo/kap/ops are in the arithmetic precision.
@@ -32,9 +33,10 @@ inline int elem_grid(int K) {
   return xcd_grid(elem_tiles(K), per);
 }
 
-// Operator kernel variant per (degree, precision): 0 = direct per-lane
-// loads/stores, 1 = LDS-staged coalesced loads/stores (degrees <= 5).
-// Set by set_ax_variant (autotuner or IPDG_AX_VARIANT), default table below.
+// Operator kernel variant per (degree, precision), degrees <= 5: bit 1 =
+// LDS-staged coalesced loads/stores instead of direct per-lane ones, bit 2 =
+// register budget lowered for one more resident wave per SIMD.  Set by
+// set_ax_variant or IPDG_AX_VARIANT; defaults in dispatch.cpp.
 int ax_variant(int N, bool fp32);
 void set_ax_variant(int N, bool fp32, int v);
 

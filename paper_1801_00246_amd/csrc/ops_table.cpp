@@ -38,11 +38,10 @@ std::vector<double> build_ops_table(int N) {
   put(QS);
   put(R.LIFT);
   put(R.M1D);
-  for (int f = 0; f < 3; ++f)
-    for (int j = 0; j < Np; ++j) {
-      for (int m = 0; m < Nfp; ++m) t.push_back(R.Dr[m * Np + j]);
-      for (int m = 0; m < Nfp; ++m) t.push_back(R.Ds[m * Np + j]);
-    }
+  for (int j = 0; j < Np; ++j) {
+    for (int m = 0; m < Nfp; ++m) t.push_back(R.Dr[m * Np + j]);
+    for (int m = 0; m < Nfp; ++m) t.push_back(R.Ds[m * Np + j]);
+  }
   std::vector<double> E = mul(R.M, R.LIFT, Np, Np, 3 * Nfp);
   for (int i = 0; i < Np; ++i) {
     auto row = [&](const std::vector<double>& A, int n) {

@@ -94,7 +94,7 @@ __host__ __device__ __forceinline__ void sipdg_element_own(int e, const TX* __re
 
   const TC gx[3] = {-sx, rx + sx, -rx};
   const TC gy[3] = {-sy, ry + sy, -ry};
-  TC Fs[3], tau[3];
+  TC Fs[3], iFs[3], tau[3];
   TC jmp[3][Nfp], dnj[3][Nfp];
 
   static_for<0, 3>([&](auto fc) {
@@ -102,8 +102,8 @@ __host__ __device__ __forceinline__ void sipdg_element_own(int e, const TX* __re
     phase_fence();
     const TC* __restrict__ opf = ops + opaque_zero();
     Fs[f] = sqrt(gx[f] * gx[f] + gy[f] * gy[f]);
-    const TC inv = TC(1) / Fs[f];
-    const TC nx = gx[f] * inv, ny = gy[f] * inv;
+    iFs[f] = TC(1) / Fs[f];
+    const TC nx = gx[f] * iFs[f], ny = gy[f] * iFs[f];
     const TC nr = nx * rx + ny * ry, ns = nx * sx + ny * sy;
     const int bc = conn_bc(c.info, f);
     const int nb = c.nb[f];
@@ -136,8 +136,8 @@ __host__ __device__ __forceinline__ void sipdg_element_own(int e, const TX* __re
         if constexpr (j < Nfp) pv[j] = v;   // face-0 nodes are ids 0..N
 #pragma unroll
         for (int m = 0; m < Nfp; ++m) {
-          pr[m] += opf[L::NBR + ((f * Np + j) * 2 + 0) * Nfp + m] * v;
-          ps[m] += opf[L::NBR + ((f * Np + j) * 2 + 1) * Nfp + m] * v;
+          pr[m] += opf[L::NBR + (j * 2 + 0) * Nfp + m] * v;
+          ps[m] += opf[L::NBR + (j * 2 + 1) * Nfp + m] * v;
         }
       });
     }
@@ -170,7 +170,7 @@ __host__ __device__ __forceinline__ void sipdg_element_own(int e, const TX* __re
     constexpr int f2 = decltype(f2c)::value;
     TC cn[3];
 #pragma unroll
-    for (int f = 0; f < 3; ++f) cn[f] = TC(0.5) * (gx[f2] * gx[f] + gy[f2] * gy[f]) / Fs[f2];
+    for (int f = 0; f < 3; ++f) cn[f] = TC(0.5) * (gx[f2] * gx[f] + gy[f2] * gy[f]) * iFs[f2];
     static_for<0, Nfp>([&](auto pc) {
       constexpr int p = decltype(pc)::value;
       constexpr int i = G::fm(f2, p);

@@ -10,10 +10,11 @@
 //   p = z + beta p
 // The host reads the scalars every check_every iterations.  A stop is
 // accepted only on the true FP64 residual b - A x; otherwise the recurrence
-// restarts from it (residual replacement).  In mixed precision the outer
-// operator and the preconditioner run in FP32 while x, r, p, the dots and the
-// true residual stay in FP64, and the residual is also replaced whenever
-// ||r|| fell by reliable_drop since the last replacement.
+// restarts from it (residual replacement).  In mixed precision the
+// preconditioner runs in FP32 while the outer operator, x, r, p, the dots and
+// the true residual stay in FP64; optionally (reliable_drop > 0) the residual
+// is also replaced whenever ||r|| fell by that factor since the last
+// replacement.
 //
 // p-multigrid (Sec. 3, the degree-coarsening part of pMG-AMG): levels of
 // degree N_0 > N_1 > ... rediscretise the operator with penalty constant
@@ -234,7 +235,7 @@ class Solver {
       mark_done();
       return R.finished = true;
     }
-    const double drop2 = mixed_ ? o_.reliable_drop * o_.reliable_drop : 0.0;
+    const double drop2 = o_.reliable_drop * o_.reliable_drop;
     const bool stopped = h.done != 0;
     const bool replace = stopped || (drop2 > 0.0 && h.rr <= drop2 * R.rr_ref);
     if (!replace) return false;
@@ -343,7 +344,7 @@ class Solver {
     w.r.ensure(n_ * 8);
     w.p.ensure(n_ * 8);
     w.t64.ensure(n_ * 8);
-    w.Ap.ensure(n_ * (mixed_ ? 4 : 8));
+    w.Ap.ensure(n_ * 8);
     w.z.ensure(n_ * (mixed_ ? 4 : 8));
     w.partials.ensure(3 * kMaxPartials * sizeof(double));
     w.cpartials.ensure(3 * kMaxPartials * sizeof(double));
@@ -630,8 +631,10 @@ class Solver {
   void coarse_solve(Level& v, const void* f, void* x) {
     Work& w = *w_;
     if (w.coarse_grid > 0) {
-      // one persistent launch (barrier counters reset by a kernel node)
-      IPDG_HIP(zero_ints(w.cbar.get(), 5, s_));
+      // one persistent launch; a kernel node resets the two barrier counters
+      // (the status words keep the last executed solve's record, since the
+      // launch is a no-op once the outer solve is done)
+      IPDG_HIP(zero_ints(w.cbar.get(), 2, s_));
       CoarseArgs ca;
       ca.f = f;
       ca.x = x;
@@ -702,20 +705,23 @@ class Solver {
   void iteration(double* x) {
     Work& w = *w_;
     CGScal* sc = w.scal.as<CGScal>();
-    const Kind ka = mixed_ ? Kind::F32_IN64 : Kind::F64;
-    ElemArgs a = elem_args(m_, N_, ka, lambda_, ctau_);
+    // the outer operator is FP64 also in mixed precision: an FP32 product
+    // A p loses relative accuracy ~ u32 cond(A) on the smooth directions late
+    // CG builds, which stalls the recurrence; FP32 stays inside the
+    // preconditioner, where its error only perturbs a flexible preconditioner
+    ElemArgs a = elem_args(m_, N_, Kind::F64, lambda_, ctau_);
     a.x = w.p.get();
     a.y = w.Ap.get();
     a.partials = w.partials.as<double>();
     a.skip = outer_done();
-    IPDG_HIP(ax(N_, ka, a, s_));
+    IPDG_HIP(ax(N_, Kind::F64, a, s_));
     IPDG_HIP(finalize(w.partials.as<double>(), elem_grid(K_), 1, sc, kFinAlpha, s_));
     const bool jac = o_.pc == IPDG_PC_JACOBI || o_.pc == IPDG_PC_NONE;
-    IPDG_HIP(cg_update(mixed_, jac, x, w.r.as<double>(), w.p.as<double>(), w.Ap.get(), w.dinv64.as<double>(),
+    IPDG_HIP(cg_update(mixed_, jac, x, w.r.as<double>(), w.p.as<double>(), w.Ap.as<double>(), w.dinv64.as<double>(),
                        w.z.get(), sc, n_, w.partials.as<double>(), s_));
     if (!jac) {
       precond();
-      IPDG_HIP(dots_rz(mixed_, w.r.as<double>(), w.z.get(), w.Ap.get(), sc, n_, w.partials.as<double>(), s_));
+      IPDG_HIP(dots_rz(mixed_, w.r.as<double>(), w.z.get(), w.Ap.as<double>(), sc, n_, w.partials.as<double>(), s_));
     }
     IPDG_HIP(finalize(w.partials.as<double>(), flat_grid(n_), 3, sc, kFinBeta, s_));
     IPDG_HIP(pupdate(mixed_, w.p.as<double>(), w.z.get(), sc, n_, s_));

@@ -65,11 +65,9 @@ struct Tri {
 //   M, Minv          mass matrix and its inverse
 //   LIFT             M^{-1} E  (Np x 3 Nfp)
 //   M1D              face mass on [-1, 1]
-//   NBR              [f][j][d][m]: entry (m, j) of D_r (d = 0) or D_s
-//                    (d = 1) for the face-0 rows m = 0..N, stored column by
-//                    column (the neighbour phase streams over j) and once per
-//                    face so that the three neighbour phases read distinct
-//                    addresses
+//   NBR              [j][d][m]: entry (m, j) of D_r (d = 0) or D_s (d = 1)
+//                    for the face-0 rows m = 0..N, stored column by column
+//                    (the neighbour phase streams over j)
 template <int N>
 struct OpsLayout {
   static constexpr int Np = Tri<N>::Np, Nfp = Tri<N>::Nfp;
@@ -89,13 +87,13 @@ struct OpsLayout {
   //   Krr_i | Krs_i | Kss_i (Np each) | QR_i | QS_i | E_i (3 Nfp each) | M_i
   // with E = M LIFT (the face mass scattered to face-node rows).
   static constexpr int RowLen = 4 * Np + 9 * Nfp;
-  static constexpr int ROW = NBR + 3 * 2 * Nfp * Np;
+  static constexpr int ROW = NBR + 2 * Nfp * Np;
   static constexpr int total = ROW + Np * RowLen;
 };
 
 inline int ops_total(int N) {
   const int Np = (N + 1) * (N + 2) / 2, Nfp = N + 1;
-  return 7 * Np * Np + 3 * Np * 3 * Nfp + Nfp * Nfp + 6 * Nfp * Np + Np * (4 * Np + 9 * Nfp);
+  return 7 * Np * Np + 3 * Np * 3 * Nfp + Nfp * Nfp + 2 * Nfp * Np + Np * (4 * Np + 9 * Nfp);
 }
 
 }  // namespace ipdg

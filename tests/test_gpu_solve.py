@@ -258,3 +258,24 @@ def test_persistent_coarse_solve_matches_kernel_sequence(prec):
         assert info["coarse_iters"] > 0
         res.append(info)
     assert abs(res[0]["iters"] - res[1]["iters"]) <= 1
+
+
+@pytest.mark.parametrize("pc", ["jacobi", "pmg"])
+def test_mixed_precision_keeps_the_fp64_iteration_count(pc):
+    """With the FP32 preconditioner inside FP64 CG the outer convergence is
+    that of the FP64 solve (a few iterations more at most), with and without
+    residual replacement."""
+    msh, m, A, b, ctau = problem(24, 6, jitter=0.2, seed=11)
+    g = P.Mesh.from_synth(6, msh)
+    kw = dict(pc=P.PC_PMG, degrees=[6, 3, 1]) if pc == "pmg" else dict(pc=P.PC_JACOBI)
+    its = {}
+    for prec, drop in ((P.PREC_FP64, 0.0), (P.PREC_MIXED, 0.0), (P.PREC_MIXED, 1e-3)):
+        o = P.default_opts(prec=prec, reliable_drop=drop, flexible=1, **kw)
+        x, info, st = g.pcg(dev(b), tol=1e-9, tau=ctau, opts=o)
+        assert st == 0
+        assert true_relres(A, host(x), b) <= 1e-9
+        its[(prec, drop)] = info["iters"]
+    print(f"{pc}: iterations {its}")
+    base = its[(P.PREC_FP64, 0.0)]
+    for k, v in its.items():
+        assert v <= base + max(3, base // 20), k
