@@ -251,6 +251,7 @@ __global__ void k_cg_start_fin(const double* __restrict__ partials, int nparts, 
   sc->rr = red[0][0];
   sc->bb = red[0][0];
   sc->rz = red[1][0];
+  sc->rzb[0] = red[1][0];
   sc->tol2 = sc->tol * sc->tol * sc->rr;
   sc->iters = 0;
   sc->breakdown = 0;
@@ -291,6 +292,83 @@ __global__ __launch_bounds__(kBlock) void k_cg_pupdate(T* __restrict__ p, const 
 }
 
 // reciprocal of the diagonal (in place) and an optional FP32 copy
+// Sum of slot `slot` of the partials over nparts entries, returned to every
+// thread of the block; every block that calls it gets the same value (same
+// order), so all blocks take the same decisions from it.
+__device__ double block_total(const double* __restrict__ partials, int slot, int nparts) {
+  __shared__ double tot;
+  double v[1] = {0.0};
+  for (int i = threadIdx.x; i < nparts; i += kBlock) v[0] += partials[slot * kMaxPartials + i];
+  block_sum<1>(v);
+  if (threadIdx.x == 0) tot = v[0];
+  __syncthreads();
+  const double t = tot;
+  __syncthreads();
+  return t;
+}
+
+// Coarse Jacobi-PCG step without a finalize launch: every block reduces the
+// (p, Ap) partials of the operator launch itself, alpha = rz / (p, Ap);
+// x += alpha p; r -= alpha Ap; z = dinv r; partials (r, r), (r, z) in
+// slots 1, 2.  rz of iteration `par` parity is sc->rzb[par].
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_cg_update_red(T* __restrict__ x, T* __restrict__ r,
+                                                          const T* __restrict__ p, const T* __restrict__ Ap,
+                                                          const T* __restrict__ dinv, T* __restrict__ z,
+                                                          CGScal* __restrict__ sc, size_t n,
+                                                          double* __restrict__ partials, int nAp, int par) {
+  if (sc->done) return;
+  const double pAp = block_total(partials, 0, nAp);
+  if (!(pAp > 0.0) || !isfinite(pAp)) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      sc->breakdown = 1;
+      sc->done = 1;
+    }
+    return;
+  }
+  const T alpha = static_cast<T>(sc->rzb[par] / pAp);
+  double v[2] = {0.0, 0.0};
+  for (size_t i = blockIdx.x * (size_t)kBlock + threadIdx.x; i < n; i += (size_t)gridDim.x * kBlock) {
+    x[i] += alpha * p[i];
+    const T ri = r[i] - alpha * Ap[i];
+    r[i] = ri;
+    const T zi = dinv[i] * ri;
+    z[i] = zi;
+    v[0] += double(ri) * double(ri);
+    v[1] += double(ri) * double(zi);
+  }
+  block_sum<2>(v);
+  if (threadIdx.x == 0) {
+    partials[1 * kMaxPartials + blockIdx.x] = v[0];
+    partials[2 * kMaxPartials + blockIdx.x] = v[1];
+  }
+}
+
+// ... then every block reduces (r, r), (r, z): stop at rr <= tol2 or at
+// iteration `it` + 1 == max_iters, else beta = rz_new / rz and
+// p = z + beta p.  Block 0 records the iteration count, the stop and
+// rz_new in sc->rzb[1 - par] (other blocks read only sc->rzb[par]).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_cg_pupdate_red(T* __restrict__ p, const T* __restrict__ z,
+                                                           CGScal* __restrict__ sc, size_t n,
+                                                           const double* __restrict__ partials, int nparts,
+                                                           int it, int par) {
+  if (sc->done) return;
+  const double rr = block_total(partials, 1, nparts);
+  const double rz = block_total(partials, 2, nparts);
+  const bool stop = rr <= sc->tol2 || it + 1 >= sc->max_iters || !isfinite(rr);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    sc->iters = it + 1;
+    sc->rr = rr;
+    sc->rzb[1 - par] = rz;
+    if (stop) sc->done = 1;
+  }
+  if (stop) return;
+  const T beta = static_cast<T>(rz / sc->rzb[par]);
+  for (size_t i = blockIdx.x * (size_t)kBlock + threadIdx.x; i < n; i += (size_t)gridDim.x * kBlock)
+    p[i] = z[i] + beta * p[i];
+}
+
 __global__ __launch_bounds__(kBlock) void k_recip(double* __restrict__ d, float* __restrict__ d32, size_t n) {
   for (size_t i = blockIdx.x * (size_t)kBlock + threadIdx.x; i < n; i += (size_t)gridDim.x * kBlock) {
     const double v = 1.0 / d[i];
@@ -407,6 +485,37 @@ hipError_t cg_update_state(bool fp32, void* x, void* r, const void* p, const voi
 hipError_t cg_pupdate_state(bool fp32, void* p, const void* z, const CGScal* sc, size_t n, hipStream_t s) {
   if (fp32) LAUNCH(k_cg_pupdate<float>, n, s, (float*)p, (const float*)z, sc, n);
   else LAUNCH(k_cg_pupdate<double>, n, s, (double*)p, (const double*)z, sc, n);
+  return hipGetLastError();
+}
+
+int coarse_vec_grid(size_t n) {
+  const int b = flat_grid(n);
+  return b > kCoarseVecBlocks ? kCoarseVecBlocks : b;
+}
+
+hipError_t cg_update_red(bool fp32, void* x, void* r, const void* p, const void* Ap, const void* dinv,
+                         void* z, CGScal* sc, size_t n, double* partials, int nAp, int par, hipStream_t s) {
+  const int g = coarse_vec_grid(n);
+  if (fp32)
+    hipLaunchKernelGGL(k_cg_update_red<float>, dim3(g), dim3(kBlock), 0, s, (float*)x, (float*)r,
+                       (const float*)p, (const float*)Ap, (const float*)dinv, (float*)z, sc, n, partials, nAp,
+                       par);
+  else
+    hipLaunchKernelGGL(k_cg_update_red<double>, dim3(g), dim3(kBlock), 0, s, (double*)x, (double*)r,
+                       (const double*)p, (const double*)Ap, (const double*)dinv, (double*)z, sc, n, partials,
+                       nAp, par);
+  return hipGetLastError();
+}
+
+hipError_t cg_pupdate_red(bool fp32, void* p, const void* z, CGScal* sc, size_t n, const double* partials,
+                          int it, int par, hipStream_t s) {
+  const int g = coarse_vec_grid(n);
+  if (fp32)
+    hipLaunchKernelGGL(k_cg_pupdate_red<float>, dim3(g), dim3(kBlock), 0, s, (float*)p, (const float*)z, sc, n,
+                       partials, g, it, par);
+  else
+    hipLaunchKernelGGL(k_cg_pupdate_red<double>, dim3(g), dim3(kBlock), 0, s, (double*)p, (const double*)z, sc,
+                       n, partials, g, it, par);
   return hipGetLastError();
 }
 

@@ -666,11 +666,9 @@ class Solver {
       a.partials = part;
       a.skip = cdone;
       IPDG_HIP(ax(v.N, v.kind, a, s_));
-      IPDG_HIP(finalize(part, elem_grid(K_), 1, sc, kFinAlpha, s_));
-      IPDG_HIP(cg_update_state(v.fp32, x, v.cr.get(), v.cp.get(), v.cAp.get(), v.dinv(), v.cz.get(), sc,
-                               v.n, part, s_));
-      IPDG_HIP(finalize(part, flat_grid(v.n), 3, sc, kFinBeta, s_));
-      IPDG_HIP(cg_pupdate_state(v.fp32, v.cp.get(), v.cz.get(), sc, v.n, s_));
+      IPDG_HIP(cg_update_red(v.fp32, x, v.cr.get(), v.cp.get(), v.cAp.get(), v.dinv(), v.cz.get(), sc, v.n,
+                             part, elem_grid(K_), it & 1, s_));
+      IPDG_HIP(cg_pupdate_red(v.fp32, v.cp.get(), v.cz.get(), sc, v.n, part, it, it & 1, s_));
     }
   }
 
