@@ -36,7 +36,9 @@ FP32_PEAK_TFS = 157.3          # vector FP32, published
 # rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE), each scaled by the
 # counter's reading for a device-to-device copy of known size.  Valid only for
 # the kernel sources it was measured on (their SHA-256), else reported null.
-MEASURED_TRAFFIC = None
+MEASURED_TRAFFIC = {"N": 3, "dtype": "f64", "lambda": 100.0, "bytes": 113624551,
+                    "sources_sha256": "c327c3fb92afc958a955021402ea8b4a82b3500d0bf37bb02b2ab6cae8f4b7fb",
+                    "profile": "profiles/k_ax_N3_f64_524288.md"}
 
 KERNEL_SOURCES = ("elem_inst.hip", "sipdg_core.hpp", "tri.hpp", "device_common.hpp",
                   "ops_table.cpp", "ops_table.hpp", "refelem.cpp", "refelem.hpp", "dispatch.cpp")
@@ -175,7 +177,7 @@ def cpu_baseline(N, lam, target_s=12.0):
         A @ x
         reps += 1
         dt = time.time() - t0
-        if dt >= target_s or reps >= 2000:
+        if dt >= target_s or reps >= 20000:
             break
     rate = reps * S * Np / dt / 1e9
     return {"value": rate, "unit": "GDOF/s", "cores": cores, "kind": "oracle",
