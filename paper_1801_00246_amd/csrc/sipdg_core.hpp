@@ -97,53 +97,39 @@ __host__ __device__ __forceinline__ void sipdg_element_own(int e, const TX* __re
   TC Fs[3], iFs[3], tau[3];
   TC jmp[3][Nfp], dnj[3][Nfp];
 
+  // EARLY: all loads of a neighbour are issued before the element's own face
+  // derivative, which then covers their latency (costs Np live values; used
+  // where that keeps the occupancy); otherwise they stream into the
+  // neighbour's derivative sums.
+  constexpr bool EARLY = N <= 5;
   static_for<0, 3>([&](auto fc) {
     constexpr int f = decltype(fc)::value;
     phase_fence();
     const TC* __restrict__ opf = ops + opaque_zero();
+    const int bc = conn_bc(c.info, f);
+    const int nb = c.nb[f];
+    const int fp = conn_fp(c.info, f);
+    const TX* xn = x + (size_t)nb * Np;
+    // the neighbour's nodal values in the rotated order that puts its face
+    // fp at face 0
+    auto nbr_value = [&](auto jc) -> TC {
+      constexpr int j = decltype(jc)::value;
+      constexpr int o1 = G::rot(1, j), o2 = G::rot(2, j);
+      const int o = fp == 0 ? j : (fp == 1 ? o1 : o2);
+      return ld<TX, TC>(xn + o);
+    };
+    TC xv[Np];
+    if constexpr (EARLY && !DIAG) static_for<0, Np>([&](auto jc) { xv[decltype(jc)::value] = nbr_value(jc); });
+    const TC prx = geo[4 * nb + 0], psx = geo[4 * nb + 1], pry = geo[4 * nb + 2], psy = geo[4 * nb + 3];
+    const TC kp = KAP ? kap[nb] : TC(1);
+    if constexpr (EARLY) phase_fence();
     Fs[f] = sqrt(gx[f] * gx[f] + gy[f] * gy[f]);
     iFs[f] = TC(1) / Fs[f];
     const TC nx = gx[f] * iFs[f], ny = gy[f] * iFs[f];
     const TC nr = nx * rx + ny * ry, ns = nx * sx + ny * sy;
-    const int bc = conn_bc(c.info, f);
-    const int nb = c.nb[f];
-    const int fp = conn_fp(c.info, f);
-    // neighbour metric in the frame that puts its face fp at face 0
-    const TC prx = geo[4 * nb + 0], psx = geo[4 * nb + 1], pry = geo[4 * nb + 2], psy = geo[4 * nb + 3];
-    const TC qx = -(prx + psx), qy = -(pry + psy);
-    const TC Rx = fp == 0 ? prx : (fp == 1 ? psx : qx);
-    const TC Ry = fp == 0 ? pry : (fp == 1 ? psy : qy);
-    const TC Sx = fp == 0 ? psx : (fp == 1 ? qx : prx);
-    const TC Sy = fp == 0 ? psy : (fp == 1 ? qy : pry);
-    const TC Fsp = sqrt(Sx * Sx + Sy * Sy);
-    const TC kp = KAP ? kap[nb] : TC(1);
-    const TC nrp = nx * Rx + ny * Ry, nsp = nx * Sx + ny * Sy;
-    const bool inner = (bc == 0);
-    const bool dir = (bc == 1);
-
-    // neighbour: reference derivatives at its face-0 nodes (rotated frame),
-    // streamed over its nodal values
-    TC pr[Nfp], ps[Nfp], pv[Nfp];
-#pragma unroll
-    for (int m = 0; m < Nfp; ++m) pr[m] = ps[m] = pv[m] = TC(0);
-    if constexpr (!DIAG) {
-      const TX* xn = x + (size_t)nb * Np;
-      static_for<0, Np>([&](auto jc) {
-        constexpr int j = decltype(jc)::value;
-        constexpr int o1 = G::rot(1, j), o2 = G::rot(2, j);
-        const int o = fp == 0 ? j : (fp == 1 ? o1 : o2);
-        const TC v = ld<TX, TC>(xn + o);
-        if constexpr (j < Nfp) pv[j] = v;   // face-0 nodes are ids 0..N
-#pragma unroll
-        for (int m = 0; m < Nfp; ++m) {
-          pr[m] += opf[L::NBR + (j * 2 + 0) * Nfp + m] * v;
-          ps[m] += opf[L::NBR + (j * 2 + 1) * Nfp + m] * v;
-        }
-      });
-    }
-    static_for<0, Nfp>([&](auto kc) {
+    // own normal derivative at face node k
+    auto own_at = [&](auto kc) -> TC {
       constexpr int k = decltype(kc)::value;
-      constexpr int m = Nfp - 1 - k;           // neighbour's face-0 position
       constexpr int vm = G::fm(f, k);
       TC dr = TC(0), ds = TC(0);
 #pragma unroll
@@ -151,13 +137,56 @@ __host__ __device__ __forceinline__ void sipdg_element_own(int e, const TX* __re
         dr += opf[L::Dr + vm * Np + j] * u[j];
         ds += opf[L::Ds + vm * Np + j] * u[j];
       }
-      const TC own = nr * dr + ns * ds;
+      return nr * dr + ns * ds;
+    };
+    TC own[Nfp];
+    if constexpr (EARLY) static_for<0, Nfp>([&](auto kc) { own[decltype(kc)::value] = own_at(kc); });
+    // neighbour metric in its rotated frame; reference derivatives at its
+    // face-0 nodes
+    const TC qx = -(prx + psx), qy = -(pry + psy);
+    const TC Rx = fp == 0 ? prx : (fp == 1 ? psx : qx);
+    const TC Ry = fp == 0 ? pry : (fp == 1 ? psy : qy);
+    const TC Sx = fp == 0 ? psx : (fp == 1 ? qx : prx);
+    const TC Sy = fp == 0 ? psy : (fp == 1 ? qy : pry);
+    const TC Fsp = sqrt(Sx * Sx + Sy * Sy);
+    const TC nrp = nx * Rx + ny * Ry, nsp = nx * Sx + ny * Sy;
+    const bool inner = (bc == 0);
+    const bool dir = (bc == 1);
+    TC pr[Nfp], ps[Nfp];
+#pragma unroll
+    for (int m = 0; m < Nfp; ++m) pr[m] = ps[m] = TC(0);
+    if constexpr (!DIAG) {
+      static_for<0, Np>([&](auto jc) {
+        constexpr int j = decltype(jc)::value;
+        TC v;
+        if constexpr (EARLY) v = xv[j];
+        else {
+          v = nbr_value(jc);
+          if constexpr (j < Nfp) xv[j] = v;
+        }
+#pragma unroll
+        for (int m = 0; m < Nfp; ++m) {
+          pr[m] += opf[L::NBR + (j * 2 + 0) * Nfp + m] * v;
+          ps[m] += opf[L::NBR + (j * 2 + 1) * Nfp + m] * v;
+        }
+      });
+    }
+    // 4. jumps of the value and of the normal flux (face-0 nodes of the
+    //    neighbour are ids 0..N, in reverse order along the shared face)
+    static_for<0, Nfp>([&](auto kc) {
+      constexpr int k = decltype(kc)::value;
+      constexpr int m = Nfp - 1 - k;
+      constexpr int vm = G::fm(f, k);
+      TC ownk;
+      if constexpr (EARLY) ownk = own[k];
+      else ownk = own_at(kc);
       const TC dnp = nrp * pr[m] + nsp * ps[m];
       const TC um = u[vm];
-      const TC ji = pv[m] - um;
-      const TC di = kp * dnp - ke * own;
+      const TC pv = DIAG ? TC(0) : xv[m];
+      const TC ji = pv - um;
+      const TC di = kp * dnp - ke * ownk;
       jmp[f][k] = inner ? ji : (dir ? TC(-2) * um : TC(0));
-      dnj[f][k] = inner ? di : (dir ? TC(0) : TC(-2) * ke * own);
+      dnj[f][k] = inner ? di : (dir ? TC(0) : TC(-2) * ke * ownk);
     });
     // branch-free: a boundary face takes the element's own side only
     tau[f] = ctau * fmax(ke * Fs[f], TC(inner ? 1 : 0) * (kp * Fsp));
