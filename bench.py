@@ -209,6 +209,7 @@ def run_pcg_compare(P, torch, coarse_caps=(200, 20)):
             torch.cuda.synchronize()
             key = f"{name}_coarse{cmax}"
             out[key] = {"time_to_solution_ms": round((time.time() - t0) * 1e3, 2),
+                        "coarse_iters_last": info["coarse_iters"],
                         "iters": info["iters"], "true_relres": info["relres"],
                         "restarts": info["restarts"], "setup_ms": round(info["setup_ms"], 2)}
             print(f"# pcg {key}: {out[key]}", file=sys.stderr, flush=True)

@@ -153,8 +153,9 @@ ipdg_status ipdg_precond_apply(ipdg_mesh mesh, double lambda, double tau,
                                ipdg_solve_info* info, void* hip_stream);
 
 /* nb independent solves (lambda_i M - Lap) x_i = b_i, one mesh each (Sec. 3:
- * per-component velocity Helmholtz solves), advanced together: one graph
- * launch runs check_every iterations of every unfinished solve.  b and x are
+ * per-component velocity Helmholtz solves), advanced together: every round
+ * replays each unfinished solve's captured graph of check_every iterations on
+ * that solve's own stream, all launched before any is waited for.  b and x are
  * HOST arrays of nb device FP64 vector pointers; iters and relres are HOST
  * arrays of nb entries (may be NULL).  Each mesh handle may appear once.
  * With IPDG_PC_PMG the coarsest level runs as ordinary launches (never the

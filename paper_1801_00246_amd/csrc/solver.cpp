@@ -285,10 +285,9 @@ class Solver {
     return R.status;
   }
 
-  // `every` outer iterations enqueued on this solve's stream (no graph)
-  void enqueue_iterations(int every) {
-    for (int k = 0; k < every; ++k) iteration(w_->xw.as<double>());
-  }
+  // `every` outer iterations launched on this solve's own stream (its
+  // captured graph)
+  void launch_iterations(int every) { run_iterations(w_->xw.as<double>(), every); }
   hipStream_t stream() const { return s_; }
   void copy_scal() {
     IPDG_HIP(hipMemcpyAsync(w_->host_scal, w_->scal.get(), sizeof(CGScal), hipMemcpyDeviceToHost, s_));
@@ -794,10 +793,8 @@ ipdg_status precond_apply(ipdg_mesh_s* m, double lambda, double tau, const ipdg_
 ipdg_status solve_batch(int nb, ipdg_mesh_s* const* meshes, const double* lambdas, double tau,
                         const double* const* b, double* const* x, double tol, const ipdg_solve_opts& o,
                         int* iters, double* relres, hipStream_t s) {
-  // Every solve keeps its own device state and stream; one captured graph
-  // holds `check_every` iterations of all of them as parallel branches
-  // (fork/join on a batch stream), so a single graph launch advances the
-  // whole batch.  Finished solves' kernels are no-ops (done flag).
+  // Every solve keeps its own device state, stream and captured graph; the
+  // host advances all of them by check_every iterations per round.
   for (int i = 0; i < nb; ++i) {
     if (!meshes[i]) throw Error(IPDG_EINVAL, "null mesh in batch");
     if (!b[i] || !x[i]) throw Error(IPDG_EINVAL, "null vector in batch");
@@ -817,52 +814,24 @@ ipdg_status solve_batch(int nb, ipdg_mesh_s* const* meshes, const double* lambda
   for (int k = 0; k < na; ++k) IPDG_HIP(hipStreamSynchronize(sv[k]->stream()));
   for (int k = 0; k < na; ++k) sv[k]->after_start(runs[k]);
   const int every = std::max(1, o.check_every);
-  hipStream_t ms = nullptr;
-  hipGraphExec_t exec = nullptr;
-  std::vector<hipEvent_t> ev(na + 1, nullptr);
-  auto cleanup = [&]() {
-    if (exec) (void)hipGraphExecDestroy(exec);
-    for (auto e : ev)
-      if (e) (void)hipEventDestroy(e);
-    if (ms) (void)hipStreamDestroy(ms);
-  };
-  try {
-    IPDG_HIP(hipStreamCreateWithFlags(&ms, hipStreamNonBlocking));
-    for (auto& e : ev) IPDG_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  // Each solve replays its own captured graph of `every` iterations on its
+  // own stream; the launches of all unfinished solves are issued before any
+  // is waited for, so the device runs the solves' small kernels concurrently
+  // (one stream per solve, spread over the hardware queues).
+  int left = 0;
+  for (int k = 0; k < na; ++k) left += !runs[k].finished;
+  while (left > 0) {
+    for (int k = 0; k < na; ++k)
+      if (!runs[k].finished) sv[k]->launch_iterations(every);
+    for (int k = 0; k < na; ++k)
+      if (!runs[k].finished) sv[k]->copy_scal();
     for (int k = 0; k < na; ++k) IPDG_HIP(hipStreamSynchronize(sv[k]->stream()));
-    hipGraph_t g = nullptr;
-    IPDG_HIP(hipStreamBeginCapture(ms, hipStreamCaptureModeThreadLocal));
-    IPDG_HIP(hipEventRecord(ev[na], ms));
-    for (int k = 0; k < na; ++k) {
-      IPDG_HIP(hipStreamWaitEvent(sv[k]->stream(), ev[na], 0));
-      sv[k]->enqueue_iterations(every);
-      IPDG_HIP(hipEventRecord(ev[k], sv[k]->stream()));
-      IPDG_HIP(hipStreamWaitEvent(ms, ev[k], 0));
-    }
-    IPDG_HIP(hipStreamEndCapture(ms, &g));
-    hipError_t e = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(g);
-    IPDG_HIP(e);
-    int left = 0;
-    for (int k = 0; k < na; ++k) left += !runs[k].finished;
-    while (left > 0) {
-      IPDG_HIP(hipGraphLaunch(exec, ms));
-      IPDG_HIP(hipStreamSynchronize(ms));
-      for (int k = 0; k < na; ++k)
-        if (!runs[k].finished) sv[k]->copy_scal();
-      for (int k = 0; k < na; ++k) IPDG_HIP(hipStreamSynchronize(sv[k]->stream()));
-      left = 0;
-      for (int k = 0; k < na; ++k)
-        if (!runs[k].finished) left += !sv[k]->after_step(runs[k]);
-      // residual replacements were enqueued on the solves' own streams; the
-      // next graph launch must start after them
-      for (int k = 0; k < na; ++k) IPDG_HIP(hipStreamSynchronize(sv[k]->stream()));
-    }
-  } catch (...) {
-    cleanup();
-    throw;
+    left = 0;
+    for (int k = 0; k < na; ++k)
+      if (!runs[k].finished) left += !sv[k]->after_step(runs[k]);
+    // residual replacements were enqueued on the solves' own streams and run
+    // before their next graph launch (same stream)
   }
-  cleanup();
   ipdg_status worst = IPDG_OK;
   for (int k = 0; k < na; ++k) {
     ipdg_solve_info info{};

@@ -279,3 +279,4 @@ def test_mixed_precision_keeps_the_fp64_iteration_count(pc):
     base = its[(P.PREC_FP64, 0.0)]
     for k, v in its.items():
         assert v <= base + max(3, base // 20), k
+
