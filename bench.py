@@ -265,6 +265,62 @@ def run_batch_compare(P, torch, nb=64, prec=None, tol=1e-8):
             "max_relres": max(rel), "status": st}
 
 
+def run_grad_compare(P, torch, n=128, N=5, lam=1.0, tol=1e-8, reps=3):
+    """Differentiable solve: n x n squares (jittered), N = 5, kappa_e =
+    exp(0.5 N(0,1)), f ~ N(0,1) nodal, L = (u - u_t)^T M (u - u_t) with u_t a
+    smooth sine series; dL/df and dL/dkappa through forward PCG + adjoint PCG
+    + the kappa-gradient kernel, p-multigrid 5 -> 2 -> 1, FP64 vs mixed."""
+    import numpy as np
+    import synth
+    from paper_1801_00246_amd.autograd import helmholtz_solve, mass
+    msh = synth.square_mesh(n, jitter=0.2, seed=0)
+    kap = synth.kappa_draw(msh.K, seed=2)
+    g = P.Mesh.from_synth(N, msh, kappa=kap)
+    x, y = g.node_coords()
+    ut = torch.from_numpy(synth.smooth_field(x.ravel(), y.ravel(), synth.smooth_coeffs(seed=3))).to("cuda")
+    f0 = torch.from_numpy(synth.nodal_normal(msh.K, g.Np, seed=5)).to("cuda")
+    kap0 = torch.from_numpy(kap).to("cuda")
+    out = {"workload": f"{n}x{n} squares ({msh.K} triangles), N={N}, kappa lognormal(0,0.5), "
+                       f"lambda={lam}, tol {tol}, pMG {N}->{N // 2}->...->1; forward + adjoint"}
+    grads = {}
+    for name, prec in (("fp64", P.PREC_FP64), ("mixed", P.PREC_MIXED)):
+        o = P.default_opts(pc=P.PC_PMG, prec=prec)
+        times = []
+        for r in range(reps + 1):
+            kap_t = kap0.clone().requires_grad_(True)
+            f_t = f0.clone().requires_grad_(True)
+            torch.cuda.synchronize()
+            t0 = time.time()
+            u = helmholtz_solve(f_t, kap_t, g, lam=lam, tol=tol, opts=o)
+            d = u - ut
+            L = torch.dot(d, mass(d, g))
+            L.backward()
+            torch.cuda.synchronize()
+            if r > 0:                  # the first run includes the set-up
+                times.append(time.time() - t0)
+        grads[name] = (kap_t.grad.detach().cpu().numpy(), f_t.grad.detach().cpu().numpy())
+        out[name] = {"ms_forward_backward": round(1e3 * min(times), 2), "loss": float(L)}
+        print(f"# grad {name}: {out[name]}", file=sys.stderr, flush=True)
+    gk64, gf64 = grads["fp64"]
+    gk32, gf32 = grads["mixed"]
+    out["mixed_vs_fp64_rel"] = {"dL/dkappa": float(np.linalg.norm(gk32 - gk64) / np.linalg.norm(gk64)),
+                                "dL/df": float(np.linalg.norm(gf32 - gf64) / np.linalg.norm(gf64))}
+    # the coefficient-gradient kernel alone (one launch over all elements)
+    u = torch.randn(msh.K * g.Np, dtype=torch.float64, device="cuda")
+    w = torch.randn_like(u)
+    g.kappa_grad(u, w)
+    s_ = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s_)
+    for _ in range(20):
+        g.kappa_grad(u, w)
+    e1.record(s_)
+    torch.cuda.synchronize()
+    out["kappa_grad_kernel_us"] = round(1e3 * e0.elapsed_time(e1) / 20, 2)
+    g.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -278,6 +334,7 @@ def main():
     ap.add_argument("--no-pcg", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--batch", action="store_true", help="also run the 64-solve batched Helmholtz leg")
+    ap.add_argument("--grad", action="store_true", help="also run the differentiable-solve leg")
     ap.add_argument("--sweep-orders", default="1,2,3,4,5,6,7,8")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -329,6 +386,8 @@ def main():
             line["pcg"] = run_pcg_compare(P, torch)
         except P.IpdgError as e:
             line["pcg"] = {"error": str(e)}
+    if args.grad:
+        line["grad"] = run_grad_compare(P, torch)
     if args.batch:
         line["batch"] = run_batch_compare(P, torch)
         print(f"# batch: {line['batch']}", file=sys.stderr, flush=True)

@@ -1,5 +1,6 @@
 // C ABI entry points (include/ipdg.h).  Every call catches library errors and
 // maps them to an ipdg_status; the message is kept per thread.
+#include <algorithm>
 #include <cstring>
 #include <string>
 
@@ -35,12 +36,16 @@ ipdg::Kind kind_of(ipdg_dtype d) { return d == IPDG_F32 ? ipdg::Kind::F32 : ipdg
 void upload_kappa(ipdg_mesh_s* m, const double* kappa) {
   const int K = m->host.K;
   if (!kappa) {
+    if (m->has_kappa) ++m->kappa_version;
     m->has_kappa = false;
     m->kappa.clear();
     return;
   }
   for (int e = 0; e < K; ++e)
     if (!(kappa[e] > 0.0)) throw ipdg::Error(IPDG_EINVAL, "kappa must be positive");
+  // the same values again: nothing to upload, solver set-ups stay valid
+  if (m->has_kappa && (int)m->kappa.size() == K && std::equal(kappa, kappa + K, m->kappa.begin())) return;
+  ++m->kappa_version;
   m->kappa.assign(kappa, kappa + K);
   std::vector<float> k32(kappa, kappa + K);
   m->kap64.ensure(K * sizeof(double));

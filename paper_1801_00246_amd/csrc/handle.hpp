@@ -67,6 +67,7 @@ struct ipdg_mesh_s {
   int Np = 0;
   bool has_kappa = false;
   std::vector<double> kappa;      // host copy (K) when has_kappa
+  unsigned kappa_version = 0;     // changes whenever the coefficient values change
   ipdg::DevBuf geo64, geo32, conn, kap64, kap32;
   std::unique_ptr<ipdg::SolverWork> work;
   ~ipdg_mesh_s();

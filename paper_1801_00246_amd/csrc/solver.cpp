@@ -64,6 +64,7 @@ struct Work : SolverWork {
   int degrees[IPDG_MAX_LEVELS] = {0};
   double rho_in[IPDG_MAX_LEVELS] = {0};
   bool has_kappa = false;
+  unsigned kappa_version = 0;
   double setup_ms = 0;
 
   size_t n = 0;
@@ -317,7 +318,7 @@ class Solver {
     if (w.n != n_ || w.lambda != lambda_ || w.ctau != ctau_ || w.pc != o_.pc || w.prec != o_.prec ||
         w.has_kappa != m_->has_kappa)
       return false;
-    if (m_->has_kappa) return false;   // kappa may have been replaced
+    if (m_->has_kappa && w.kappa_version != m_->kappa_version) return false;
     if (o_.pc == IPDG_PC_PMG) {
       if (w.nlev != o_.n_levels || w.cheb_degree != o_.cheb_degree || w.cheb_lo != o_.cheb_lo ||
           w.cheb_hi != o_.cheb_hi || w.coarse_max != o_.coarse_max_iters ||
@@ -381,6 +382,7 @@ class Solver {
     w.pc = o_.pc;
     w.prec = o_.prec;
     w.has_kappa = m_->has_kappa;
+    w.kappa_version = m_->kappa_version;
     w.nlev = o_.n_levels;
     w.cheb_degree = o_.cheb_degree;
     w.cheb_lo = o_.cheb_lo;
