@@ -333,8 +333,8 @@ def main():
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--no-pcg", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--batch", action="store_true", help="also run the 64-solve batched Helmholtz leg")
-    ap.add_argument("--grad", action="store_true", help="also run the differentiable-solve leg")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 64-solve batched Helmholtz leg")
+    ap.add_argument("--no-grad", action="store_true", help="skip the differentiable-solve leg")
     ap.add_argument("--sweep-orders", default="1,2,3,4,5,6,7,8")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -386,9 +386,9 @@ def main():
             line["pcg"] = run_pcg_compare(P, torch)
         except P.IpdgError as e:
             line["pcg"] = {"error": str(e)}
-    if args.grad:
+    if not args.no_grad:
         line["grad"] = run_grad_compare(P, torch)
-    if args.batch:
+    if not args.no_batch:
         line["batch"] = run_batch_compare(P, torch)
         print(f"# batch: {line['batch']}", file=sys.stderr, flush=True)
     print(json.dumps(line), flush=True)
