@@ -307,26 +307,29 @@ __device__ double block_total(const double* __restrict__ partials, int slot, int
   return t;
 }
 
-// Coarse Jacobi-PCG step without a finalize launch: every block reduces the
-// (p, Ap) partials of the operator launch itself, alpha = rz / (p, Ap);
-// x += alpha p; r -= alpha Ap; z = dinv r; partials (r, r), (r, z) in
-// slots 1, 2.  rz of iteration `par` parity is sc->rzb[par].
+// Second launch of a coarse Jacobi-PCG iteration `it` (the first is the
+// operator launch k_coarse_step, which formed p and wrote (p, Ap) partials to
+// slot 2): every block reduces those itself, alpha = rz / (p, Ap) with rz in
+// sc->rzb[it % 2]; x += alpha p; r -= alpha Ap; z = dinv r; partials (r, r),
+// (r, z) in slots 0, 1.  Block 0 records the iteration count.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_cg_update_red(T* __restrict__ x, T* __restrict__ r,
                                                           const T* __restrict__ p, const T* __restrict__ Ap,
                                                           const T* __restrict__ dinv, T* __restrict__ z,
                                                           CGScal* __restrict__ sc, size_t n,
-                                                          double* __restrict__ partials, int nAp, int par) {
+                                                          double* __restrict__ partials, int nAp, int it) {
   if (sc->done) return;
-  const double pAp = block_total(partials, 0, nAp);
+  const double pAp = block_total(partials, 2, nAp);
+  const bool b0 = blockIdx.x == 0 && threadIdx.x == 0;
   if (!(pAp > 0.0) || !isfinite(pAp)) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (b0) {
       sc->breakdown = 1;
       sc->done = 1;
     }
     return;
   }
-  const T alpha = static_cast<T>(sc->rzb[par] / pAp);
+  if (b0) sc->iters = it + 1;
+  const T alpha = static_cast<T>(sc->rzb[it & 1] / pAp);
   double v[2] = {0.0, 0.0};
   for (size_t i = blockIdx.x * (size_t)kBlock + threadIdx.x; i < n; i += (size_t)gridDim.x * kBlock) {
     x[i] += alpha * p[i];
@@ -339,34 +342,9 @@ __global__ __launch_bounds__(kBlock) void k_cg_update_red(T* __restrict__ x, T* 
   }
   block_sum<2>(v);
   if (threadIdx.x == 0) {
-    partials[1 * kMaxPartials + blockIdx.x] = v[0];
-    partials[2 * kMaxPartials + blockIdx.x] = v[1];
+    partials[0 * kMaxPartials + blockIdx.x] = v[0];
+    partials[1 * kMaxPartials + blockIdx.x] = v[1];
   }
-}
-
-// ... then every block reduces (r, r), (r, z): stop at rr <= tol2 or at
-// iteration `it` + 1 == max_iters, else beta = rz_new / rz and
-// p = z + beta p.  Block 0 records the iteration count, the stop and
-// rz_new in sc->rzb[1 - par] (other blocks read only sc->rzb[par]).
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_cg_pupdate_red(T* __restrict__ p, const T* __restrict__ z,
-                                                           CGScal* __restrict__ sc, size_t n,
-                                                           const double* __restrict__ partials, int nparts,
-                                                           int it, int par) {
-  if (sc->done) return;
-  const double rr = block_total(partials, 1, nparts);
-  const double rz = block_total(partials, 2, nparts);
-  const bool stop = rr <= sc->tol2 || it + 1 >= sc->max_iters || !isfinite(rr);
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    sc->iters = it + 1;
-    sc->rr = rr;
-    sc->rzb[1 - par] = rz;
-    if (stop) sc->done = 1;
-  }
-  if (stop) return;
-  const T beta = static_cast<T>(rz / sc->rzb[par]);
-  for (size_t i = blockIdx.x * (size_t)kBlock + threadIdx.x; i < n; i += (size_t)gridDim.x * kBlock)
-    p[i] = z[i] + beta * p[i];
 }
 
 __global__ __launch_bounds__(kBlock) void k_recip(double* __restrict__ d, float* __restrict__ d32, size_t n) {
@@ -494,28 +472,16 @@ int coarse_vec_grid(size_t n) {
 }
 
 hipError_t cg_update_red(bool fp32, void* x, void* r, const void* p, const void* Ap, const void* dinv,
-                         void* z, CGScal* sc, size_t n, double* partials, int nAp, int par, hipStream_t s) {
+                         void* z, CGScal* sc, size_t n, double* partials, int nAp, int it, hipStream_t s) {
   const int g = coarse_vec_grid(n);
   if (fp32)
     hipLaunchKernelGGL(k_cg_update_red<float>, dim3(g), dim3(kBlock), 0, s, (float*)x, (float*)r,
                        (const float*)p, (const float*)Ap, (const float*)dinv, (float*)z, sc, n, partials, nAp,
-                       par);
+                       it);
   else
     hipLaunchKernelGGL(k_cg_update_red<double>, dim3(g), dim3(kBlock), 0, s, (double*)x, (double*)r,
                        (const double*)p, (const double*)Ap, (const double*)dinv, (double*)z, sc, n, partials,
-                       nAp, par);
-  return hipGetLastError();
-}
-
-hipError_t cg_pupdate_red(bool fp32, void* p, const void* z, CGScal* sc, size_t n, const double* partials,
-                          int it, int par, hipStream_t s) {
-  const int g = coarse_vec_grid(n);
-  if (fp32)
-    hipLaunchKernelGGL(k_cg_pupdate_red<float>, dim3(g), dim3(kBlock), 0, s, (float*)p, (const float*)z, sc, n,
-                       partials, g, it, par);
-  else
-    hipLaunchKernelGGL(k_cg_pupdate_red<double>, dim3(g), dim3(kBlock), 0, s, (double*)p, (const double*)z, sc,
-                       n, partials, g, it, par);
+                       nAp, it);
   return hipGetLastError();
 }
 

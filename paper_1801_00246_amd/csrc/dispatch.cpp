@@ -82,6 +82,12 @@ hipError_t prolong(int Nf, int Nc, Kind kind, const TransferArgs& a, hipStream_t
 #undef C
 }
 
+hipError_t coarse_step(int N, Kind kind, const CoarseStepArgs& a, hipStream_t s) {
+#define C(n) launch_coarse_step<n>(kind, a, s)
+  IPDG_SWITCH(N, C)
+#undef C
+}
+
 hipError_t coarse_pcg(int N, Kind kind, const CoarseArgs& a, int grid, hipStream_t s) {
 #define C(n) launch_coarse_pcg<n>(kind, a, grid, s)
   IPDG_SWITCH(N, C)

@@ -472,6 +472,118 @@ __global__ __launch_bounds__(kBlock) void k_coarse_pcg(const T* __restrict__ f, 
   if (blockIdx.x == 0 && threadIdx.x == 0) status[0] = it;
 }
 
+// Sum of slot `slot` of the partials over nparts entries, returned to every
+// thread; every block gets the same value (same order).
+__device__ double slot_total(const double* __restrict__ partials, int slot, int nparts) {
+  __shared__ double tot;
+  double v[1] = {0.0};
+  for (int i = threadIdx.x; i < nparts; i += kBlock) v[0] += partials[slot * kMaxPartials + i];
+  block_sum<1>(v);
+  if (threadIdx.x == 0) tot = v[0];
+  __syncthreads();
+  const double t = tot;
+  __syncthreads();
+  return t;
+}
+
+// p = z + beta p_old read on the fly (beta = 0: p = z)
+template <typename T>
+struct AxpySrc {
+  const T* __restrict__ z;
+  const T* __restrict__ p;
+  T beta;
+  bool first;
+  __device__ __forceinline__ T operator()(size_t i) const { return first ? z[i] : z[i] + beta * p[i]; }
+};
+
+template <typename T, bool KAP>
+__global__ __launch_bounds__(kBlock) void k_coarse_step(const T* __restrict__ z, const T* __restrict__ p_old,
+                                                        T* __restrict__ p_new, T* __restrict__ Ap,
+                                                        const T* __restrict__ geo,
+                                                        const Conn* __restrict__ conn,
+                                                        const T* __restrict__ kap,
+                                                        const T* __restrict__ ops, T lambda, T ctau, int K,
+                                                        int per, double* __restrict__ partials, int nin,
+                                                        CGScal* __restrict__ sc, const int* __restrict__ outer,
+                                                        int it) {
+  const bool first = it == 0;
+  const int par = it & 1;
+  const bool b0 = blockIdx.x == 0 && threadIdx.x == 0;
+  if (first) {
+    if (outer && *outer) {               // outer solve finished: keep the last record
+      if (b0) sc->done = 1;
+      return;
+    }
+  } else if (sc->done) {
+    return;
+  }
+  const double rr = slot_total(partials, 0, nin);
+  const double rz = slot_total(partials, 1, nin);
+  T beta = T(0);
+  if (first) {
+    const bool stop = !(rr > 0.0) || sc->max_iters <= 0;
+    if (b0) {
+      sc->tol2 = sc->tol * sc->tol * rr;
+      sc->rr = rr;
+      sc->rzb[par] = rz;
+      sc->iters = 0;
+      sc->breakdown = 0;
+      sc->done = stop ? 1 : 0;
+    }
+    if (stop) return;
+  } else {
+    const bool stop = rr <= sc->tol2 || !isfinite(rr);
+    if (b0) {
+      sc->rr = rr;
+      sc->rzb[par] = rz;
+      if (stop) sc->done = 1;
+    }
+    if (stop) return;
+    beta = static_cast<T>(rz / sc->rzb[1 - par]);
+  }
+  const AxpySrc<T> src{z, p_old, beta, first};
+  const int e = xcd_tile(blockIdx.x, per) * kBlock + threadIdx.x;
+  double dot = 0.0;
+  if (e < K) {
+    T u[Np];
+    T* pe = p_new + (size_t)e * Np;
+    T* ye = Ap + (size_t)e * Np;
+    sipdg_element_src<N, T, KAP, false>(
+        e, src, geo, conn, kap, ops, lambda, ctau, 0, u,
+        [&](int i, T v) {
+          ye[i] = v;
+          dot += double(pe[i]) * double(v);
+        },
+        [&](int j) {
+          const T pj = src((size_t)e * Np + j);
+          pe[j] = pj;
+          return pj;
+        });
+  }
+  double v[1] = {dot};
+  block_sum<1>(v);
+  if (threadIdx.x == 0) partials[2 * kMaxPartials + blockIdx.x] = v[0];
+}
+
+template <typename T>
+hipError_t run_coarse_step(const CoarseStepArgs& a, hipStream_t s) {
+  const ElemArgs& o = a.op;
+  int per;
+  const int grid = xcd_grid(elem_tiles(o.K), per);
+  if (o.K == 0) return hipSuccess;
+  if (o.kap)
+    hipLaunchKernelGGL((k_coarse_step<T, true>), dim3(grid), dim3(kBlock), 0, s, (const T*)a.z,
+                       (const T*)a.p_old, (T*)a.p_new, (T*)a.Ap, (const T*)o.geo, o.conn, (const T*)o.kap,
+                       (const T*)o.ops, T(o.lambda), T(o.ctau), o.K, per, a.partials, a.nin, a.sc, a.outer,
+                       a.it);
+  else
+    hipLaunchKernelGGL((k_coarse_step<T, false>), dim3(grid), dim3(kBlock), 0, s, (const T*)a.z,
+                       (const T*)a.p_old, (T*)a.p_new, (T*)a.Ap, (const T*)o.geo, o.conn, (const T*)o.kap,
+                       (const T*)o.ops, T(o.lambda), T(o.ctau), o.K, per, a.partials, a.nin, a.sc, a.outer,
+                       a.it);
+  return hipGetLastError();
+}
+
 template <int NN, typename T>
 hipError_t run_coarse(const CoarseArgs& a, int grid, hipStream_t s) {
   const ElemArgs& o = a.op;
@@ -625,6 +737,11 @@ hipError_t launch_ax<N>(Kind kind, const ElemArgs& a, hipStream_t s) {
     case Kind::F32_IN64: break;   // not used: operators read their own precision
   }
   return hipErrorInvalidValue;
+}
+
+template <>
+hipError_t launch_coarse_step<N>(Kind kind, const CoarseStepArgs& a, hipStream_t s) {
+  return kind == Kind::F64 ? run_coarse_step<double>(a, s) : run_coarse_step<float>(a, s);
 }
 
 template <>

@@ -93,6 +93,26 @@ struct CoarseArgs {
 template <int N> hipError_t launch_coarse_pcg(Kind kind, const CoarseArgs& a, int grid, hipStream_t s);
 template <int N> int coarse_pcg_grid(Kind kind, int K);   // resident grid size, 0 if unsupported
 
+// First launch of a coarse Jacobi-PCG iteration `it` (the second is
+// cg_update_red): every block reduces the (r, r), (r, z) partials of the
+// previous launch (slots 0, 1, nin entries), records the stop in sc, else
+// forms p = z + beta p_old on the fly (p = z at it = 0), writes it to p_new
+// and computes Ap = A p with the (p, Ap) block partials in slot 2.
+struct CGScal;
+struct CoarseStepArgs {
+  const void* z = nullptr;
+  const void* p_old = nullptr;
+  void* p_new = nullptr;
+  void* Ap = nullptr;
+  ElemArgs op;                 // operator of the level (x, y, partials unused)
+  double* partials = nullptr;  // 3 x kMaxPartials
+  int nin = 0;
+  CGScal* sc = nullptr;
+  const int* outer = nullptr;  // outer solve's done flag (checked at it = 0)
+  int it = 0;
+};
+template <int N> hipError_t launch_coarse_step(Kind kind, const CoarseStepArgs& a, hipStream_t s);
+
 // Runtime-degree dispatch (dispatch.cpp)
 hipError_t ax(int N, Kind kind, const ElemArgs& a, hipStream_t s);
 hipError_t diag(int N, Kind kind, const ElemArgs& a, hipStream_t s);
@@ -102,6 +122,7 @@ hipError_t kgrad(int N, const KgradArgs& a, hipStream_t s);
 hipError_t restrict_(int Nf, int Nc, Kind kind, const TransferArgs& a, hipStream_t s);
 hipError_t prolong(int Nf, int Nc, Kind kind, const TransferArgs& a, hipStream_t s);
 hipError_t coarse_pcg(int N, Kind kind, const CoarseArgs& a, int grid, hipStream_t s);
+hipError_t coarse_step(int N, Kind kind, const CoarseStepArgs& a, hipStream_t s);
 int coarse_pcg_grid(int N, Kind kind, int K);
 
 }  // namespace ipdg

@@ -64,14 +64,21 @@ __host__ __device__ __forceinline__ void phase_fence() {
 #endif
 }
 
+// Nodal values of the operand: x[i] from a vector in TX, converted to TC.
+template <typename TX, typename TC>
+struct VecSrc {
+  const TX* __restrict__ x;
+  __host__ __device__ __forceinline__ TC operator()(size_t i) const { return ld<TX, TC>(x + i); }
+};
+
 // Computes y_e and hands each output row to out(i, y_i) as soon as it is
-// formed (so no output array stays live).  DIAG: u = unit vector e_unit on
-// this element and zero neighbours (Jacobi diagonal).  u holds the element's
-// values throughout.
-// As above, with the element's own nodal values supplied by own(j) (e.g. from
-// a block-wide staging buffer).
-template <int N, typename TC, typename TX, bool KAP, bool DIAG, typename Out, typename Own>
-__host__ __device__ __forceinline__ void sipdg_element_own(int e, const TX* __restrict__ x,
+// formed (so no output array stays live).  The element's own nodal values
+// come from own(j) (e.g. a block-wide staging buffer), the neighbours' from
+// src(i), i = e Np + j (a vector, or one formed on the fly from two others).
+// DIAG: u = unit vector e_unit on this element and zero neighbours (Jacobi
+// diagonal).  u holds the element's values throughout.
+template <int N, typename TC, bool KAP, bool DIAG, typename Src, typename Out, typename Own>
+__host__ __device__ __forceinline__ void sipdg_element_src(int e, const Src& src,
                                                            const TC* __restrict__ geo,
                                                            const Conn* __restrict__ conn,
                                                            const TC* __restrict__ kap,
@@ -109,14 +116,14 @@ __host__ __device__ __forceinline__ void sipdg_element_own(int e, const TX* __re
     const int bc = conn_bc(c.info, f);
     const int nb = c.nb[f];
     const int fp = conn_fp(c.info, f);
-    const TX* xn = x + (size_t)nb * Np;
+    const size_t xn = (size_t)nb * Np;
     // the neighbour's nodal values in the rotated order that puts its face
     // fp at face 0
     auto nbr_value = [&](auto jc) -> TC {
       constexpr int j = decltype(jc)::value;
       constexpr int o1 = G::rot(1, j), o2 = G::rot(2, j);
       const int o = fp == 0 ? j : (fp == 1 ? o1 : o2);
-      return ld<TX, TC>(xn + o);
+      return src(xn + o);
     };
     TC xv[Np];
     if constexpr (EARLY && !DIAG) static_for<0, Np>([&](auto jc) { xv[decltype(jc)::value] = nbr_value(jc); });
@@ -200,10 +207,10 @@ __host__ __device__ __forceinline__ void sipdg_element_own(int e, const TX* __re
     TC cn[3];
 #pragma unroll
     for (int f = 0; f < 3; ++f) cn[f] = TC(0.5) * (gx[f2] * gx[f] + gy[f2] * gy[f]) * iFs[f2];
+    const TC* __restrict__ opp = ops + opaque_zero();
     static_for<0, Nfp>([&](auto pc) {
       constexpr int p = decltype(pc)::value;
       constexpr int i = G::fm(f2, p);
-      const TC* __restrict__ opp = ops + opaque_zero();
       TC nl = TC(0);
 #pragma unroll
       for (int f = 0; f < 3; ++f) {
@@ -261,6 +268,18 @@ __host__ __device__ __forceinline__ void sipdg_element_own(int e, const TX* __re
     }
     out(i, acc * J - fa);
   }
+}
+
+template <int N, typename TC, typename TX, bool KAP, bool DIAG, typename Out, typename Own>
+__host__ __device__ __forceinline__ void sipdg_element_own(int e, const TX* __restrict__ x,
+                                                           const TC* __restrict__ geo,
+                                                           const Conn* __restrict__ conn,
+                                                           const TC* __restrict__ kap,
+                                                           const TC* __restrict__ ops, TC lambda,
+                                                           TC ctau, int unit, TC (&u)[Tri<N>::Np],
+                                                           Out&& out, Own&& own) {
+  sipdg_element_src<N, TC, KAP, DIAG>(e, VecSrc<TX, TC>{x}, geo, conn, kap, ops, lambda, ctau, unit, u, out,
+                                      own);
 }
 
 template <int N, typename TC, typename TX, bool KAP, bool DIAG, typename Out>

@@ -51,7 +51,7 @@ struct Level {
   Kind kind = Kind::F64;
   DevBuf dinv64, dinv32;
   DevBuf f, z, r, d, t;            // V-cycle work (level precision)
-  DevBuf cr, cz, cp, cAp;          // coarsest level: Jacobi-PCG work
+  DevBuf cr, cz, cp, cp2, cAp;     // coarsest level: Jacobi-PCG work (p by parity)
   const void* P = nullptr;         // interpolation from the next level
   const void* dinv() const { return fp32 ? dinv32.get() : dinv64.get(); }
 };
@@ -427,6 +427,7 @@ class Solver {
         v.cr.ensure(v.n * w8);
         v.cz.ensure(v.n * w8);
         v.cp.ensure(v.n * w8);
+        v.cp2.ensure(v.n * w8);
         v.cAp.ensure(v.n * w8);
         if (!v.z.get()) v.z.ensure(v.n * w8);
       }
@@ -656,20 +657,25 @@ class Solver {
     }
     CGScal* sc = w.cscal.as<CGScal>();
     double* part = w.cpartials.as<double>();
+    // x = 0, r = f, z = D^-1 f and the (r, r), (r, z) partials
     IPDG_HIP(cg_start0(v.fp32, f, v.dinv(), x, v.cr.get(), v.cz.get(), v.cp.get(), v.n, part,
                        outer_done(), s_));
-    IPDG_HIP(cg_start_fin(part, flat_grid(v.n), sc, outer_done(), s_));
-    const int* cdone = done_ptr(w.cscal);
-    ElemArgs a = elem_args(m_, v.N, v.kind, lambda_, v.ctau);
+    CoarseStepArgs ca;
+    ca.z = v.cz.get();
+    ca.Ap = v.cAp.get();
+    ca.op = elem_args(m_, v.N, v.kind, lambda_, v.ctau);
+    ca.partials = part;
+    ca.sc = sc;
+    ca.outer = outer_done();
+    void* pb[2] = {v.cp.get(), v.cp2.get()};   // p by iteration parity
     for (int it = 0; it < o_.coarse_max_iters; ++it) {
-      a.x = v.cp.get();
-      a.y = v.cAp.get();
-      a.partials = part;
-      a.skip = cdone;
-      IPDG_HIP(ax(v.N, v.kind, a, s_));
-      IPDG_HIP(cg_update_red(v.fp32, x, v.cr.get(), v.cp.get(), v.cAp.get(), v.dinv(), v.cz.get(), sc, v.n,
-                             part, elem_grid(K_), it & 1, s_));
-      IPDG_HIP(cg_pupdate_red(v.fp32, v.cp.get(), v.cz.get(), sc, v.n, part, it, it & 1, s_));
+      ca.it = it;
+      ca.p_new = pb[it & 1];
+      ca.p_old = pb[(it + 1) & 1];
+      ca.nin = it == 0 ? flat_grid(v.n) : coarse_vec_grid(v.n);
+      IPDG_HIP(coarse_step(v.N, v.kind, ca, s_));
+      IPDG_HIP(cg_update_red(v.fp32, x, v.cr.get(), pb[it & 1], v.cAp.get(), v.dinv(), v.cz.get(), sc, v.n,
+                             part, elem_grid(K_), it, s_));
     }
   }
 
