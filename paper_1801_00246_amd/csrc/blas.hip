@@ -158,8 +158,6 @@ __global__ __launch_bounds__(kBlock) void k_finalize(const double* __restrict__ 
       if (s0 <= sc->tol2 || sc->iters >= sc->max_iters) sc->done = 1;
       break;
     }
-    case kFinRho:        // Lanczos steps record alpha/beta history (host reads)
-      break;
   }
 }
 

@@ -16,7 +16,7 @@ struct CGScal {
 // Partial-sum slots per reduction (>= blocks of any element or vector launch).
 constexpr int kMaxPartials = 65536;
 
-enum FinOp { kFinResidual = 0, kFinInit = 1, kFinAlpha = 2, kFinBeta = 3, kFinRho = 4 };
+enum FinOp { kFinResidual = 0, kFinInit = 1, kFinAlpha = 2, kFinBeta = 3 };
 
 int flat_grid(size_t n);
 

@@ -68,7 +68,7 @@ struct Work : SolverWork {
   double setup_ms = 0;
 
   size_t n = 0;
-  DevBuf r, p, Ap, z, t64, xw, partials, cpartials, scal, cscal, dinv64, dinv32, zero_flag;
+  DevBuf r, p, Ap, z, t64, xw, partials, cpartials, scal, cscal, dinv64, dinv32;
   DevBuf cbar;                     // persistent coarse solve: 2 barrier counters + 3 status ints
   int coarse_grid = 0;             // resident grid of the persistent coarse solve (0: not used)
   std::vector<Level> lv;
@@ -350,8 +350,6 @@ class Solver {
     w.cpartials.ensure(3 * kMaxPartials * sizeof(double));
     w.scal.ensure(sizeof(CGScal));
     w.cscal.ensure(sizeof(CGScal));
-    w.zero_flag.ensure(sizeof(int));
-    IPDG_HIP(hipMemsetAsync(w.zero_flag.get(), 0, sizeof(int), s_));
     if (!w.host_scal) IPDG_HIP(hipHostMalloc(reinterpret_cast<void**>(&w.host_scal), sizeof(CGScal)));
     if (o_.pc == IPDG_PC_JACOBI || o_.pc == IPDG_PC_NONE) {
       w.dinv64.ensure(n_ * 8);

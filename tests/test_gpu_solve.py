@@ -280,3 +280,21 @@ def test_mixed_precision_keeps_the_fp64_iteration_count(pc):
     for k, v in its.items():
         assert v <= base + max(3, base // 20), k
 
+
+
+def test_new_coefficient_values_replace_the_solver_setup():
+    """A solver set-up (diagonals, spectral estimates, graph) is kept while the
+    coefficient is unchanged and rebuilt when its values change."""
+    msh = synth.square_mesh(10, jitter=0.2, seed=31)
+    m = OracleMesh(msh.VX, msh.VY, msh.EToV, msh.EToB, 3)
+    k1 = synth.kappa_draw(msh.K, seed=5)
+    k2 = synth.kappa_draw(msh.K, seed=6)
+    b = mass_apply(m, synth.nodal_normal(msh.K, m.Np, seed=7))
+    g = P.Mesh.from_synth(3, msh, kappa=k1)
+    o = P.default_opts(pc=P.PC_PMG, degrees=[3, 1])
+    for kap in (k1, k2, k2, k1):
+        g.set_kappa(kap)
+        x, info, st = g.pcg(dev(b), lam=1.0, tol=1e-10, opts=o)
+        A = assemble(m, 1.0, 16.0, kappa=kap)
+        assert st == 0
+        assert true_relres(A, host(x), b) <= 1e-10
