@@ -115,7 +115,9 @@ void ipdg_default_opts(ipdg_solve_opts* opts);
  *   kappa    : K per-element coefficients > 0, or NULL for kappa = 1 (host).
  * IPDG_EMESH for a non-positive Jacobian, a face shared by more than two
  * elements, an unmatched face flagged interior or a matched face flagged as
- * boundary.  IPDG_EUNSUPPORTED for N outside 1..8.  Sec. 2.1 (mesh, degree),
+ * boundary.  IPDG_EUNSUPPORTED for N outside 1..8.  The mesh's device data
+ * live on the device current at creation; later calls on the mesh run there
+ * (and restore the caller's current device).  Sec. 2.1 (mesh, degree),
  * Sec. 5.2 (geometric factors of the affine map, Eq. operators2). */
 ipdg_status ipdg_mesh_create(int N, int Nv, const double* VX, const double* VY,
                              int K, const int32_t* EToV, const int8_t* EToB,
@@ -160,14 +162,18 @@ ipdg_status ipdg_precond_apply(ipdg_mesh mesh, double lambda, double tau,
  * arrays of nb entries (may be NULL).  Each mesh handle may appear once.
  * With IPDG_PC_PMG the coarsest level runs as ordinary launches (never the
  * persistent single-launch form, whose grids could not all be resident).
- * Returns IPDG_NOT_CONVERGED if any solve stopped at max_iters. */
+ * All meshes must live on one device.  opts NULL: defaults with the
+ * block inverse-mass preconditioner.  Returns IPDG_NOT_CONVERGED if any
+ * solve stopped at max_iters. */
 ipdg_status ipdg_helmholtz_solve_batch(int nb, const ipdg_mesh* meshes, const double* lambdas,
                                        double tau, const double* const* b, double* const* x,
                                        double tol, const ipdg_solve_opts* opts, int* iters,
                                        double* relres, void* hip_stream);
 
 /* dL/dkappa_e = -w^T (dA/dkappa_e) u for device FP64 vectors u, w;
- * dLdkappa is a device array of K doubles. */
+ * dLdkappa is a device array of K doubles.  On a mesh without a
+ * coefficient the derivative is taken at kappa = 1 (the mesh is not
+ * changed). */
 ipdg_status ipdg_kappa_grad(ipdg_mesh mesh, double tau, const double* u, const double* w,
                             double* dLdkappa, void* hip_stream);
 

@@ -33,6 +33,26 @@ ipdg_status guarded(F&& f) {
 
 ipdg::Kind kind_of(ipdg_dtype d) { return d == IPDG_F32 ? ipdg::Kind::F32 : ipdg::Kind::F64; }
 
+// Makes the mesh's device current for the duration of a call (device
+// buffers, operator tables and streams of a mesh live on the device that was
+// current when it was created) and restores the caller's device.
+class DeviceGuard {
+ public:
+  explicit DeviceGuard(const ipdg_mesh_s* m) {
+    IPDG_HIP(hipGetDevice(&prev_));
+    if (prev_ != m->device) IPDG_HIP(hipSetDevice(m->device));
+    else prev_ = -1;
+  }
+  ~DeviceGuard() {
+    if (prev_ >= 0) (void)hipSetDevice(prev_);
+  }
+  DeviceGuard(const DeviceGuard&) = delete;
+  DeviceGuard& operator=(const DeviceGuard&) = delete;
+
+ private:
+  int prev_ = -1;
+};
+
 void upload_kappa(ipdg_mesh_s* m, const double* kappa) {
   const int K = m->host.K;
   if (!kappa) {
@@ -114,6 +134,8 @@ ipdg_status ipdg_mesh_create(int N, int Nv, const double* VX, const double* VY, 
 
 ipdg_status ipdg_mesh_destroy(ipdg_mesh mesh) {
   return guarded([&]() -> ipdg_status {
+    if (!mesh) return IPDG_OK;
+    DeviceGuard dg(mesh);
     delete mesh;
     return IPDG_OK;
   });
@@ -141,6 +163,7 @@ ipdg_status ipdg_node_coords(ipdg_mesh mesh, double* x, double* y) {
 ipdg_status ipdg_set_kappa(ipdg_mesh mesh, const double* kappa) {
   return guarded([&]() -> ipdg_status {
     if (!mesh) return fail(IPDG_EINVAL, "mesh is null");
+    DeviceGuard dg(mesh);
     upload_kappa(mesh, kappa);
     return IPDG_OK;
   });
@@ -154,6 +177,7 @@ ipdg_status ipdg_apply(ipdg_mesh mesh, double lambda, double tau, ipdg_dtype dty
     if (mesh->host.K == 0) return IPDG_OK;
     if (!x || !y) return fail(IPDG_EINVAL, "null vector");
     if (x == y) return fail(IPDG_EINVAL, "x and y must not overlap");
+    DeviceGuard dg(mesh);
     const int N = mesh->host.N;
     const ipdg::Kind k = kind_of(dtype);
     ipdg::ElemArgs a = ipdg::elem_args(mesh, N, k, lambda, ipdg::ctau_of(N, tau));
@@ -171,6 +195,7 @@ ipdg_status ipdg_mass_apply(ipdg_mesh mesh, ipdg_dtype dtype, const void* x, voi
     if (dtype != IPDG_F64 && dtype != IPDG_F32) return fail(IPDG_EINVAL, "bad dtype");
     if (mesh->host.K == 0) return IPDG_OK;
     if (!x || !y) return fail(IPDG_EINVAL, "null vector");
+    DeviceGuard dg(mesh);
     const int N = mesh->host.N;
     const ipdg::Kind k = kind_of(dtype);
     ipdg::ElemArgs a = ipdg::elem_args(mesh, N, k, 0.0, 0.0);
@@ -186,6 +211,7 @@ ipdg_status ipdg_pcg_solve(ipdg_mesh mesh, double lambda, double tau, const doub
                            void* hip_stream) {
   return guarded([&]() -> ipdg_status {
     if (!mesh) return fail(IPDG_EINVAL, "mesh is null");
+    DeviceGuard dg(mesh);
     ipdg_solve_opts o;
     if (opts) o = *opts;
     else ipdg_default_opts(&o);
@@ -199,6 +225,7 @@ ipdg_status ipdg_precond_apply(ipdg_mesh mesh, double lambda, double tau,
                                ipdg_solve_info* info, void* hip_stream) {
   return guarded([&]() -> ipdg_status {
     if (!mesh) return fail(IPDG_EINVAL, "mesh is null");
+    DeviceGuard dg(mesh);
     ipdg_solve_opts o;
     if (opts) o = *opts;
     else ipdg_default_opts(&o);
@@ -215,6 +242,12 @@ ipdg_status ipdg_helmholtz_solve_batch(int nb, const ipdg_mesh* meshes, const do
     if (nb < 0) return fail(IPDG_EINVAL, "nb < 0");
     if (nb == 0) return IPDG_OK;
     if (!meshes || !lambdas || !b || !x) return fail(IPDG_EINVAL, "null argument");
+    for (int i = 0; i < nb; ++i) {
+      if (!meshes[i]) return fail(IPDG_EINVAL, "null mesh in batch");
+      if (meshes[i]->device != meshes[0]->device)
+        return fail(IPDG_EINVAL, "all meshes of a batch must live on one device");
+    }
+    DeviceGuard dg(meshes[0]);
     ipdg_solve_opts o;
     if (opts) o = *opts;
     else {
@@ -232,13 +265,21 @@ ipdg_status ipdg_kappa_grad(ipdg_mesh mesh, double tau, const double* u, const d
     if (!mesh) return fail(IPDG_EINVAL, "mesh is null");
     if (mesh->host.K == 0) return IPDG_OK;
     if (!u || !w || !dLdkappa) return fail(IPDG_EINVAL, "null vector");
+    DeviceGuard dg(mesh);
     const int N = mesh->host.N;
+    const double* kap = mesh->kap64.as<double>();
     if (!mesh->has_kappa) {
-      std::vector<double> ones(mesh->host.K, 1.0);
-      upload_kappa(mesh, ones.data());
+      // kappa = 1: a device array of ones kept with the mesh (the mesh's
+      // operator stays the coefficient-free one)
+      if (!mesh->ones64.get()) {
+        std::vector<double> ones(mesh->host.K, 1.0);
+        mesh->ones64.ensure(mesh->host.K * sizeof(double));
+        IPDG_HIP(hipMemcpy(mesh->ones64.get(), ones.data(), mesh->host.K * sizeof(double),
+                           hipMemcpyHostToDevice));
+      }
+      kap = mesh->ones64.as<double>();
     }
-    ipdg::KgradArgs a{u, w, dLdkappa, mesh->geo64.as<double>(), mesh->conn.as<ipdg::Conn>(),
-                      mesh->kap64.as<double>(),
+    ipdg::KgradArgs a{u, w, dLdkappa, mesh->geo64.as<double>(), mesh->conn.as<ipdg::Conn>(), kap,
                       static_cast<const double*>(ipdg::device_ops(N, ipdg::Kind::F64)),
                       ipdg::ctau_of(N, tau), mesh->host.K};
     IPDG_HIP(ipdg::kgrad(N, a, static_cast<hipStream_t>(hip_stream)));

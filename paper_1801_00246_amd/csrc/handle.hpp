@@ -69,6 +69,7 @@ struct ipdg_mesh_s {
   std::vector<double> kappa;      // host copy (K) when has_kappa
   unsigned kappa_version = 0;     // changes whenever the coefficient values change
   ipdg::DevBuf geo64, geo32, conn, kap64, kap32;
+  ipdg::DevBuf ones64;            // kappa = 1 for the coefficient gradient of a plain mesh
   std::unique_ptr<ipdg::SolverWork> work;
   ~ipdg_mesh_s();
 };

@@ -104,3 +104,20 @@ def test_autograd_matches_central_differences():
         Lp = float(gpu_loss(g, dev(kap), dev(f + h * df), ut_t, lam, tol, opts))
         Lm = float(gpu_loss(g, dev(kap), dev(f - h * df), ut_t, lam, tol, opts))
         assert gf @ df == pytest.approx((Lp - Lm) / (2 * h), rel=1e-5)
+
+
+def test_kappa_grad_on_a_plain_mesh_leaves_it_plain():
+    """The coefficient gradient of a mesh without coefficient is taken at
+    kappa = 1 and does not turn the mesh into a coefficient mesh."""
+    N = 3
+    msh = synth.square_mesh(9, jitter=0.2, seed=41)
+    m = OracleMesh(msh.VX, msh.VY, msh.EToV, msh.EToB, N)
+    u = synth.nodal_normal(msh.K, m.Np, 42)
+    w = synth.nodal_normal(msh.K, m.Np, 43)
+    go = kappa_grad(m, float((N + 1) ** 2), np.ones(msh.K), u, w)
+    g = P.Mesh.from_synth(N, msh)
+    y0 = host(g.apply(dev(u), lam=2.0))
+    gg = host(g.kappa_grad(dev(u), dev(w)))
+    assert np.linalg.norm(gg - go) <= 1e-11 * np.linalg.norm(go)
+    y1 = host(g.apply(dev(u), lam=2.0))
+    assert np.array_equal(y0, y1)
