@@ -186,7 +186,7 @@ def cpu_baseline(N, lam, target_s=12.0):
                        f"took {t_asm:.1f}s (excluded)")}
 
 
-def run_pcg_compare(P, torch, coarse_caps=(200, 20)):
+def run_pcg_compare(P, torch, coarse_caps=(150, 300)):
     """PCG + p-multigrid (7 -> 3 -> 1) on 256 x 256 squares, N = 7, FP64 vs
     mixed precision, time to a true relative residual of 1e-8."""
     import numpy as np
