@@ -180,7 +180,8 @@ class PMG:
     """p-multigrid V-cycle on degrees ``degrees`` (fine first), Sec. 3."""
 
     def __init__(self, mesh, degrees, lam, ctau, rho, cheb_lo=0.1, cheb_hi=1.1,
-                 cheb_degree=2, coarse_tol=1e-2, coarse_max=200, coarse_exact=False):
+                 cheb_degree=2, coarse_tol=1e-2, coarse_max=200, coarse_exact=False,
+                 coarse_amg=False, amg_cycles=1, amg_coarse_size=1024):
         self.degrees = list(degrees)
         N0 = self.degrees[0]
         self.levels = []
@@ -199,6 +200,14 @@ class PMG:
         self.coarse_tol, self.coarse_max = coarse_tol, coarse_max
         self.coarse_exact = coarse_exact
         self.coarse_iters = []
+        self.amg = None
+        self.amg_cycles = amg_cycles
+        if coarse_amg:
+            # the algebraic levels below the degree-1 level (pMG-AMG, Sec. 3)
+            from .amg import AMG
+            L = self.levels[-1]
+            self.amg = AMG(L["m"], L["A"], self.rho[-1], cheb_lo, cheb_hi, cheb_degree,
+                           coarse_size=amg_coarse_size)
 
     def smooth(self, l, f, x0):
         L = self.levels[l]
@@ -207,6 +216,8 @@ class PMG:
     def vcycle(self, l, r):
         L = self.levels[l]
         if l == len(self.levels) - 1:
+            if self.amg is not None:
+                return self.amg.solve(r, self.amg_cycles)
             if self.coarse_exact:
                 import scipy.sparse.linalg as spla
                 return spla.spsolve(L["A"].tocsc(), r)
