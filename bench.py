@@ -36,8 +36,8 @@ FP32_PEAK_TFS = 157.3          # vector FP32, published
 # rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE), each scaled by the
 # counter's reading for a device-to-device copy of known size.  Valid only for
 # the kernel sources it was measured on (their SHA-256), else reported null.
-MEASURED_TRAFFIC = {"N": 3, "dtype": "f64", "lambda": 100.0, "bytes": 113182116,
-                    "sources_sha256": "6c4361e4f75ebe62bc4f17397c87f55b33f42ac7e40eed4ac685e98aa4d357cb",
+MEASURED_TRAFFIC = {"N": 3, "dtype": "f64", "lambda": 100.0, "bytes": 113061729,
+                    "sources_sha256": "c3507fa25f1cd24427803bdd955b12a1587d8cdf1598298090aa1e701ce06404",
                     "profile": "profiles/k_ax_N3_f64_524288.md"}
 
 KERNEL_SOURCES = ("elem_inst.hip", "sipdg_core.hpp", "tri.hpp", "device_common.hpp",

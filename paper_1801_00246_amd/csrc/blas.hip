@@ -290,61 +290,6 @@ __global__ __launch_bounds__(kBlock) void k_cg_pupdate(T* __restrict__ p, const 
 }
 
 // reciprocal of the diagonal (in place) and an optional FP32 copy
-// Sum of slot `slot` of the partials over nparts entries, returned to every
-// thread of the block; every block that calls it gets the same value (same
-// order), so all blocks take the same decisions from it.
-__device__ double block_total(const double* __restrict__ partials, int slot, int nparts) {
-  __shared__ double tot;
-  double v[1] = {0.0};
-  for (int i = threadIdx.x; i < nparts; i += kBlock) v[0] += partials[slot * kMaxPartials + i];
-  block_sum<1>(v);
-  if (threadIdx.x == 0) tot = v[0];
-  __syncthreads();
-  const double t = tot;
-  __syncthreads();
-  return t;
-}
-
-// Second launch of a coarse Jacobi-PCG iteration `it` (the first is the
-// operator launch k_coarse_step, which formed p and wrote (p, Ap) partials to
-// slot 2): every block reduces those itself, alpha = rz / (p, Ap) with rz in
-// sc->rzb[it % 2]; x += alpha p; r -= alpha Ap; z = dinv r; partials (r, r),
-// (r, z) in slots 0, 1.  Block 0 records the iteration count.
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_cg_update_red(T* __restrict__ x, T* __restrict__ r,
-                                                          const T* __restrict__ p, const T* __restrict__ Ap,
-                                                          const T* __restrict__ dinv, T* __restrict__ z,
-                                                          CGScal* __restrict__ sc, size_t n,
-                                                          double* __restrict__ partials, int nAp, int it) {
-  if (sc->done) return;
-  const double pAp = block_total(partials, 2, nAp);
-  const bool b0 = blockIdx.x == 0 && threadIdx.x == 0;
-  if (!(pAp > 0.0) || !isfinite(pAp)) {
-    if (b0) {
-      sc->breakdown = 1;
-      sc->done = 1;
-    }
-    return;
-  }
-  if (b0) sc->iters = it + 1;
-  const T alpha = static_cast<T>(sc->rzb[it & 1] / pAp);
-  double v[2] = {0.0, 0.0};
-  for (size_t i = blockIdx.x * (size_t)kBlock + threadIdx.x; i < n; i += (size_t)gridDim.x * kBlock) {
-    x[i] += alpha * p[i];
-    const T ri = r[i] - alpha * Ap[i];
-    r[i] = ri;
-    const T zi = dinv[i] * ri;
-    z[i] = zi;
-    v[0] += double(ri) * double(ri);
-    v[1] += double(ri) * double(zi);
-  }
-  block_sum<2>(v);
-  if (threadIdx.x == 0) {
-    partials[0 * kMaxPartials + blockIdx.x] = v[0];
-    partials[1 * kMaxPartials + blockIdx.x] = v[1];
-  }
-}
-
 __global__ __launch_bounds__(kBlock) void k_recip(double* __restrict__ d, float* __restrict__ d32, size_t n) {
   for (size_t i = blockIdx.x * (size_t)kBlock + threadIdx.x; i < n; i += (size_t)gridDim.x * kBlock) {
     const double v = 1.0 / d[i];
@@ -461,25 +406,6 @@ hipError_t cg_update_state(bool fp32, void* x, void* r, const void* p, const voi
 hipError_t cg_pupdate_state(bool fp32, void* p, const void* z, const CGScal* sc, size_t n, hipStream_t s) {
   if (fp32) LAUNCH(k_cg_pupdate<float>, n, s, (float*)p, (const float*)z, sc, n);
   else LAUNCH(k_cg_pupdate<double>, n, s, (double*)p, (const double*)z, sc, n);
-  return hipGetLastError();
-}
-
-int coarse_vec_grid(size_t n) {
-  const int b = flat_grid(n);
-  return b > kCoarseVecBlocks ? kCoarseVecBlocks : b;
-}
-
-hipError_t cg_update_red(bool fp32, void* x, void* r, const void* p, const void* Ap, const void* dinv,
-                         void* z, CGScal* sc, size_t n, double* partials, int nAp, int it, hipStream_t s) {
-  const int g = coarse_vec_grid(n);
-  if (fp32)
-    hipLaunchKernelGGL(k_cg_update_red<float>, dim3(g), dim3(kBlock), 0, s, (float*)x, (float*)r,
-                       (const float*)p, (const float*)Ap, (const float*)dinv, (float*)z, sc, n, partials, nAp,
-                       it);
-  else
-    hipLaunchKernelGGL(k_cg_update_red<double>, dim3(g), dim3(kBlock), 0, s, (double*)x, (double*)r,
-                       (const double*)p, (const double*)Ap, (const double*)dinv, (double*)z, sc, n, partials,
-                       nAp, it);
   return hipGetLastError();
 }
 

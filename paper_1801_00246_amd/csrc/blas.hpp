@@ -10,7 +10,8 @@ namespace ipdg {
 struct CGScal {
   double rz = 0, pAp = 0, alpha = 0, beta = 0, rr = 0, bb = 0, tol = 0, tol2 = 0;
   int done = 0, breakdown = 0, iters = 0, max_iters = 0, flexible = 0, pad = 0;
-  double rzb[2] = {0, 0};   // coarse solve: (r, z) by iteration parity
+  double rzb[2] = {0, 0};   // coarse solve: (r, u) by iteration parity
+  double ab[2] = {0, 0};    // coarse solve: alpha by iteration parity
 };
 
 // Partial-sum slots per reduction (>= blocks of any element or vector launch).
@@ -38,14 +39,6 @@ hipError_t cg_start_fin(const double* partials, int nparts, CGScal* sc, const in
 hipError_t cg_update_state(bool fp32, void* x, void* r, const void* p, const void* Ap, const void* dinv,
                            void* z, const CGScal* sc, size_t n, double* partials, hipStream_t s);
 hipError_t cg_pupdate_state(bool fp32, void* p, const void* z, const CGScal* sc, size_t n, hipStream_t s);
-// Coarse Jacobi-PCG iteration in two launches: the operator launch
-// (k_coarse_step, kernels.hpp) and this update, each reducing the previous
-// launch's block partials in every block: no finalize launch.  `it` is the
-// iteration index of the solve (fixed in a captured graph).
-constexpr int kCoarseVecBlocks = 512;
-int coarse_vec_grid(size_t n);
-hipError_t cg_update_red(bool fp32, void* x, void* r, const void* p, const void* Ap, const void* dinv,
-                         void* z, CGScal* sc, size_t n, double* partials, int nAp, int it, hipStream_t s);
 hipError_t recip(double* d, float* d32, size_t n, hipStream_t s);
 hipError_t set_scal(CGScal* sc, const CGScal& v, hipStream_t s);
 hipError_t zero_ints(void* p, int n, hipStream_t s);

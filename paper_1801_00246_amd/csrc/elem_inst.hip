@@ -472,40 +472,67 @@ __global__ __launch_bounds__(kBlock) void k_coarse_pcg(const T* __restrict__ f, 
   if (blockIdx.x == 0 && threadIdx.x == 0) status[0] = it;
 }
 
-// Sum of slot `slot` of the partials over nparts entries, returned to every
-// thread; every block gets the same value (same order).
-__device__ double slot_total(const double* __restrict__ partials, int slot, int nparts) {
-  __shared__ double tot;
-  double v[1] = {0.0};
-  for (int i = threadIdx.x; i < nparts; i += kBlock) v[0] += partials[slot * kMaxPartials + i];
-  block_sum<1>(v);
-  if (threadIdx.x == 0) tot = v[0];
+// Slots 0, 1, 2 of the partials summed over n0, n1, n2 entries (each at most
+// kMaxPartials), returned to every thread (the same values and order in every
+// block).  Every entry below the largest count is read unconditionally (the
+// slots are kMaxPartials long) and masked by a select, two strides per trip,
+// so that a thread's loads are all in flight before the first is waited on.
+__device__ void slot_totals3(const double* __restrict__ partials, int n0, int n1, int n2, double (&t)[3]) {
+  __shared__ double tot[3];
+  double v[3] = {0.0, 0.0, 0.0};
+  const int nm = n0 > n1 ? (n0 > n2 ? n0 : n2) : (n1 > n2 ? n1 : n2);
+  for (int i = threadIdx.x; i < nm; i += 2 * kBlock) {
+    const int j = i + kBlock < nm ? i + kBlock : i;
+    const double a0 = partials[i], a1 = partials[kMaxPartials + i], a2 = partials[2 * kMaxPartials + i];
+    const double b0 = partials[j], b1 = partials[kMaxPartials + j], b2 = partials[2 * kMaxPartials + j];
+    const bool two = j != i;
+    v[0] += (i < n0 ? a0 : 0.0) + (two && j < n0 ? b0 : 0.0);
+    v[1] += (i < n1 ? a1 : 0.0) + (two && j < n1 ? b1 : 0.0);
+    v[2] += (i < n2 ? a2 : 0.0) + (two && j < n2 ? b2 : 0.0);
+  }
+  block_sum<3>(v);
+  if (threadIdx.x == 0)
+    for (int k = 0; k < 3; ++k) tot[k] = v[k];
   __syncthreads();
-  const double t = tot;
+  for (int k = 0; k < 3; ++k) t[k] = tot[k];
   __syncthreads();
-  return t;
 }
 
-// p = z + beta p_old read on the fly (beta = 0: p = z)
+// Coarse Jacobi-PCG in the single-reduction form of Chronopoulos and Gear
+// (1989): with u = D^-1 r and w = A u, the recurrences
+//   p = u + beta p,  s = w + beta s (= A p),  x += alpha p,  r -= alpha s,
+//   u = D^-1 r,  w = A u,  gamma = (r, u),  delta = (w, u),
+//   beta = gamma / gamma_prev,  alpha = gamma / (delta - beta gamma / alpha_prev)
+// are textbook PCG rearranged so that one iteration needs one global
+// reduction: one launch per iteration.  The launch reads the reductions of
+// the previous one, updates its own elements and applies the operator to
+// the new u; the new u of a neighbour is formed on the fly from that
+// neighbour's previous r, w and s, which are double-buffered by iteration
+// parity (the launch writes the other copy).
+
+// u_new = D^-1 (r - alpha (w + beta s)) of any node, from the previous state
 template <typename T>
-struct AxpySrc {
-  const T* __restrict__ z;
-  const T* __restrict__ p;
-  T beta;
-  bool first;
-  __device__ __forceinline__ T operator()(size_t i) const { return first ? z[i] : z[i] + beta * p[i]; }
+struct NextUSrc {
+  const T* __restrict__ dinv;
+  const T* __restrict__ r;
+  const T* __restrict__ w;
+  const T* __restrict__ s;
+  T alpha, beta;
+  bool first;   // s = w
+  __device__ __forceinline__ T operator()(size_t i) const {
+    const T si = first ? w[i] : w[i] + beta * s[i];
+    return dinv[i] * (r[i] - alpha * si);
+  }
 };
 
 template <typename T, bool KAP>
-__global__ __launch_bounds__(kBlock) void k_coarse_step(const T* __restrict__ z, const T* __restrict__ p_old,
-                                                        T* __restrict__ p_new, T* __restrict__ Ap,
-                                                        const T* __restrict__ geo,
-                                                        const Conn* __restrict__ conn,
-                                                        const T* __restrict__ kap,
-                                                        const T* __restrict__ ops, T lambda, T ctau, int K,
-                                                        int per, double* __restrict__ partials, int nin,
-                                                        CGScal* __restrict__ sc, const int* __restrict__ outer,
-                                                        int it) {
+__global__ __launch_bounds__(kBlock) void k_coarse_cgcg(
+    T* __restrict__ x, T* __restrict__ p, T* __restrict__ u, const T* __restrict__ dinv,
+    const T* __restrict__ r_old, T* __restrict__ r_new, const T* __restrict__ w_old, T* __restrict__ w_new,
+    const T* __restrict__ s_old, T* __restrict__ s_new, const T* __restrict__ geo,
+    const Conn* __restrict__ conn, const T* __restrict__ kap, const T* __restrict__ ops, T lambda, T ctau,
+    int K, int per, const double* __restrict__ pin, int n_rr, int n_g, int n_d, double* __restrict__ pout,
+    CGScal* __restrict__ sc, const int* __restrict__ outer, int it) {
   const bool first = it == 0;
   const int par = it & 1;
   const bool b0 = blockIdx.x == 0 && threadIdx.x == 0;
@@ -517,52 +544,93 @@ __global__ __launch_bounds__(kBlock) void k_coarse_step(const T* __restrict__ z,
   } else if (sc->done) {
     return;
   }
-  const double rr = slot_total(partials, 0, nin);
-  const double rz = slot_total(partials, 1, nin);
-  T beta = T(0);
+  // The element's own state does not depend on alpha and beta: its loads
+  // are issued before the reduction so that the two latencies overlap.
+  const int e = xcd_tile(blockIdx.x, per) * kBlock + threadIdx.x;
+  const bool live = e < K;
+  const size_t o = (size_t)(live ? e : 0) * Np;
+  T r0[Np], w0[Np], s0[Np], d0[Np], p0[Np], x0[Np], u0[Np];
+  if (live) {
+#pragma unroll
+    for (int j = 0; j < Np; ++j) {
+      r0[j] = r_old[o + j];
+      w0[j] = w_old[o + j];
+      d0[j] = dinv[o + j];
+      x0[j] = x[o + j];
+      u0[j] = u[o + j];
+      s0[j] = s_old[o + j];   // unused (and possibly unset) at it = 0
+      p0[j] = p[o + j];
+    }
+  }
+  double tot[3];
+  slot_totals3(pin, n_rr, n_g, n_d, tot);
+  const double rr = tot[0], gam = tot[1], del = tot[2];
+  double alpha, beta = 0.0;
   if (first) {
     const bool stop = !(rr > 0.0) || sc->max_iters <= 0;
+    alpha = gam / del;
+    const bool bad = !stop && !(del > 0.0 && isfinite(alpha));
     if (b0) {
       sc->tol2 = sc->tol * sc->tol * rr;
       sc->rr = rr;
-      sc->rzb[par] = rz;
       sc->iters = 0;
-      sc->breakdown = 0;
-      sc->done = stop ? 1 : 0;
+      sc->breakdown = bad ? 1 : 0;
+      sc->done = (stop || bad) ? 1 : 0;
+      sc->rzb[par] = gam;
+      sc->ab[par] = alpha;
     }
-    if (stop) return;
+    if (stop || bad) return;
   } else {
     const bool stop = rr <= sc->tol2 || !isfinite(rr);
+    beta = gam / sc->rzb[1 - par];
+    const double den = del - beta * gam / sc->ab[1 - par];
+    alpha = gam / den;
+    const bool bad = !stop && !(den > 0.0 && isfinite(alpha));
     if (b0) {
       sc->rr = rr;
-      sc->rzb[par] = rz;
-      if (stop) sc->done = 1;
+      sc->rzb[par] = gam;
+      sc->ab[par] = alpha;
+      if (bad) sc->breakdown = 1;
+      if (stop || bad) sc->done = 1;
     }
-    if (stop) return;
-    beta = static_cast<T>(rz / sc->rzb[1 - par]);
+    if (stop || bad) return;
   }
-  const AxpySrc<T> src{z, p_old, beta, first};
-  const int e = xcd_tile(blockIdx.x, per) * kBlock + threadIdx.x;
-  double dot = 0.0;
-  if (e < K) {
-    T u[Np];
-    T* pe = p_new + (size_t)e * Np;
-    T* ye = Ap + (size_t)e * Np;
+  if (b0) sc->iters = it + 1;
+  const T a = static_cast<T>(alpha), b = static_cast<T>(beta);
+  const NextUSrc<T> src{dinv, r_old, w_old, s_old, a, b, first};
+  double v[3] = {0.0, 0.0, 0.0};
+  if (live) {
+    T ue[Np], rn[Np];
     sipdg_element_src<N, T, KAP, false>(
-        e, src, geo, conn, kap, ops, lambda, ctau, 0, u,
-        [&](int i, T v) {
-          ye[i] = v;
-          dot += double(pe[i]) * double(v);
+        e, src, geo, conn, kap, ops, lambda, ctau, 0, ue,
+        [&](int i, T wi) {
+          w_new[o + i] = wi;
+          const double ri = double(rn[i]), ui = double(ue[i]);
+          v[0] += ri * ri;
+          v[1] += ri * ui;
+          v[2] += double(wi) * ui;
         },
         [&](int j) {
-          const T pj = src((size_t)e * Np + j);
-          pe[j] = pj;
-          return pj;
+          const size_t k = o + j;
+          const T pj = first ? u0[j] : u0[j] + b * p0[j];
+          const T sj = first ? w0[j] : w0[j] + b * s0[j];
+          p[k] = pj;
+          s_new[k] = sj;
+          x[k] = x0[j] + a * pj;
+          const T rj = r0[j] - a * sj;
+          r_new[k] = rj;
+          rn[j] = rj;
+          const T uj = d0[j] * rj;
+          u[k] = uj;
+          return uj;
         });
   }
-  double v[1] = {dot};
-  block_sum<1>(v);
-  if (threadIdx.x == 0) partials[2 * kMaxPartials + blockIdx.x] = v[0];
+  block_sum<3>(v);
+  if (threadIdx.x == 0) {
+    pout[0 * kMaxPartials + blockIdx.x] = v[0];
+    pout[1 * kMaxPartials + blockIdx.x] = v[1];
+    pout[2 * kMaxPartials + blockIdx.x] = v[2];
+  }
 }
 
 template <typename T>
@@ -571,16 +639,14 @@ hipError_t run_coarse_step(const CoarseStepArgs& a, hipStream_t s) {
   int per;
   const int grid = xcd_grid(elem_tiles(o.K), per);
   if (o.K == 0) return hipSuccess;
-  if (o.kap)
-    hipLaunchKernelGGL((k_coarse_step<T, true>), dim3(grid), dim3(kBlock), 0, s, (const T*)a.z,
-                       (const T*)a.p_old, (T*)a.p_new, (T*)a.Ap, (const T*)o.geo, o.conn, (const T*)o.kap,
-                       (const T*)o.ops, T(o.lambda), T(o.ctau), o.K, per, a.partials, a.nin, a.sc, a.outer,
-                       a.it);
-  else
-    hipLaunchKernelGGL((k_coarse_step<T, false>), dim3(grid), dim3(kBlock), 0, s, (const T*)a.z,
-                       (const T*)a.p_old, (T*)a.p_new, (T*)a.Ap, (const T*)o.geo, o.conn, (const T*)o.kap,
-                       (const T*)o.ops, T(o.lambda), T(o.ctau), o.K, per, a.partials, a.nin, a.sc, a.outer,
-                       a.it);
+  auto go = [&](auto kern) {
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(kBlock), 0, s, (T*)a.x, (T*)a.p, (T*)a.u, (const T*)a.dinv,
+                       (const T*)a.r_old, (T*)a.r_new, (const T*)a.w_old, (T*)a.w_new, (const T*)a.s_old,
+                       (T*)a.s_new, (const T*)o.geo, o.conn, (const T*)o.kap, (const T*)o.ops, T(o.lambda),
+                       T(o.ctau), o.K, per, a.pin, a.n_rr, a.n_g, a.n_d, a.pout, a.sc, a.outer, a.it);
+  };
+  if (o.kap) go(k_coarse_cgcg<T, true>);
+  else go(k_coarse_cgcg<T, false>);
   return hipGetLastError();
 }
 

@@ -93,20 +93,28 @@ struct CoarseArgs {
 template <int N> hipError_t launch_coarse_pcg(Kind kind, const CoarseArgs& a, int grid, hipStream_t s);
 template <int N> int coarse_pcg_grid(Kind kind, int K);   // resident grid size, 0 if unsupported
 
-// First launch of a coarse Jacobi-PCG iteration `it` (the second is
-// cg_update_red): every block reduces the (r, r), (r, z) partials of the
-// previous launch (slots 0, 1, nin entries), records the stop in sc, else
-// forms p = z + beta p_old on the fly (p = z at it = 0), writes it to p_new
-// and computes Ap = A p with the (p, Ap) block partials in slot 2.
+// One launch of the coarse Jacobi-PCG in single-reduction form (iteration
+// `it`): every block reduces the (r, r), (r, u), (w, u) partials of the
+// previous launch (pin slots 0..2 with n_rr, n_g, n_d entries), records the
+// stop in sc, else updates p, s, x, r, u of its elements, forms the new u of
+// the neighbours on the fly, writes w = A u and the next partials to pout.
+// r, w, s are double-buffered by the caller (old / new by parity).
 struct CGScal;
 struct CoarseStepArgs {
-  const void* z = nullptr;
-  const void* p_old = nullptr;
-  void* p_new = nullptr;
-  void* Ap = nullptr;
+  void* x = nullptr;
+  void* p = nullptr;
+  void* u = nullptr;
+  const void* dinv = nullptr;
+  const void* r_old = nullptr;
+  void* r_new = nullptr;
+  const void* w_old = nullptr;
+  void* w_new = nullptr;
+  const void* s_old = nullptr;
+  void* s_new = nullptr;
   ElemArgs op;                 // operator of the level (x, y, partials unused)
-  double* partials = nullptr;  // 3 x kMaxPartials
-  int nin = 0;
+  const double* pin = nullptr;
+  int n_rr = 0, n_g = 0, n_d = 0;
+  double* pout = nullptr;
   CGScal* sc = nullptr;
   const int* outer = nullptr;  // outer solve's done flag (checked at it = 0)
   int it = 0;

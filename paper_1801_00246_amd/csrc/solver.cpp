@@ -51,7 +51,8 @@ struct Level {
   Kind kind = Kind::F64;
   DevBuf dinv64, dinv32;
   DevBuf f, z, r, d, t;            // V-cycle work (level precision)
-  DevBuf cr, cz, cp, cp2, cAp;     // coarsest level: Jacobi-PCG work (p by parity)
+  DevBuf cr, cr2, cz, cp, cp2, cs2, cAp, cw2;   // coarsest level: Jacobi-PCG work
+                                               // (r, w, s double-buffered)
   const void* P = nullptr;         // interpolation from the next level
   const void* dinv() const { return fp32 ? dinv32.get() : dinv64.get(); }
 };
@@ -347,7 +348,7 @@ class Solver {
     w.Ap.ensure(n_ * 8);
     w.z.ensure(n_ * (mixed_ ? 4 : 8));
     w.partials.ensure(3 * kMaxPartials * sizeof(double));
-    w.cpartials.ensure(3 * kMaxPartials * sizeof(double));
+    w.cpartials.ensure(6 * kMaxPartials * sizeof(double));
     w.scal.ensure(sizeof(CGScal));
     w.cscal.ensure(sizeof(CGScal));
     if (!w.host_scal) IPDG_HIP(hipHostMalloc(reinterpret_cast<void**>(&w.host_scal), sizeof(CGScal)));
@@ -427,6 +428,9 @@ class Solver {
         v.cp.ensure(v.n * w8);
         v.cp2.ensure(v.n * w8);
         v.cAp.ensure(v.n * w8);
+        v.cr2.ensure(v.n * w8);
+        v.cw2.ensure(v.n * w8);
+        v.cs2.ensure(v.n * w8);
         if (!v.z.get()) v.z.ensure(v.n * w8);
       }
       if (l > 0) w.lv[l - 1].P = device_interp(v.N, w.lv[l - 1].N, mixed_);
@@ -654,26 +658,43 @@ class Solver {
       return;
     }
     CGScal* sc = w.cscal.as<CGScal>();
-    double* part = w.cpartials.as<double>();
-    // x = 0, r = f, z = D^-1 f and the (r, r), (r, z) partials
-    IPDG_HIP(cg_start0(v.fp32, f, v.dinv(), x, v.cr.get(), v.cz.get(), v.cp.get(), v.n, part,
-                       outer_done(), s_));
+    double* part = w.cpartials.as<double>();     // two sets of 3 partial slots
+    double* set[2] = {part, part + 3 * (size_t)kMaxPartials};
+    void* rb[2] = {v.cr.get(), v.cr2.get()};
+    void* wb[2] = {v.cAp.get(), v.cw2.get()};
+    void* sb[2] = {v.cp2.get(), v.cs2.get()};
+    // x = 0, r = f, u = D^-1 f and the (r, r), (r, u) partials (set 0, slots 0, 1)
+    IPDG_HIP(cg_start0(v.fp32, f, v.dinv(), x, rb[0], v.cz.get(), v.cp.get(), v.n, part, outer_done(), s_));
+    // w = A u and the (u, w) partials (set 0, slot 2)
+    ElemArgs a = elem_args(m_, v.N, v.kind, lambda_, v.ctau);
+    a.x = v.cz.get();
+    a.y = wb[0];
+    a.partials = part + 2 * (size_t)kMaxPartials;
+    a.skip = outer_done();
+    IPDG_HIP(ax(v.N, v.kind, a, s_));
     CoarseStepArgs ca;
-    ca.z = v.cz.get();
-    ca.Ap = v.cAp.get();
+    ca.x = x;
+    ca.p = v.cp.get();
+    ca.u = v.cz.get();
+    ca.dinv = v.dinv();
     ca.op = elem_args(m_, v.N, v.kind, lambda_, v.ctau);
-    ca.partials = part;
     ca.sc = sc;
     ca.outer = outer_done();
-    void* pb[2] = {v.cp.get(), v.cp2.get()};   // p by iteration parity
+    const int ne = elem_grid(K_);
     for (int it = 0; it < o_.coarse_max_iters; ++it) {
+      const int o = it & 1, nw = 1 - o;
       ca.it = it;
-      ca.p_new = pb[it & 1];
-      ca.p_old = pb[(it + 1) & 1];
-      ca.nin = it == 0 ? flat_grid(v.n) : coarse_vec_grid(v.n);
+      ca.r_old = rb[o];
+      ca.r_new = rb[nw];
+      ca.w_old = wb[o];
+      ca.w_new = wb[nw];
+      ca.s_old = sb[o];
+      ca.s_new = sb[nw];
+      ca.pin = set[o];
+      ca.pout = set[nw];
+      ca.n_rr = ca.n_g = it == 0 ? flat_grid(v.n) : ne;
+      ca.n_d = ne;
       IPDG_HIP(coarse_step(v.N, v.kind, ca, s_));
-      IPDG_HIP(cg_update_red(v.fp32, x, v.cr.get(), pb[it & 1], v.cAp.get(), v.dinv(), v.cz.get(), sc, v.n,
-                             part, elem_grid(K_), it, s_));
     }
   }
 

@@ -129,6 +129,28 @@ def test_one_vcycle_matches_oracle():
     assert rel32 <= 1e-4
 
 
+def test_vcycle_coarse_tolerance_stop_matches_oracle():
+    """Coarsest-level Jacobi-PCG stopped by its relative tolerance well before
+    its cap: the same number of coarse iterations and the same V-cycle output
+    as the oracle's PCG, whose test is ||r|| <= tol ||r0|| (Sec. 3)."""
+    degrees = (3, 1)
+    msh = synth.permuted(synth.square_mesh(12, jitter=0.2, seed=6), seed=7)
+    ctau = 16.0
+    rho = [1.8, 1.6]
+    r = synth.nodal_normal(msh.K, 10, seed=11)
+    g = P.Mesh.from_synth(3, msh)
+    for tol in (0.3, 0.05):
+        B = S.PMG(msh, degrees, 1.0, ctau, rho, coarse_tol=tol, coarse_max=500)
+        zo = B(r)
+        z, info = g.precond(dev(r), lam=1.0, tau=ctau, opts=pmg_opts(degrees, rho, coarse_tol=tol,
+                                                                  coarse_max=500))
+        print(f"tol {tol}: coarse iterations {info['coarse_iters']} (oracle {B.coarse_iters})")
+        assert 0 < B.coarse_iters[-1] < 500
+        assert info["coarse_iters"] == B.coarse_iters[-1]
+        z = host(z)
+        assert np.linalg.norm(z - zo) <= 1e-11 * np.linalg.norm(zo)
+
+
 def test_lanczos_estimate_is_close_to_the_oracle_spectrum():
     msh, m, A, b, ctau = problem(8, 3, jitter=0.2)
     g = P.Mesh.from_synth(3, msh)
