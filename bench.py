@@ -37,7 +37,7 @@ FP32_PEAK_TFS = 157.3          # vector FP32, published
 # counter's reading for a device-to-device copy of known size.  Valid only for
 # the kernel sources it was measured on (their SHA-256), else reported null.
 MEASURED_TRAFFIC = {"N": 3, "dtype": "f64", "lambda": 100.0, "bytes": 113061729,
-                    "sources_sha256": "c3507fa25f1cd24427803bdd955b12a1587d8cdf1598298090aa1e701ce06404",
+                    "sources_sha256": "b44f25942c4285458565f7c0480ffc2f3ff2532fd2a51fb2e0178cb7f040c660",
                     "profile": "profiles/k_ax_N3_f64_524288.md"}
 
 KERNEL_SOURCES = ("elem_inst.hip", "sipdg_core.hpp", "tri.hpp", "device_common.hpp",

@@ -525,6 +525,25 @@ struct NextUSrc {
   }
 };
 
+// The same values for the three neighbours, face by face in the element
+// template's rotated order, formed from raw values loaded in advance.
+template <typename T>
+struct NextUFaces {
+  static constexpr bool kPerFace = true;
+  T v[3][Np];
+  T m[4][5];   // metric (r_x, s_x, r_y, s_y) and coefficient: the element's, then
+               // face 0, 1, 2's neighbour's
+  template <int f, int j>
+  __device__ __forceinline__ T at() const { return v[f][j]; }
+  __device__ __forceinline__ T own_metric(int k) const { return m[0][k]; }
+  template <int f>
+  __device__ __forceinline__ T nbr_metric(int k) const { return m[1 + f][k]; }
+};
+
+// Low degrees load the neighbours' raw r, w, s, D^-1 before the reduction too
+// (4 x 3 Np values per lane); higher degrees read them after it.
+constexpr bool kCoarsePrefetch = N <= 2;
+
 template <typename T, bool KAP>
 __global__ __launch_bounds__(kBlock) void k_coarse_cgcg(
     T* __restrict__ x, T* __restrict__ p, T* __restrict__ u, const T* __restrict__ dinv,
@@ -562,6 +581,35 @@ __global__ __launch_bounds__(kBlock) void k_coarse_cgcg(
       p0[j] = p[o + j];
     }
   }
+  T nd[3][Np], nr[3][Np], nw[3][Np], ns[3][Np];
+  NextUFaces<T> pre;
+  if constexpr (kCoarsePrefetch) {
+    if (live) {
+      // (the connectivity is read again by the element computation: this
+      // load leaves it in cache)
+      const Conn c = conn[e];
+      auto metric = [&](int el, T (&mm)[5]) {
+        for (int k = 0; k < 4; ++k) mm[k] = geo[4 * el + k];
+        mm[4] = KAP ? kap[el] : T(1);
+      };
+      metric(e, pre.m[0]);
+      for (int f = 0; f < 3; ++f) metric(c.nb[f], pre.m[1 + f]);
+      static_for<0, 3>([&](auto fc) {
+        constexpr int f = decltype(fc)::value;
+        const int fp = conn_fp(c.info, f);
+        const size_t xn = (size_t)c.nb[f] * Np;
+        static_for<0, Np>([&](auto jc) {
+          constexpr int j = decltype(jc)::value;
+          constexpr int o1 = Tri<N>::rot(1, j), o2 = Tri<N>::rot(2, j);
+          const size_t i = xn + (fp == 0 ? j : (fp == 1 ? o1 : o2));
+          nd[f][j] = dinv[i];
+          nr[f][j] = r_old[i];
+          nw[f][j] = w_old[i];
+          ns[f][j] = s_old[i];
+        });
+      });
+    }
+  }
   double tot[3];
   slot_totals3(pin, n_rr, n_g, n_d, tot);
   const double rr = tot[0], gam = tot[1], del = tot[2];
@@ -597,11 +645,11 @@ __global__ __launch_bounds__(kBlock) void k_coarse_cgcg(
   }
   if (b0) sc->iters = it + 1;
   const T a = static_cast<T>(alpha), b = static_cast<T>(beta);
-  const NextUSrc<T> src{dinv, r_old, w_old, s_old, a, b, first};
   double v[3] = {0.0, 0.0, 0.0};
   if (live) {
     T ue[Np], rn[Np];
-    sipdg_element_src<N, T, KAP, false>(
+    auto run = [&](const auto& src) {
+      sipdg_element_src<N, T, KAP, false>(
         e, src, geo, conn, kap, ops, lambda, ctau, 0, ue,
         [&](int i, T wi) {
           w_new[o + i] = wi;
@@ -624,6 +672,19 @@ __global__ __launch_bounds__(kBlock) void k_coarse_cgcg(
           u[k] = uj;
           return uj;
         });
+    };
+    if constexpr (kCoarsePrefetch) {
+#pragma unroll
+      for (int f = 0; f < 3; ++f)
+#pragma unroll
+        for (int j = 0; j < Np; ++j) {
+          const T sj = first ? nw[f][j] : nw[f][j] + b * ns[f][j];
+          pre.v[f][j] = nd[f][j] * (nr[f][j] - a * sj);
+        }
+      run(pre);
+    } else {
+      run(NextUSrc<T>{dinv, r_old, w_old, s_old, a, b, first});
+    }
   }
   block_sum<3>(v);
   if (threadIdx.x == 0) {

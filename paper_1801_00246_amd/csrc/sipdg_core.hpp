@@ -42,6 +42,25 @@ namespace ipdg {
 template <typename TX, typename TC>
 __host__ __device__ __forceinline__ TC ld(const TX* p) { return static_cast<TC>(*p); }
 
+// Entry k of the element's metric (r_x, s_x, r_y, s_y), or with k = -1 its
+// coefficient, from a per-face source (own_metric(k), k = 4 for the
+// coefficient) or from memory (g = metric or coefficient array).
+template <bool PF, typename TC, typename Src>
+__host__ __device__ __forceinline__ TC own_metric(const Src& src, const TC* __restrict__ g, int e, int k) {
+  if constexpr (PF) return src.own_metric(k < 0 ? 4 : k);
+  else return k < 0 ? g[e] : g[4 * e + k];
+}
+
+// A source that already holds the neighbours' values, face by face in the
+// rotated order below, declares kPerFace and serves them through at<f, j>()
+// instead of a node index, the element's metric and coefficient through
+// own_metric(k) and each neighbour's through nbr_metric<f>(k), so that those
+// loads can be issued ahead of the element computation.
+template <typename S, typename = void>
+struct PerFaceSrc { static constexpr bool value = false; };
+template <typename S>
+struct PerFaceSrc<S, decltype(void(S::kPerFace))> { static constexpr bool value = S::kPerFace; };
+
 // A zero the optimiser cannot see through.  Added to the operator offsets of
 // one phase (a face, a face node, an output row), it keeps that phase's
 // scalar operator loads from being hoisted to the top of the kernel, where
@@ -88,9 +107,11 @@ __host__ __device__ __forceinline__ void sipdg_element_src(int e, const Src& src
   using G = Tri<N>;
   using L = OpsLayout<N>;
   constexpr int Np = G::Np, Nfp = G::Nfp;
-  const TC rx = geo[4 * e + 0], sx = geo[4 * e + 1], ry = geo[4 * e + 2], sy = geo[4 * e + 3];
+  constexpr bool PF = PerFaceSrc<Src>::value;
+  const TC rx = own_metric<PF>(src, geo, e, 0), sx = own_metric<PF>(src, geo, e, 1);
+  const TC ry = own_metric<PF>(src, geo, e, 2), sy = own_metric<PF>(src, geo, e, 3);
   const TC J = TC(1) / (rx * sy - sx * ry);
-  const TC ke = KAP ? kap[e] : TC(1);
+  const TC ke = KAP ? own_metric<PF>(src, kap, e, -1) : TC(1);
   const Conn c = conn[e];
 
 #pragma unroll
@@ -121,14 +142,22 @@ __host__ __device__ __forceinline__ void sipdg_element_src(int e, const Src& src
     // fp at face 0
     auto nbr_value = [&](auto jc) -> TC {
       constexpr int j = decltype(jc)::value;
-      constexpr int o1 = G::rot(1, j), o2 = G::rot(2, j);
-      const int o = fp == 0 ? j : (fp == 1 ? o1 : o2);
-      return src(xn + o);
+      if constexpr (PF) {
+        return src.template at<f, j>();
+      } else {
+        constexpr int o1 = G::rot(1, j), o2 = G::rot(2, j);
+        const int o = fp == 0 ? j : (fp == 1 ? o1 : o2);
+        return src(xn + o);
+      }
     };
     TC xv[Np];
     if constexpr (EARLY && !DIAG) static_for<0, Np>([&](auto jc) { xv[decltype(jc)::value] = nbr_value(jc); });
-    const TC prx = geo[4 * nb + 0], psx = geo[4 * nb + 1], pry = geo[4 * nb + 2], psy = geo[4 * nb + 3];
-    const TC kp = KAP ? kap[nb] : TC(1);
+    auto nmetric = [&](int k) -> TC {
+      if constexpr (PF) return src.template nbr_metric<f>(k);
+      else return k < 4 ? geo[4 * nb + k] : (KAP ? kap[nb] : TC(1));
+    };
+    const TC prx = nmetric(0), psx = nmetric(1), pry = nmetric(2), psy = nmetric(3);
+    const TC kp = nmetric(4);
     if constexpr (EARLY) phase_fence();
     Fs[f] = sqrt(gx[f] * gx[f] + gy[f] * gy[f]);
     iFs[f] = TC(1) / Fs[f];
