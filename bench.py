@@ -36,8 +36,8 @@ FP32_PEAK_TFS = 157.3          # vector FP32, published
 # rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE), each scaled by the
 # counter's reading for a device-to-device copy of known size.  Valid only for
 # the kernel sources it was measured on (their SHA-256), else reported null.
-MEASURED_TRAFFIC = {"N": 3, "dtype": "f64", "lambda": 100.0, "bytes": 113061729,
-                    "sources_sha256": "b44f25942c4285458565f7c0480ffc2f3ff2532fd2a51fb2e0178cb7f040c660",
+MEASURED_TRAFFIC = {"N": 3, "dtype": "f64", "lambda": 100.0, "variant": 0, "bytes": 113061729,
+                    "sources_sha256": "f7bc97a34f0d23275292a9c0d8bda787976c3e8685c11a8b0da22a7f1c7b3cd0",
                     "profile": "profiles/k_ax_N3_f64_524288.md"}
 
 KERNEL_SOURCES = ("elem_inst.hip", "sipdg_core.hpp", "tri.hpp", "device_common.hpp",
@@ -54,9 +54,9 @@ def kernel_sources_sha():
     return h.hexdigest()
 
 
-def measured_traffic(N, dtype, lam):
+def measured_traffic(N, dtype, lam, variant):
     t = MEASURED_TRAFFIC
-    if not t or (t["N"], t["dtype"], t["lambda"]) != (N, dtype, lam):
+    if not t or (t["N"], t["dtype"], t["lambda"], t["variant"]) != (N, dtype, lam, variant):
         return None
     return t["bytes"] if t["sources_sha256"] == kernel_sources_sha() else None
 
@@ -336,6 +336,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-solve batched Helmholtz leg")
     ap.add_argument("--no-grad", action="store_true", help="skip the differentiable-solve leg")
     ap.add_argument("--sweep-orders", default="1,2,3,4,5,6,7,8")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="time the headline with the default operator variant instead of the tuned one")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
@@ -350,6 +352,16 @@ def main():
     dt = torch.float64 if args.dtype == "f64" else torch.float32
     w = 8 if args.dtype == "f64" else 4
     N = args.order
+    tuned = None
+    if not args.no_autotune:
+        # pick the operator variant for the headline degree and precision on this GPU
+        # (set-up, outside the timed region)
+        g = P.Mesh.from_synth(N, msh)
+        chosen, times = g.autotune(lam=args.lam, tau=0.0, dtype=args.dtype, reps=20)
+        del g
+        tuned = {"chosen": chosen, "ms_per_apply": [round(t, 5) for t in times]}
+        print(f"# autotune N={N} {args.dtype}: {tuned}", file=sys.stderr, flush=True)
+    variant = P.ax_variant(N, args.dtype)
     ms, R = time_applies(P, torch, msh, N, dt, args.lam, args.steps, args.warmup,
                          args.rotate_gb * 1e9)
     gdofs = msh.K * np_of(N) / (ms * 1e-3) / 1e9
@@ -361,10 +373,12 @@ def main():
         "config": {"workload": "Ax throughput: 512x512-square jittered triangulation "
                                "(524,288 triangles), all Dirichlet, x ~ N(0,1)",
                    "N": N, "Np": np_of(N), "lambda": args.lam, "c_tau": (N + 1) ** 2,
-                   "rotation_sets": R, "parallelism": "single GPU"},
+                   "rotation_sets": R, "ax_variant": variant, "parallelism": "single GPU"},
     }
+    if tuned is not None:
+        line["autotune"] = tuned
     line["roofline"] = roofline(N, w, ms)
-    line["roofline"]["traffic"] = measured_traffic(N, args.dtype, args.lam)
+    line["roofline"]["traffic"] = measured_traffic(N, args.dtype, args.lam, variant)
     line["copy_roof_gbs"] = round(copy_probe(torch, msh.K * alg_bytes(N, w) / 2), 1)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(N, args.lam)

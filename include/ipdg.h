@@ -191,6 +191,32 @@ ipdg_status ipdg_mesh_check(int N, int Nv, const double* VX, const double* VY, i
 ipdg_status ipdg_reference_element(int N, double* r, double* s, double* Dr, double* Ds,
                                    double* M, double* LIFT);
 
+/* Operator-kernel variants.  Every call that applies the operator at degree
+ * N in a given precision (ipdg_apply and the solvers' operator launches)
+ * uses the variant set for (N, dtype), process-wide: bit 1 = the element's
+ * own nodal values staged through LDS for coalesced loads and stores, bit
+ * 2 = raised occupancy (fewer registers per lane).  Degrees 1..5 take
+ * variants 0..3; degrees 6..8 only 0.  All variants give identical results
+ * (same arithmetic in the same order); they differ in speed only.  Solves
+ * already captured into a graph keep the variant they were captured with.
+ * Defaults come from sweeps of the 524,288-triangle operator workload; the
+ * environment variable IPDG_AX_VARIANT, read once, overrides them for all
+ * degrees <= 5.  Returns IPDG_EINVAL for N outside 1..8, a bad dtype or a
+ * variant the degree does not have. */
+ipdg_status ipdg_ax_variant_get(int N, ipdg_dtype dtype, int* variant);
+ipdg_status ipdg_ax_variant_set(int N, ipdg_dtype dtype, int variant);
+
+/* Autotuner: times every operator variant of this mesh's degree in dtype on
+ * this mesh (one warm-up apply, then reps applies, on hip_stream, with the
+ * given lambda and tau), selects the fastest for (N, dtype) as by
+ * ipdg_ax_variant_set and returns it in *chosen.  times_ms (HOST, 4
+ * entries, may be NULL) receives the mean time per apply of variants 0..3
+ * (-1 for a variant the degree does not have).  reps <= 0 selects 20.
+ * Allocates two device vectors of K*Np values for the duration of the call
+ * and synchronises hip_stream.  On failure the previous variant is kept. */
+ipdg_status ipdg_autotune_apply(ipdg_mesh mesh, double lambda, double tau, ipdg_dtype dtype,
+                                int reps, int* chosen, double* times_ms, void* hip_stream);
+
 /* Message of the last failed call on this thread ("" after a success). */
 const char* ipdg_last_error(void);
 

@@ -188,6 +188,86 @@ ipdg_status ipdg_apply(ipdg_mesh mesh, double lambda, double tau, ipdg_dtype dty
   });
 }
 
+ipdg_status ipdg_ax_variant_get(int N, ipdg_dtype dtype, int* variant) {
+  return guarded([&]() -> ipdg_status {
+    if (N < 1 || N > 8) return fail(IPDG_EINVAL, "degree must be 1..8");
+    if (dtype != IPDG_F64 && dtype != IPDG_F32) return fail(IPDG_EINVAL, "bad dtype");
+    if (!variant) return fail(IPDG_EINVAL, "variant is null");
+    *variant = ipdg::ax_variant(N, dtype == IPDG_F32);
+    return IPDG_OK;
+  });
+}
+
+ipdg_status ipdg_ax_variant_set(int N, ipdg_dtype dtype, int variant) {
+  return guarded([&]() -> ipdg_status {
+    if (N < 1 || N > 8) return fail(IPDG_EINVAL, "degree must be 1..8");
+    if (dtype != IPDG_F64 && dtype != IPDG_F32) return fail(IPDG_EINVAL, "bad dtype");
+    if (variant < 0 || variant >= ipdg::ax_variant_count(N))
+      return fail(IPDG_EINVAL, "degree " + std::to_string(N) + " has no operator variant " +
+                                   std::to_string(variant));
+    ipdg::set_ax_variant(N, dtype == IPDG_F32, variant);
+    return IPDG_OK;
+  });
+}
+
+ipdg_status ipdg_autotune_apply(ipdg_mesh mesh, double lambda, double tau, ipdg_dtype dtype, int reps,
+                                int* chosen, double* times_ms, void* hip_stream) {
+  return guarded([&]() -> ipdg_status {
+    if (!mesh) return fail(IPDG_EINVAL, "mesh is null");
+    if (dtype != IPDG_F64 && dtype != IPDG_F32) return fail(IPDG_EINVAL, "bad dtype");
+    if (!chosen) return fail(IPDG_EINVAL, "chosen is null");
+    const int N = mesh->host.N;
+    const bool fp32 = dtype == IPDG_F32;
+    const int prev = ipdg::ax_variant(N, fp32);
+    const int nvar = ipdg::ax_variant_count(N);
+    if (times_ms)
+      for (int v = 0; v < 4; ++v) times_ms[v] = -1.0;
+    *chosen = prev;
+    if (mesh->host.K == 0) return IPDG_OK;
+    if (reps <= 0) reps = 20;
+    DeviceGuard dg(mesh);
+    const ipdg::Kind k = kind_of(dtype);
+    const size_t n = (size_t)mesh->host.K * mesh->Np;
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    ipdg::DevBuf x(n * (fp32 ? 4 : 8)), y(n * (fp32 ? 4 : 8));
+    // operand: every value about 1 (any finite data times the same)
+    IPDG_HIP(hipMemsetD32Async(x.get(), fp32 ? 0x3F800000 : 0x3FF00000, n * (fp32 ? 1 : 2), s));
+    ipdg::ElemArgs a = ipdg::elem_args(mesh, N, k, lambda, ipdg::ctau_of(N, tau));
+    a.x = x.get();
+    a.y = y.get();
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    IPDG_HIP(hipEventCreate(&e0));
+    IPDG_HIP(hipEventCreate(&e1));
+    int best = prev;
+    double best_ms = 0.0;
+    try {
+      for (int v = 0; v < nvar; ++v) {
+        ipdg::set_ax_variant(N, fp32, v);
+        IPDG_HIP(ipdg::ax(N, k, a, s));
+        IPDG_HIP(hipEventRecord(e0, s));
+        for (int r = 0; r < reps; ++r) IPDG_HIP(ipdg::ax(N, k, a, s));
+        IPDG_HIP(hipEventRecord(e1, s));
+        IPDG_HIP(hipEventSynchronize(e1));
+        float ms = 0.0f;
+        IPDG_HIP(hipEventElapsedTime(&ms, e0, e1));
+        const double t = double(ms) / reps;
+        if (times_ms) times_ms[v] = t;
+        if (v == 0 || t < best_ms) best = v, best_ms = t;
+      }
+    } catch (...) {
+      ipdg::set_ax_variant(N, fp32, prev);
+      hipEventDestroy(e0);
+      hipEventDestroy(e1);
+      throw;
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    ipdg::set_ax_variant(N, fp32, best);
+    *chosen = best;
+    return IPDG_OK;
+  });
+}
+
 ipdg_status ipdg_mass_apply(ipdg_mesh mesh, ipdg_dtype dtype, const void* x, void* y,
                             void* hip_stream) {
   return guarded([&]() -> ipdg_status {

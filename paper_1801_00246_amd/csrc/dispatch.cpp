@@ -30,8 +30,11 @@ int ax_variant(int N, bool fp32) {
 }
 
 void set_ax_variant(int N, bool fp32, int v) {
+  ax_variant(N, fp32);   // the environment override is read before any explicit choice
   if (N >= 1 && N <= 8) g_variant[fp32 ? 1 : 0][N] = (N <= 5) ? v : 0;
 }
+
+int ax_variant_count(int N) { return N >= 1 && N <= 5 ? 4 : (N <= 8 ? 1 : 0); }
 
 #define IPDG_SWITCH(N_, CALL)      \
   switch (N_) {                    \

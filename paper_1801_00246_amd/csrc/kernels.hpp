@@ -39,6 +39,7 @@ inline int elem_grid(int K) {
 // set_ax_variant or IPDG_AX_VARIANT; defaults in dispatch.cpp.
 int ax_variant(int N, bool fp32);
 void set_ax_variant(int N, bool fp32, int v);
+int ax_variant_count(int N);   // variants 0..count-1 exist at degree N
 
 // y = A x (SIPDG operator).  Per degree, defined in the per-degree units.
 template <int N> hipError_t launch_ax(Kind kind, const ElemArgs& a, hipStream_t s);

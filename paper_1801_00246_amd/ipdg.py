@@ -73,6 +73,10 @@ _SIGS = {
     "ipdg_kappa_grad": (C.c_int, [_P, C.c_double, _P, _P, _P, _P]),
     "ipdg_mesh_check": (C.c_int, [C.c_int, C.c_int, _P, _P, C.c_int, _P, _P, _P, _P]),
     "ipdg_reference_element": (C.c_int, [C.c_int, _P, _P, _P, _P, _P, _P]),
+    "ipdg_ax_variant_get": (C.c_int, [C.c_int, C.c_int, C.POINTER(C.c_int)]),
+    "ipdg_ax_variant_set": (C.c_int, [C.c_int, C.c_int, C.c_int]),
+    "ipdg_autotune_apply": (C.c_int, [_P, C.c_double, C.c_double, C.c_int, C.c_int, C.POINTER(C.c_int),
+                                      _P, _P]),
 }
 
 
@@ -114,6 +118,18 @@ def default_opts(**kw) -> SolveOpts:
         else:
             setattr(o, k, v)
     return o
+
+
+def ax_variant(N, dtype="f64"):
+    """Operator-kernel variant in use at degree N for dtype ("f64"/"f32")."""
+    v = C.c_int(-1)
+    check(lib().ipdg_ax_variant_get(int(N), F64 if dtype in ("f64", F64) else F32, C.byref(v)))
+    return v.value
+
+
+def set_ax_variant(N, dtype, variant):
+    """Select the operator-kernel variant for degree N and dtype, process-wide."""
+    check(lib().ipdg_ax_variant_set(int(N), F64 if dtype in ("f64", F64) else F32, int(variant)))
 
 
 def _np_ptr(a, dtype):
@@ -235,6 +251,17 @@ class Mesh:
         py = _dev_vec(out, self.ndof, (x.dtype,), "out")
         check(lib().ipdg_apply(self._h, float(lam), float(tau), dt, px, py, _stream(stream)))
         return out
+
+    def autotune(self, lam=0.0, tau=0.0, dtype="f64", reps=20, stream=None):
+        """Time the operator variants of this degree on this mesh and select the
+        fastest for (N, dtype).  Returns (chosen, [ms per apply of variants 0..3],
+        -1 where the degree has no such variant)."""
+        dt = F64 if dtype in ("f64", F64) else F32
+        chosen = C.c_int(-1)
+        times = (C.c_double * 4)()
+        check(lib().ipdg_autotune_apply(self._h, float(lam), float(tau), dt, int(reps), C.byref(chosen),
+                                        C.cast(times, _P), _stream(stream)))
+        return chosen.value, list(times)
 
     def mass(self, x, out=None, stream=None):
         import torch

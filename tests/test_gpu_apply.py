@@ -149,3 +149,31 @@ def test_kappa_one_equals_plain_operator():
     a = host(g1.apply(x, lam=1.0))
     b = host(g2.apply(x, lam=1.0))
     assert np.linalg.norm(a - b) <= 1e-14 * np.linalg.norm(a)
+
+
+@pytest.mark.parametrize("N", [2, 7])
+def test_autotune_selects_a_variant_with_identical_results(N):
+    """The autotuner times every variant of the degree, selects the fastest,
+    and every variant gives the same operator output bit for bit."""
+    msh = synth.permuted(synth.square_mesh(40, jitter=0.2, seed=21, bc="mixed"), seed=22)
+    g = P.Mesh.from_synth(N, msh)
+    x = synth.nodal_normal(msh.K, (N + 1) * (N + 2) // 2, seed=23)
+    saved = {dt: P.ax_variant(N, dt) for dt in ("f64", "f32")}
+    try:
+        for dt, tdt in (("f64", torch.float64), ("f32", torch.float32)):
+            chosen, times = g.autotune(lam=2.0, tau=0.0, dtype=dt, reps=5)
+            nvar = 4 if N <= 5 else 1
+            print(f"N={N} {dt}: chosen {chosen}, ms per apply {times}")
+            assert 0 <= chosen < nvar
+            assert P.ax_variant(N, dt) == chosen
+            assert all(t > 0 for t in times[:nvar]) and all(t == -1 for t in times[nvar:])
+            assert times[chosen] == min(times[:nvar])
+            ys = []
+            for v in range(nvar):
+                P.set_ax_variant(N, dt, v)
+                ys.append(host(g.apply(dev(x, tdt), lam=2.0)))
+            for y in ys[1:]:
+                assert np.array_equal(y, ys[0])
+    finally:
+        for dt, v in saved.items():
+            P.set_ax_variant(N, dt, v)
