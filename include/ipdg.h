@@ -160,8 +160,13 @@ ipdg_status ipdg_precond_apply(ipdg_mesh mesh, double lambda, double tau,
  * that solve's own stream, all launched before any is waited for.  b and x are
  * HOST arrays of nb device FP64 vector pointers; iters and relres are HOST
  * arrays of nb entries (may be NULL).  Each mesh handle may appear once.
- * With IPDG_PC_PMG the coarsest level runs as ordinary launches (never the
- * persistent single-launch form, whose grids could not all be resident).
+ * With IPDG_PC_PMG and at least two solves whose coarsest levels share a
+ * degree, those levels are solved together every outer iteration: one
+ * launch per coarse-CG iteration covers all solves (their concatenated
+ * coarsest levels), between each solve's captured parts before and after
+ * it; the environment variable IPDG_BATCH_COARSE=separate keeps each solve's
+ * coarsest level on its own launches.  The persistent single-launch coarse
+ * form is never used in a batch (its grids could not all be resident).
  * All meshes must live on one device.  opts NULL: defaults with the
  * block inverse-mass preconditioner.  Returns IPDG_NOT_CONVERGED if any
  * solve stopped at max_iters. */

@@ -91,6 +91,12 @@ hipError_t coarse_step(int N, Kind kind, const CoarseStepArgs& a, hipStream_t s)
 #undef C
 }
 
+hipError_t coarse_batch(int N, Kind kind, const CoarseBatchArgs& a, int it, hipStream_t s) {
+#define C(n) launch_coarse_batch<n>(kind, a, it, s)
+  IPDG_SWITCH(N, C)
+#undef C
+}
+
 hipError_t coarse_pcg(int N, Kind kind, const CoarseArgs& a, int grid, hipStream_t s) {
 #define C(n) launch_coarse_pcg<n>(kind, a, grid, s)
   IPDG_SWITCH(N, C)

@@ -544,17 +544,41 @@ struct NextUFaces {
 // (4 x 3 Np values per lane); higher degrees read them after it.
 constexpr bool kCoarsePrefetch = N <= 2;
 
-template <typename T, bool KAP>
+// BATCH: the concatenated coarsest levels of a batch of solves; each block
+// belongs to one solve (tile_solve), whose constants, scalars, partial-sum
+// range and done flag it uses.  Otherwise K, lambda, ctau, sc, outer and the
+// partial counts describe the one level.
+template <typename T, bool KAP, bool BATCH>
 __global__ __launch_bounds__(kBlock) void k_coarse_cgcg(
     T* __restrict__ x, T* __restrict__ p, T* __restrict__ u, const T* __restrict__ dinv,
     const T* __restrict__ r_old, T* __restrict__ r_new, const T* __restrict__ w_old, T* __restrict__ w_new,
     const T* __restrict__ s_old, T* __restrict__ s_new, const T* __restrict__ geo,
     const Conn* __restrict__ conn, const T* __restrict__ kap, const T* __restrict__ ops, T lambda, T ctau,
     int K, int per, const double* __restrict__ pin, int n_rr, int n_g, int n_d, double* __restrict__ pout,
-    CGScal* __restrict__ sc, const int* __restrict__ outer, int it) {
+    CGScal* __restrict__ sc, const int* __restrict__ outer, int it,
+    const CoarseBatchEntry* __restrict__ ent, const int* __restrict__ tile_solve) {
   const bool first = it == 0;
   const int par = it & 1;
-  const bool b0 = blockIdx.x == 0 && threadIdx.x == 0;
+  const int tile = xcd_tile(blockIdx.x, per);
+  int base = 0, ltile = tile, slot = blockIdx.x;
+  bool lead = blockIdx.x == 0;
+  if constexpr (BATCH) {
+    const int si = tile_solve[tile];
+    if (si < 0) return;
+    const CoarseBatchEntry& d = ent[si];
+    base = d.off;
+    K = d.K;
+    ltile = tile - d.tile0;
+    lead = ltile == 0;
+    slot = tile;
+    lambda = T(d.lambda);
+    ctau = T(d.ctau);
+    outer = d.outer;
+    sc += si;
+    pin += d.tile0;
+    n_rr = n_g = n_d = d.ntiles;
+  }
+  const bool b0 = lead && threadIdx.x == 0;
   if (first) {
     if (outer && *outer) {               // outer solve finished: keep the last record
       if (b0) sc->done = 1;
@@ -565,8 +589,8 @@ __global__ __launch_bounds__(kBlock) void k_coarse_cgcg(
   }
   // The element's own state does not depend on alpha and beta: its loads
   // are issued before the reduction so that the two latencies overlap.
-  const int e = xcd_tile(blockIdx.x, per) * kBlock + threadIdx.x;
-  const bool live = e < K;
+  const bool live = ltile * kBlock + (int)threadIdx.x < K;
+  const int e = base + ltile * kBlock + threadIdx.x;   // element (global id in a batch)
   const size_t o = (size_t)(live ? e : 0) * Np;
   T r0[Np], w0[Np], s0[Np], d0[Np], p0[Np], x0[Np], u0[Np];
   if (live) {
@@ -688,10 +712,117 @@ __global__ __launch_bounds__(kBlock) void k_coarse_cgcg(
   }
   block_sum<3>(v);
   if (threadIdx.x == 0) {
-    pout[0 * kMaxPartials + blockIdx.x] = v[0];
-    pout[1 * kMaxPartials + blockIdx.x] = v[1];
-    pout[2 * kMaxPartials + blockIdx.x] = v[2];
+    pout[0 * kMaxPartials + slot] = v[0];
+    pout[1 * kMaxPartials + slot] = v[1];
+    pout[2 * kMaxPartials + slot] = v[2];
   }
+}
+
+// u = D^-1 f of any node of a batch solve's level, read from that solve's own
+// right-hand side (element ids are global, f is indexed from the solve's first)
+template <typename T>
+struct DinvRhsSrc {
+  const T* __restrict__ dinv;
+  const T* __restrict__ f;
+  size_t base;   // first node of the solve
+  __device__ __forceinline__ T operator()(size_t i) const { return dinv[i] * f[i - base]; }
+};
+
+// Start of the batched coarse solves: x = 0, r = f, u = D^-1 r, w = A u and
+// the block partials of (r, r), (r, u), (u, w) in the solve's tile slots.
+template <typename T, bool KAP>
+__global__ __launch_bounds__(kBlock) void k_coarse_binit(
+    T* __restrict__ x, T* __restrict__ u, const T* __restrict__ dinv, T* __restrict__ r, T* __restrict__ w,
+    const T* __restrict__ geo, const Conn* __restrict__ conn, const T* __restrict__ kap,
+    const T* __restrict__ ops, int per, double* __restrict__ pout, const CoarseBatchEntry* __restrict__ ent,
+    const int* __restrict__ tile_solve) {
+  const int tile = xcd_tile(blockIdx.x, per);
+  const int si = tile_solve[tile];
+  if (si < 0) return;
+  const CoarseBatchEntry& d = ent[si];
+  if (d.outer && *d.outer) return;   // the first iteration then marks the solve done
+  const int ltile = tile - d.tile0;
+  const bool live = ltile * kBlock + (int)threadIdx.x < d.K;
+  const int e = d.off + ltile * kBlock + threadIdx.x;
+  const size_t o = (size_t)e * Np, base = (size_t)d.off * Np;
+  const T* __restrict__ f = static_cast<const T*>(d.f);
+  double v[3] = {0.0, 0.0, 0.0};
+  if (live) {
+    T ue[Np], fe[Np];
+#pragma unroll
+    for (int j = 0; j < Np; ++j) fe[j] = f[o - base + j];
+    sipdg_element_src<N, T, KAP, false>(
+        e, DinvRhsSrc<T>{dinv, f, base}, geo, conn, kap, ops, T(d.lambda), T(d.ctau), 0, ue,
+        [&](int i, T wi) {
+          w[o + i] = wi;
+          v[0] += double(fe[i]) * double(fe[i]);
+          v[1] += double(fe[i]) * double(ue[i]);
+          v[2] += double(wi) * double(ue[i]);
+        },
+        [&](int j) {
+          const T uj = dinv[o + j] * fe[j];
+          x[o + j] = T(0);
+          r[o + j] = fe[j];
+          u[o + j] = uj;
+          return uj;
+        });
+  }
+  block_sum<3>(v);
+  if (threadIdx.x == 0) {
+    pout[0 * kMaxPartials + tile] = v[0];
+    pout[1 * kMaxPartials + tile] = v[1];
+    pout[2 * kMaxPartials + tile] = v[2];
+  }
+}
+
+// End of the batched coarse solves: each unfinished solve's x to its own z.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_coarse_bscatter(const T* __restrict__ x, int per,
+                                                            const CoarseBatchEntry* __restrict__ ent,
+                                                            const int* __restrict__ tile_solve) {
+  const int tile = xcd_tile(blockIdx.x, per);
+  const int si = tile_solve[tile];
+  if (si < 0) return;
+  const CoarseBatchEntry& d = ent[si];
+  if (d.outer && *d.outer) return;
+  const int le = (tile - d.tile0) * kBlock + threadIdx.x;
+  if (le >= d.K) return;
+  T* __restrict__ z = static_cast<T*>(d.z);
+  const size_t o = (size_t)(d.off + le) * Np;
+#pragma unroll
+  for (int j = 0; j < Np; ++j) z[(size_t)le * Np + j] = x[o + j];
+}
+
+template <typename T>
+hipError_t run_coarse_batch(const CoarseBatchArgs& a, int it, hipStream_t s) {
+  if (a.grid == 0) return hipSuccess;
+  if (it == -2) {
+    hipLaunchKernelGGL(k_coarse_bscatter<T>, dim3(a.grid), dim3(kBlock), 0, s, (const T*)a.x, a.per, a.ent,
+                       a.tile_solve);
+    return hipGetLastError();
+  }
+  double* set0 = a.partials;
+  double* set1 = a.partials + 3 * (size_t)kMaxPartials;
+  if (it == -1) {
+    auto go = [&](auto kern) {
+      hipLaunchKernelGGL(kern, dim3(a.grid), dim3(kBlock), 0, s, (T*)a.x, (T*)a.u, (const T*)a.dinv, (T*)a.r[0],
+                         (T*)a.w[0], (const T*)a.geo, a.conn, (const T*)a.kap, (const T*)a.ops, a.per, set0, a.ent,
+                         a.tile_solve);
+    };
+    if (a.kap) go(k_coarse_binit<T, true>);
+    else go(k_coarse_binit<T, false>);
+    return hipGetLastError();
+  }
+  const int o = it & 1, nw = 1 - o;
+  auto go = [&](auto kern) {
+    hipLaunchKernelGGL(kern, dim3(a.grid), dim3(kBlock), 0, s, (T*)a.x, (T*)a.p, (T*)a.u, (const T*)a.dinv,
+                       (const T*)a.r[o], (T*)a.r[nw], (const T*)a.w[o], (T*)a.w[nw], (const T*)a.s[o],
+                       (T*)a.s[nw], (const T*)a.geo, a.conn, (const T*)a.kap, (const T*)a.ops, T(0), T(0), 0,
+                       a.per, o ? set1 : set0, 0, 0, 0, o ? set0 : set1, a.sc, nullptr, it, a.ent, a.tile_solve);
+  };
+  if (a.kap) go(k_coarse_cgcg<T, true, true>);
+  else go(k_coarse_cgcg<T, false, true>);
+  return hipGetLastError();
 }
 
 template <typename T>
@@ -704,10 +835,11 @@ hipError_t run_coarse_step(const CoarseStepArgs& a, hipStream_t s) {
     hipLaunchKernelGGL(kern, dim3(grid), dim3(kBlock), 0, s, (T*)a.x, (T*)a.p, (T*)a.u, (const T*)a.dinv,
                        (const T*)a.r_old, (T*)a.r_new, (const T*)a.w_old, (T*)a.w_new, (const T*)a.s_old,
                        (T*)a.s_new, (const T*)o.geo, o.conn, (const T*)o.kap, (const T*)o.ops, T(o.lambda),
-                       T(o.ctau), o.K, per, a.pin, a.n_rr, a.n_g, a.n_d, a.pout, a.sc, a.outer, a.it);
+                       T(o.ctau), o.K, per, a.pin, a.n_rr, a.n_g, a.n_d, a.pout, a.sc, a.outer, a.it, nullptr,
+                       nullptr);
   };
-  if (o.kap) go(k_coarse_cgcg<T, true>);
-  else go(k_coarse_cgcg<T, false>);
+  if (o.kap) go(k_coarse_cgcg<T, true, false>);
+  else go(k_coarse_cgcg<T, false, false>);
   return hipGetLastError();
 }
 
@@ -869,6 +1001,11 @@ hipError_t launch_ax<N>(Kind kind, const ElemArgs& a, hipStream_t s) {
 template <>
 hipError_t launch_coarse_step<N>(Kind kind, const CoarseStepArgs& a, hipStream_t s) {
   return kind == Kind::F64 ? run_coarse_step<double>(a, s) : run_coarse_step<float>(a, s);
+}
+
+template <>
+hipError_t launch_coarse_batch<N>(Kind kind, const CoarseBatchArgs& a, int it, hipStream_t s) {
+  return kind == Kind::F64 ? run_coarse_batch<double>(a, it, s) : run_coarse_batch<float>(a, it, s);
 }
 
 template <>

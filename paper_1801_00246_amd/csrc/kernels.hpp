@@ -122,6 +122,40 @@ struct CoarseStepArgs {
 };
 template <int N> hipError_t launch_coarse_step(Kind kind, const CoarseStepArgs& a, hipStream_t s);
 
+// The coarsest levels of a batch of solves (same degree and precision) as one
+// concatenated level: solve i owns elements [off, off + K) (off a multiple of
+// kBlock, so tiles never straddle two solves) and tiles [tile0, tile0 + ntiles).
+// Connectivity is stored with global element ids.  Each solve keeps its own
+// operator constants, coarse-CG scalars, partial-sum slots (its tile range)
+// and outer done flag; f and z are its own coarse right-hand side and
+// solution buffers.
+struct CoarseBatchEntry {
+  int off = 0, K = 0, tile0 = 0, ntiles = 0;
+  double lambda = 0.0, ctau = 0.0;
+  const int* outer = nullptr;
+  const void* f = nullptr;
+  void* z = nullptr;
+};
+struct CoarseBatchArgs {
+  const CoarseBatchEntry* ent = nullptr;   // device, one per solve
+  const int* tile_solve = nullptr;         // device, grid entries: solve of each tile, -1 past the end
+  int grid = 0, per = 0;                   // launch: grid = per * kXcd blocks
+  void* x = nullptr;                       // concatenated coarse work vectors (level precision)
+  void* p = nullptr;
+  void* u = nullptr;
+  const void* dinv = nullptr;
+  void* r[2] = {nullptr, nullptr};
+  void* w[2] = {nullptr, nullptr};
+  void* s[2] = {nullptr, nullptr};
+  const void* geo = nullptr;
+  const Conn* conn = nullptr;
+  const void* kap = nullptr;               // null: no solve has a coefficient
+  const void* ops = nullptr;
+  double* partials = nullptr;              // 2 sets of 3 slots of kMaxPartials
+  CGScal* sc = nullptr;                    // device, one per solve
+};
+template <int N> hipError_t launch_coarse_batch(Kind kind, const CoarseBatchArgs& a, int it, hipStream_t s);
+
 // Runtime-degree dispatch (dispatch.cpp)
 hipError_t ax(int N, Kind kind, const ElemArgs& a, hipStream_t s);
 hipError_t diag(int N, Kind kind, const ElemArgs& a, hipStream_t s);
@@ -132,6 +166,9 @@ hipError_t restrict_(int Nf, int Nc, Kind kind, const TransferArgs& a, hipStream
 hipError_t prolong(int Nf, int Nc, Kind kind, const TransferArgs& a, hipStream_t s);
 hipError_t coarse_pcg(int N, Kind kind, const CoarseArgs& a, int grid, hipStream_t s);
 hipError_t coarse_step(int N, Kind kind, const CoarseStepArgs& a, hipStream_t s);
+// it = -1: initial state and partials; 0.. : one coarse-CG iteration; -2:
+// copy each solve's solution to its z buffer
+hipError_t coarse_batch(int N, Kind kind, const CoarseBatchArgs& a, int it, hipStream_t s);
 int coarse_pcg_grid(int N, Kind kind, int K);
 
 }  // namespace ipdg

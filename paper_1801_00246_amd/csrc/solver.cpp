@@ -77,11 +77,16 @@ struct Work : SolverWork {
   hipStream_t gs = nullptr;        // internal stream of the solver (default priority)
   hipGraphExec_t graph = nullptr;  // check_every captured outer iterations
   int graph_iters = 0;
+  // one outer iteration split at its coarsest-level solve (batched coarse mode)
+  hipGraphExec_t graph_pre = nullptr, graph_post = nullptr;
 
   void drop_graph() {
     if (graph) (void)hipGraphExecDestroy(graph);
     graph = nullptr;
     graph_iters = 0;
+    if (graph_pre) (void)hipGraphExecDestroy(graph_pre);
+    if (graph_post) (void)hipGraphExecDestroy(graph_post);
+    graph_pre = graph_post = nullptr;
   }
   ~Work() override {
     drop_graph();
@@ -291,6 +296,47 @@ class Solver {
   // captured graph)
   void launch_iterations(int every) { run_iterations(w_->xw.as<double>(), every); }
   hipStream_t stream() const { return s_; }
+
+  // Batched coarse mode: one outer iteration captured as two graphs, the part
+  // before the coarsest-level solve and the part after it; the caller runs
+  // the coarsest-level solves of all members of a batch together in between
+  // (reading coarse_rhs(), writing coarse_sol()).  Only p-multigrid has one.
+  void capture_split() {
+    Work& w = *w_;
+    w.drop_graph();
+    split_f_ = nullptr;
+    split_x_ = nullptr;
+    split_count_ = 0;
+    splitting_ = true;
+    hipGraph_t g = nullptr;
+    IPDG_HIP(hipStreamBeginCapture(s_, hipStreamCaptureModeThreadLocal));
+    try {
+      iteration(w.xw.as<double>());
+    } catch (...) {
+      splitting_ = false;
+      (void)hipStreamEndCapture(s_, &g);
+      if (g) (void)hipGraphDestroy(g);
+      w.drop_graph();
+      throw;
+    }
+    splitting_ = false;
+    IPDG_HIP(hipStreamEndCapture(s_, &g));
+    hipError_t e = hipGraphInstantiate(&w.graph_post, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    IPDG_HIP(e);
+    if (split_count_ != 1 || !w.graph_pre) {
+      w.drop_graph();
+      throw Error(IPDG_EUNSUPPORTED, "an outer iteration does not reach the coarsest level exactly once");
+    }
+  }
+  void launch_pre() { IPDG_HIP(hipGraphLaunch(w_->graph_pre, s_)); }
+  void launch_post() { IPDG_HIP(hipGraphLaunch(w_->graph_post, s_)); }
+  const Level& coarsest() const { return w_->lv.back(); }
+  const void* coarse_rhs() const { return split_f_; }
+  void* coarse_sol() const { return split_x_; }
+  ipdg_mesh_s* mesh() const { return m_; }
+  double lambda() const { return lambda_; }
+  const int* done_flag() const { return outer_done(); }
   void copy_scal() {
     IPDG_HIP(hipMemcpyAsync(w_->host_scal, w_->scal.get(), sizeof(CGScal), hipMemcpyDeviceToHost, s_));
   }
@@ -634,6 +680,22 @@ class Solver {
   // Jacobi-PCG from zero on the coarsest level, coarse_max iterations at most
   void coarse_solve(Level& v, const void* f, void* x) {
     Work& w = *w_;
+    if (splitting_) {
+      // batched coarse mode: close the graph of the part before, open the
+      // one of the part after; the batch solves this level in between
+      split_f_ = f;
+      split_x_ = x;
+      ++split_count_;
+      hipGraph_t g = nullptr;
+      IPDG_HIP(hipStreamEndCapture(s_, &g));
+      if (w.graph_pre) (void)hipGraphExecDestroy(w.graph_pre);
+      w.graph_pre = nullptr;
+      hipError_t e = hipGraphInstantiate(&w.graph_pre, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      IPDG_HIP(e);
+      IPDG_HIP(hipStreamBeginCapture(s_, hipStreamCaptureModeThreadLocal));
+      return;
+    }
     if (w.coarse_grid > 0) {
       // one persistent launch; a kernel node resets the two barrier counters
       // (the status words keep the last executed solve's record, since the
@@ -793,6 +855,10 @@ class Solver {
   size_t n_ = 0;
   double lambda_ = 0, ctau_ = 0;
   bool mixed_ = false, flexible_ = false;
+  bool splitting_ = false;           // capturing the two halves of a split iteration
+  int split_count_ = 0;
+  const void* split_f_ = nullptr;    // the coarsest level's right-hand side and solution
+  void* split_x_ = nullptr;
 };
 
 }  // namespace
@@ -816,6 +882,172 @@ ipdg_status precond_apply(ipdg_mesh_s* m, double lambda, double tau, const ipdg_
   sv.apply_precond(r, z, info);
   return IPDG_OK;
 }
+
+namespace {
+
+// The coarsest levels of a batch's solves, concatenated (CoarseBatchArgs),
+// with the captured graph of one batched coarse solve and the events that
+// order it against the solves' own streams.
+struct CoarseBatchSet {
+  DevBuf ent, tile_solve, x, p, u, dinv, r0, r1, w0, w1, s0, s1, geo, conn, kap, partials, sc;
+  CoarseBatchArgs a;
+  hipStream_t stream = nullptr;
+  hipGraphExec_t graph = nullptr;
+  std::vector<hipEvent_t> ev;
+  hipEvent_t ev_done = nullptr;
+  ~CoarseBatchSet() {
+    if (graph) (void)hipGraphExecDestroy(graph);
+    for (hipEvent_t e : ev)
+      if (e) (void)hipEventDestroy(e);
+    if (ev_done) (void)hipEventDestroy(ev_done);
+    if (stream) (void)hipStreamDestroy(stream);
+  }
+};
+
+// IPDG_BATCH_COARSE=separate keeps every solve's coarsest level on its own
+// launches (the fused form is the default).
+bool batch_coarse_fused() {
+  const char* v = std::getenv("IPDG_BATCH_COARSE");
+  return !(v && std::strcmp(v, "separate") == 0);
+}
+
+// Null when the solves' coarsest levels differ in degree or precision (the
+// caller then keeps them separate).
+std::unique_ptr<CoarseBatchSet> make_coarse_batch(std::vector<std::unique_ptr<Solver>>& sv,
+                                                  const ipdg_solve_opts& o, hipStream_t user) {
+  const int na = int(sv.size());
+  for (int k = 0; k < na; ++k) sv[k]->capture_split();
+  const Level& c0 = sv[0]->coarsest();
+  for (int k = 1; k < na; ++k) {
+    const Level& c = sv[k]->coarsest();
+    if (c.N != c0.N || c.kind != c0.kind) return nullptr;
+  }
+  const int Nc = c0.N, Np = c0.Np;
+  const Kind kind = c0.kind;
+  const size_t w = c0.fp32 ? 4 : 8;
+  std::unique_ptr<CoarseBatchSet> cb(new CoarseBatchSet);
+  IPDG_HIP(hipStreamCreateWithFlags(&cb->stream, hipStreamNonBlocking));
+  std::vector<CoarseBatchEntry> ent(na);
+  int off = 0;
+  bool any_kappa = false;
+  for (int k = 0; k < na; ++k) {
+    const int K = sv[k]->mesh()->host.K;
+    const int nt = (K + kBlock - 1) / kBlock;
+    ent[k].off = off;
+    ent[k].K = K;
+    ent[k].tile0 = off / kBlock;
+    ent[k].ntiles = nt;
+    ent[k].lambda = sv[k]->lambda();
+    ent[k].ctau = sv[k]->coarsest().ctau;
+    ent[k].outer = sv[k]->done_flag();
+    ent[k].f = sv[k]->coarse_rhs();
+    ent[k].z = sv[k]->coarse_sol();
+    off += nt * kBlock;
+    any_kappa = any_kappa || sv[k]->mesh()->has_kappa;
+  }
+  const int Kt = off, tiles = off / kBlock;
+  int per;
+  const int grid = xcd_grid(tiles, per);
+  if (grid > kMaxPartials) throw Error(IPDG_EUNSUPPORTED, "batch too large for one coarse launch");
+  std::vector<int> ts(grid, -1);
+  for (int k = 0; k < na; ++k)
+    for (int t = 0; t < ent[k].ntiles; ++t) ts[ent[k].tile0 + t] = k;
+  std::vector<Conn> conn((size_t)Kt, Conn{});
+  for (int k = 0; k < na; ++k) {
+    const auto& hc = sv[k]->mesh()->host.conn;
+    for (int e = 0; e < ent[k].K; ++e) {
+      Conn c = hc[e];
+      for (int f = 0; f < 3; ++f) c.nb[f] += ent[k].off;
+      conn[(size_t)ent[k].off + e] = c;
+    }
+  }
+  const size_t nv = (size_t)Kt * Np * w;
+  hipStream_t cs = cb->stream;
+  cb->ent.alloc(na * sizeof(CoarseBatchEntry));
+  cb->tile_solve.alloc(grid * sizeof(int));
+  cb->conn.alloc((size_t)Kt * sizeof(Conn));
+  IPDG_HIP(hipMemcpyAsync(cb->ent.get(), ent.data(), na * sizeof(CoarseBatchEntry), hipMemcpyHostToDevice, cs));
+  IPDG_HIP(hipMemcpyAsync(cb->tile_solve.get(), ts.data(), grid * sizeof(int), hipMemcpyHostToDevice, cs));
+  IPDG_HIP(hipMemcpyAsync(cb->conn.get(), conn.data(), (size_t)Kt * sizeof(Conn), hipMemcpyHostToDevice, cs));
+  for (DevBuf* b : {&cb->x, &cb->p, &cb->u, &cb->dinv, &cb->r0, &cb->r1, &cb->w0, &cb->w1, &cb->s0, &cb->s1})
+    b->alloc(nv);
+  cb->geo.alloc((size_t)Kt * 4 * w);
+  if (any_kappa) cb->kap.alloc((size_t)Kt * w);
+  for (int k = 0; k < na; ++k) {
+    ipdg_mesh_s* m = sv[k]->mesh();
+    const int K = ent[k].K;
+    char* g = cb->geo.as<char>() + (size_t)ent[k].off * 4 * w;
+    IPDG_HIP(hipMemcpyAsync(g, geo_for(m, kind), (size_t)K * 4 * w, hipMemcpyDeviceToDevice, cs));
+    char* d = cb->dinv.as<char>() + (size_t)ent[k].off * Np * w;
+    IPDG_HIP(hipMemcpyAsync(d, sv[k]->coarsest().dinv(), (size_t)K * Np * w, hipMemcpyDeviceToDevice, cs));
+    if (any_kappa) {
+      char* q = cb->kap.as<char>() + (size_t)ent[k].off * w;
+      if (m->has_kappa) {
+        const void* src = c0.fp32 ? m->kap32.get() : m->kap64.get();
+        IPDG_HIP(hipMemcpyAsync(q, src, (size_t)K * w, hipMemcpyDeviceToDevice, cs));
+      } else {
+        const std::vector<float> one32(c0.fp32 ? K : 0, 1.0f);
+        const std::vector<double> one64(c0.fp32 ? 0 : K, 1.0);
+        const void* src = c0.fp32 ? (const void*)one32.data() : (const void*)one64.data();
+        IPDG_HIP(hipMemcpyAsync(q, src, (size_t)K * w, hipMemcpyHostToDevice, cs));
+        IPDG_HIP(hipStreamSynchronize(cs));   // before the host vectors go
+      }
+    }
+  }
+  cb->partials.alloc(6 * (size_t)kMaxPartials * sizeof(double));
+  std::vector<CGScal> sc(na);
+  for (auto& c : sc) {
+    c.tol = o.coarse_tol;
+    c.max_iters = o.coarse_max_iters;
+  }
+  cb->sc.alloc(na * sizeof(CGScal));
+  IPDG_HIP(hipMemcpyAsync(cb->sc.get(), sc.data(), na * sizeof(CGScal), hipMemcpyHostToDevice, cs));
+  IPDG_HIP(hipStreamSynchronize(cs));
+  CoarseBatchArgs& a = cb->a;
+  a.ent = cb->ent.as<CoarseBatchEntry>();
+  a.tile_solve = cb->tile_solve.as<int>();
+  a.grid = grid;
+  a.per = per;
+  a.x = cb->x.get();
+  a.p = cb->p.get();
+  a.u = cb->u.get();
+  a.dinv = cb->dinv.get();
+  a.r[0] = cb->r0.get();
+  a.r[1] = cb->r1.get();
+  a.w[0] = cb->w0.get();
+  a.w[1] = cb->w1.get();
+  a.s[0] = cb->s0.get();
+  a.s[1] = cb->s1.get();
+  a.geo = cb->geo.get();
+  a.conn = cb->conn.as<Conn>();
+  a.kap = any_kappa ? cb->kap.get() : nullptr;
+  a.ops = device_ops(Nc, kind);
+  a.partials = cb->partials.as<double>();
+  a.sc = cb->sc.as<CGScal>();
+  // one batched coarse solve: start, coarse_max iterations, copy-out
+  hipGraph_t g = nullptr;
+  IPDG_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+  try {
+    IPDG_HIP(coarse_batch(Nc, kind, a, -1, cs));
+    for (int it = 0; it < o.coarse_max_iters; ++it) IPDG_HIP(coarse_batch(Nc, kind, a, it, cs));
+    IPDG_HIP(coarse_batch(Nc, kind, a, -2, cs));
+  } catch (...) {
+    (void)hipStreamEndCapture(cs, &g);
+    if (g) (void)hipGraphDestroy(g);
+    throw;
+  }
+  IPDG_HIP(hipStreamEndCapture(cs, &g));
+  hipError_t e = hipGraphInstantiate(&cb->graph, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  IPDG_HIP(e);
+  cb->ev.assign(na, nullptr);
+  for (int k = 0; k < na; ++k) IPDG_HIP(hipEventCreateWithFlags(&cb->ev[k], hipEventDisableTiming));
+  IPDG_HIP(hipEventCreateWithFlags(&cb->ev_done, hipEventDisableTiming));
+  (void)user;
+  return cb;
+}
+
+}  // namespace
 
 ipdg_status solve_batch(int nb, ipdg_mesh_s* const* meshes, const double* lambdas, double tau,
                         const double* const* b, double* const* x, double tol, const ipdg_solve_opts& o,
@@ -841,12 +1073,46 @@ ipdg_status solve_batch(int nb, ipdg_mesh_s* const* meshes, const double* lambda
   for (int k = 0; k < na; ++k) IPDG_HIP(hipStreamSynchronize(sv[k]->stream()));
   for (int k = 0; k < na; ++k) sv[k]->after_start(runs[k]);
   const int every = std::max(1, o.check_every);
-  // Each solve replays its own captured graph of `every` iterations on its
-  // own stream; the launches of all unfinished solves are issued before any
-  // is waited for, so the device runs the solves' small kernels concurrently
-  // (one stream per solve, spread over the hardware queues).
   int left = 0;
   for (int k = 0; k < na; ++k) left += !runs[k].finished;
+  std::unique_ptr<CoarseBatchSet> cb;
+  if (left > 0 && o.pc == IPDG_PC_PMG && na >= 2 && batch_coarse_fused()) cb = make_coarse_batch(sv, o, s);
+  if (cb) {
+    // Fused coarse mode: every outer iteration runs each solve's part before
+    // its coarsest-level solve on its own stream, then the coarsest-level
+    // solves of all solves together (one launch per coarse iteration over the
+    // concatenated levels), then each solve's part after it.
+    int it = 0;
+    while (left > 0) {
+      for (int k = 0; k < na; ++k) {
+        if (runs[k].finished) continue;
+        sv[k]->launch_pre();
+        IPDG_HIP(hipEventRecord(cb->ev[k], sv[k]->stream()));
+        IPDG_HIP(hipStreamWaitEvent(cb->stream, cb->ev[k], 0));
+      }
+      IPDG_HIP(hipGraphLaunch(cb->graph, cb->stream));
+      IPDG_HIP(hipEventRecord(cb->ev_done, cb->stream));
+      for (int k = 0; k < na; ++k) {
+        if (runs[k].finished) continue;
+        IPDG_HIP(hipStreamWaitEvent(sv[k]->stream(), cb->ev_done, 0));
+        sv[k]->launch_post();
+      }
+      if (++it % every != 0) continue;
+      for (int k = 0; k < na; ++k)
+        if (!runs[k].finished) sv[k]->copy_scal();
+      for (int k = 0; k < na; ++k) IPDG_HIP(hipStreamSynchronize(sv[k]->stream()));
+      IPDG_HIP(hipStreamSynchronize(cb->stream));
+      left = 0;
+      for (int k = 0; k < na; ++k)
+        if (!runs[k].finished) left += !sv[k]->after_step(runs[k]);
+    }
+    IPDG_HIP(hipStreamSynchronize(cb->stream));
+  }
+  // Otherwise each solve replays its own captured graph of `every`
+  // iterations on its own stream; the launches of all unfinished solves are
+  // issued before any is waited for, so the device runs the solves' small
+  // kernels concurrently (one stream per solve, spread over the hardware
+  // queues).
   while (left > 0) {
     for (int k = 0; k < na; ++k)
       if (!runs[k].finished) sv[k]->launch_iterations(every);

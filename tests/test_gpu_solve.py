@@ -252,6 +252,42 @@ def test_batch_pmg_auto_levels(prec):
         assert abs(info["iters"] - iters[i]) <= max(2, info["iters"] // 10)
 
 
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_batch_fused_coarse_matches_separate_coarse(prec, monkeypatch):
+    """The batch's coarsest levels solved together (one launch per coarse
+    iteration over all solves, the default) against each solve's own coarse
+    launches: the same preconditioner up to the order of the partial sums.
+    A fixed coarse iteration count (tolerance 0) keeps both on the same
+    number of coarse steps; one mesh carries a coefficient."""
+    draws = [(10, 4, 1.0, False), (12, 7, 30.0, True), (8, 8, 1000.0, False), (14, 5, 3.0, False)]
+    pr = P.PREC_FP64 if prec == "fp64" else P.PREC_MIXED
+    o = P.default_opts(pc=P.PC_PMG, prec=pr, coarse_tol=0.0, coarse_max_iters=25)
+    meshes, bs, As, lams = [], [], [], []
+    for i, (n, N, lam, kap) in enumerate(draws):
+        msh = synth.square_mesh(n, jitter=0.15, seed=70 + i)
+        kv = synth.kappa_draw(msh.K, seed=80 + i) if kap else None
+        m = OracleMesh(msh.VX, msh.VY, msh.EToV, msh.EToB, N)
+        b = mass_apply(m, synth.nodal_normal(msh.K, m.Np, seed=90 + i))
+        As.append(assemble(m, lam, float((N + 1) ** 2), kappa=kv))
+        meshes.append(P.Mesh.from_synth(N, msh, kappa=kv))
+        bs.append(dev(b))
+        lams.append(lam)
+    xf, itf, relf, st = P.solve_batch(meshes, lams, bs, tol=1e-8, opts=o)
+    assert st == 0
+    monkeypatch.setenv("IPDG_BATCH_COARSE", "separate")
+    xs, its, rels, st2 = P.solve_batch(meshes, lams, bs, tol=1e-8, opts=o)
+    assert st2 == 0
+    for i, A in enumerate(As):
+        a, c = host(xf[i]), host(xs[i])
+        print(f"solve {i}: fused {itf[i]} iterations, separate {its[i]}, "
+              f"rel diff {np.linalg.norm(a - c) / np.linalg.norm(c):.2e}")
+        assert true_relres(A, a, host(bs[i])) <= 1e-8
+        assert relf[i] <= 1e-8
+        assert abs(itf[i] - its[i]) <= 1
+        if itf[i] == its[i]:
+            assert np.linalg.norm(a - c) <= 1e-6 * np.linalg.norm(c)
+
+
 def test_pmg_auto_levels_halve_degree():
     g_N = {7: [7, 3, 1], 8: [8, 4, 2, 1], 2: [2, 1], 1: [1]}
     for N, levels in g_N.items():
