@@ -37,7 +37,7 @@ FP32_PEAK_TFS = 157.3          # vector FP32, published
 # counter's reading for a device-to-device copy of known size.  Valid only for
 # the kernel sources it was measured on (their SHA-256), else reported null.
 MEASURED_TRAFFIC = {"N": 3, "dtype": "f64", "lambda": 100.0, "variant": 0, "bytes": 113061729,
-                    "sources_sha256": "f7bc97a34f0d23275292a9c0d8bda787976c3e8685c11a8b0da22a7f1c7b3cd0",
+                    "sources_sha256": "0ae00fc32c369f6335a04d7c8b432a20b6ba051c435a8810ae27a4c07a4ac71c",
                     "profile": "profiles/k_ax_N3_f64_524288.md"}
 
 KERNEL_SOURCES = ("elem_inst.hip", "sipdg_core.hpp", "tri.hpp", "device_common.hpp",
