@@ -25,6 +25,8 @@
 #include "solver.hpp"
 
 #include <algorithm>
+#include <atomic>
+#include <mutex>
 #include <chrono>
 #include <cmath>
 #include <cstddef>
@@ -77,16 +79,28 @@ struct Work : SolverWork {
   hipStream_t gs = nullptr;        // internal stream of the solver (default priority)
   hipGraphExec_t graph = nullptr;  // check_every captured outer iterations
   int graph_iters = 0;
-  // one outer iteration split at its coarsest-level solve (batched coarse mode)
+  // one outer iteration split at its coarsest-level solve (batched coarse
+  // mode), and that solve's right-hand side and solution buffers
   hipGraphExec_t graph_pre = nullptr, graph_post = nullptr;
+  const void* split_f = nullptr;
+  void* split_x = nullptr;
+  unsigned long long setup_id = 0;   // changes with every new setup (never reused)
 
-  void drop_graph() {
+  void drop_main() {
     if (graph) (void)hipGraphExecDestroy(graph);
     graph = nullptr;
     graph_iters = 0;
+  }
+  void drop_split() {
     if (graph_pre) (void)hipGraphExecDestroy(graph_pre);
     if (graph_post) (void)hipGraphExecDestroy(graph_post);
     graph_pre = graph_post = nullptr;
+    split_f = nullptr;
+    split_x = nullptr;
+  }
+  void drop_graph() {
+    drop_main();
+    drop_split();
   }
   ~Work() override {
     drop_graph();
@@ -96,6 +110,11 @@ struct Work : SolverWork {
 };
 
 size_t off_done() { return offsetof(CGScal, done); }
+
+unsigned long long next_setup_id() {
+  static std::atomic<unsigned long long> n{0};
+  return ++n;
+}
 const int* done_ptr(const DevBuf& sc) {
   return reinterpret_cast<const int*>(static_cast<const char*>(sc.get()) + off_done());
 }
@@ -303,9 +322,8 @@ class Solver {
   // (reading coarse_rhs(), writing coarse_sol()).  Only p-multigrid has one.
   void capture_split() {
     Work& w = *w_;
-    w.drop_graph();
-    split_f_ = nullptr;
-    split_x_ = nullptr;
+    if (w.graph_pre && w.graph_post) return;   // captured for this setup already
+    w.drop_split();
     split_count_ = 0;
     splitting_ = true;
     hipGraph_t g = nullptr;
@@ -316,7 +334,7 @@ class Solver {
       splitting_ = false;
       (void)hipStreamEndCapture(s_, &g);
       if (g) (void)hipGraphDestroy(g);
-      w.drop_graph();
+      w.drop_split();
       throw;
     }
     splitting_ = false;
@@ -325,15 +343,16 @@ class Solver {
     (void)hipGraphDestroy(g);
     IPDG_HIP(e);
     if (split_count_ != 1 || !w.graph_pre) {
-      w.drop_graph();
+      w.drop_split();
       throw Error(IPDG_EUNSUPPORTED, "an outer iteration does not reach the coarsest level exactly once");
     }
   }
+  unsigned long long setup_id() const { return w_->setup_id; }
   void launch_pre() { IPDG_HIP(hipGraphLaunch(w_->graph_pre, s_)); }
   void launch_post() { IPDG_HIP(hipGraphLaunch(w_->graph_post, s_)); }
   const Level& coarsest() const { return w_->lv.back(); }
-  const void* coarse_rhs() const { return split_f_; }
-  void* coarse_sol() const { return split_x_; }
+  const void* coarse_rhs() const { return w_->split_f; }
+  void* coarse_sol() const { return w_->split_x; }
   ipdg_mesh_s* mesh() const { return m_; }
   double lambda() const { return lambda_; }
   const int* done_flag() const { return outer_done(); }
@@ -385,6 +404,7 @@ class Solver {
     }
     const auto t0 = clk::now();
     w.drop_graph();
+    w.setup_id = next_setup_id();
     w.lv.clear();
     w.n = n_;
     w.xw.ensure(n_ * 8);
@@ -683,8 +703,8 @@ class Solver {
     if (splitting_) {
       // batched coarse mode: close the graph of the part before, open the
       // one of the part after; the batch solves this level in between
-      split_f_ = f;
-      split_x_ = x;
+      w.split_f = f;
+      w.split_x = x;
       ++split_count_;
       hipGraph_t g = nullptr;
       IPDG_HIP(hipStreamEndCapture(s_, &g));
@@ -769,7 +789,7 @@ class Solver {
     }
     Work& w = *w_;
     if (!w.graph || w.graph_iters != every) {
-      w.drop_graph();
+      w.drop_main();
       hipGraph_t g = nullptr;
       IPDG_HIP(hipStreamBeginCapture(s_, hipStreamCaptureModeThreadLocal));
       try {
@@ -857,8 +877,6 @@ class Solver {
   bool mixed_ = false, flexible_ = false;
   bool splitting_ = false;           // capturing the two halves of a split iteration
   int split_count_ = 0;
-  const void* split_f_ = nullptr;    // the coarsest level's right-hand side and solution
-  void* split_x_ = nullptr;
 };
 
 }  // namespace
@@ -916,7 +934,6 @@ bool batch_coarse_fused() {
 std::unique_ptr<CoarseBatchSet> make_coarse_batch(std::vector<std::unique_ptr<Solver>>& sv,
                                                   const ipdg_solve_opts& o, hipStream_t user) {
   const int na = int(sv.size());
-  for (int k = 0; k < na; ++k) sv[k]->capture_split();
   const Level& c0 = sv[0]->coarsest();
   for (int k = 1; k < na; ++k) {
     const Level& c = sv[k]->coarsest();
@@ -1047,6 +1064,44 @@ std::unique_ptr<CoarseBatchSet> make_coarse_batch(std::vector<std::unique_ptr<So
   return cb;
 }
 
+// What a batched coarse set was built for: the solves' setups (ids are never
+// reused, so a destroyed mesh never matches), their coarse buffers and
+// constants, the coarse options and the device.
+struct CoarseBatchKey {
+  std::vector<unsigned long long> ids;
+  std::vector<const void*> ptrs;
+  std::vector<double> lambdas;
+  double coarse_tol = 0;
+  int coarse_max = 0, device = -1;
+  bool operator==(const CoarseBatchKey& o) const {
+    return ids == o.ids && ptrs == o.ptrs && lambdas == o.lambdas && coarse_tol == o.coarse_tol &&
+           coarse_max == o.coarse_max && device == o.device;
+  }
+};
+
+CoarseBatchKey coarse_batch_key(const std::vector<std::unique_ptr<Solver>>& sv, const ipdg_solve_opts& o) {
+  CoarseBatchKey k;
+  for (const auto& s : sv) {
+    k.ids.push_back(s->setup_id());
+    k.ptrs.push_back(s->coarse_rhs());
+    k.ptrs.push_back(s->coarse_sol());
+    k.ptrs.push_back(s->done_flag());
+    k.lambdas.push_back(s->lambda());
+  }
+  k.coarse_tol = o.coarse_tol;
+  k.coarse_max = o.coarse_max_iters;
+  (void)hipGetDevice(&k.device);
+  return k;
+}
+
+// The last batched coarse set, reused by the next batch of the same solves
+// (a serving loop); held until it is replaced (never freed at process exit,
+// when the runtime may already be gone).
+std::mutex g_cb_mu;
+CoarseBatchSet* g_cb = nullptr;
+bool g_cb_valid = false;
+CoarseBatchKey g_cb_key;
+
 }  // namespace
 
 ipdg_status solve_batch(int nb, ipdg_mesh_s* const* meshes, const double* lambdas, double tau,
@@ -1075,8 +1130,27 @@ ipdg_status solve_batch(int nb, ipdg_mesh_s* const* meshes, const double* lambda
   const int every = std::max(1, o.check_every);
   int left = 0;
   for (int k = 0; k < na; ++k) left += !runs[k].finished;
-  std::unique_ptr<CoarseBatchSet> cb;
-  if (left > 0 && o.pc == IPDG_PC_PMG && na >= 2 && batch_coarse_fused()) cb = make_coarse_batch(sv, o, s);
+  std::unique_ptr<CoarseBatchSet> own_cb;
+  CoarseBatchSet* cb = nullptr;
+  std::unique_lock<std::mutex> lk(g_cb_mu, std::defer_lock);
+  if (left > 0 && o.pc == IPDG_PC_PMG && na >= 2 && batch_coarse_fused()) {
+    for (int k = 0; k < na; ++k) sv[k]->capture_split();
+    const CoarseBatchKey key = coarse_batch_key(sv, o);
+    if (lk.try_lock()) {
+      if (!g_cb_valid || !(g_cb_key == key)) {
+        delete g_cb;
+        g_cb = nullptr;
+        g_cb_valid = false;
+        g_cb = make_coarse_batch(sv, o, s).release();
+        g_cb_key = key;
+        g_cb_valid = true;
+      }
+      cb = g_cb;
+    } else {
+      own_cb = make_coarse_batch(sv, o, s);   // another thread holds the cached set
+      cb = own_cb.get();
+    }
+  }
   if (cb) {
     // Fused coarse mode: every outer iteration runs each solve's part before
     // its coarsest-level solve on its own stream, then the coarsest-level

@@ -288,6 +288,26 @@ def test_batch_fused_coarse_matches_separate_coarse(prec, monkeypatch):
             assert np.linalg.norm(a - c) <= 1e-6 * np.linalg.norm(c)
 
 
+def test_batch_repeated_calls_reuse_and_rebuild():
+    """Repeated batches of the same solves reuse the captured split graphs and
+    the fused coarse set; a new right-hand side gives its own solution, and a
+    changed lambda (a new setup) is picked up."""
+    draws = [(9, 4), (11, 6), (8, 5)]
+    o = P.default_opts(pc=P.PC_PMG)
+    meshes, ms = [], []
+    for i, (n, N) in enumerate(draws):
+        msh = synth.square_mesh(n, jitter=0.1, seed=110 + i)
+        ms.append(OracleMesh(msh.VX, msh.VY, msh.EToV, msh.EToB, N))
+        meshes.append(P.Mesh.from_synth(N, msh))
+    for lams, seed in (([1.0, 10.0, 100.0], 1), ([1.0, 10.0, 100.0], 2), ([5.0, 10.0, 100.0], 1)):
+        bs = [mass_apply(m, synth.nodal_normal(m.K, m.Np, seed=120 + 10 * seed + i)) for i, m in enumerate(ms)]
+        xs, iters, rel, st = P.solve_batch(meshes, lams, [dev(b) for b in bs], tol=1e-8, opts=o)
+        assert st == 0
+        for m, b, x, lam in zip(ms, bs, xs, lams):
+            A = assemble(m, lam, float((m.N + 1) ** 2))
+            assert true_relres(A, host(x), b) <= 1e-8
+
+
 def test_pmg_auto_levels_halve_degree():
     g_N = {7: [7, 3, 1], 8: [8, 4, 2, 1], 2: [2, 1], 1: [1]}
     for N, levels in g_N.items():
