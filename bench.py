@@ -36,8 +36,8 @@ FP32_PEAK_TFS = 157.3          # vector FP32, published
 # rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE), each scaled by the
 # counter's reading for a device-to-device copy of known size.  Valid only for
 # the kernel sources it was measured on (their SHA-256), else reported null.
-MEASURED_TRAFFIC = {"N": 3, "dtype": "f64", "lambda": 100.0, "variant": 0, "bytes": 113061729,
-                    "sources_sha256": "0ae00fc32c369f6335a04d7c8b432a20b6ba051c435a8810ae27a4c07a4ac71c",
+MEASURED_TRAFFIC = {"N": 3, "dtype": "f64", "lambda": 100.0, "variant": 0, "bytes": 113019193,
+                    "sources_sha256": "2cc1b908737e70ca957fa4292f5cde5fdee9d77a7d0d37d745eeaba55a6e21a3",
                     "profile": "profiles/k_ax_N3_f64_524288.md"}
 
 KERNEL_SOURCES = ("elem_inst.hip", "sipdg_core.hpp", "tri.hpp", "device_common.hpp",

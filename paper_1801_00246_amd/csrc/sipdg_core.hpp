@@ -34,6 +34,8 @@
 // entries are wave-uniform compile-time offsets (scalar loads), while the
 // neighbour's nodal values are gathered in rotated order.
 #pragma once
+#include <cmath>
+
 #include "device_common.hpp"
 #include "tri.hpp"
 
@@ -60,6 +62,41 @@ template <typename S, typename = void>
 struct PerFaceSrc { static constexpr bool value = false; };
 template <typename S>
 struct PerFaceSrc<S, decltype(void(S::kPerFace))> { static constexpr bool value = S::kPerFace; };
+
+// 1/sqrt(x) and 1/x for a positive normal x (lengths and Jacobians of
+// non-degenerate elements).  On the device: the hardware estimate and one
+// Newton-Raphson step, y <- y (3 - x y^2)/2 and y <- y (2 - x y), which
+// squares the estimate's relative error (a few units in the last place
+// remain); the IEEE-rounded sqrt and division sequences cost several times
+// more instructions.  FP32 takes the estimate alone (about one unit).
+template <typename TC>
+__host__ __device__ __forceinline__ TC rsqrt_pos(TC x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  if constexpr (sizeof(TC) == 8) {
+    const double y = __builtin_amdgcn_rsq(x);
+    const double e = __builtin_fma(-x * y, y, 1.0);   // 1 - x y^2
+    return __builtin_fma(0.5 * y, e, y);
+  } else {
+    return __builtin_amdgcn_rsqf(x);
+  }
+#else
+  return TC(1) / std::sqrt(x);
+#endif
+}
+template <typename TC>
+__host__ __device__ __forceinline__ TC rcp_pos(TC x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  if constexpr (sizeof(TC) == 8) {
+    const double y = __builtin_amdgcn_rcp(x);
+    const double e = __builtin_fma(-x, y, 1.0);        // 1 - x y
+    return __builtin_fma(y, e, y);
+  } else {
+    return __builtin_amdgcn_rcpf(x);
+  }
+#else
+  return TC(1) / x;
+#endif
+}
 
 // A zero the optimiser cannot see through.  Added to the operator offsets of
 // one phase (a face, a face node, an output row), it keeps that phase's
@@ -110,7 +147,12 @@ __host__ __device__ __forceinline__ void sipdg_element_src(int e, const Src& src
   constexpr bool PF = PerFaceSrc<Src>::value;
   const TC rx = own_metric<PF>(src, geo, e, 0), sx = own_metric<PF>(src, geo, e, 1);
   const TC ry = own_metric<PF>(src, geo, e, 2), sy = own_metric<PF>(src, geo, e, 3);
-  const TC J = TC(1) / (rx * sy - sx * ry);
+  // LEAN (degrees <= 5, where the per-face work is a large share): reciprocal
+  // square roots and reciprocals from the refined estimates, boundary types
+  // as coefficients; higher degrees keep IEEE sqrt/division and selects
+  // (their register allocation is at an occupancy boundary)
+  constexpr bool LEAN = N <= 5;
+  const TC J = LEAN ? rcp_pos(rx * sy - sx * ry) : TC(1) / (rx * sy - sx * ry);
   const TC ke = KAP ? own_metric<PF>(src, kap, e, -1) : TC(1);
   const Conn c = conn[e];
 
@@ -159,8 +201,14 @@ __host__ __device__ __forceinline__ void sipdg_element_src(int e, const Src& src
     const TC prx = nmetric(0), psx = nmetric(1), pry = nmetric(2), psy = nmetric(3);
     const TC kp = nmetric(4);
     if constexpr (EARLY) phase_fence();
-    Fs[f] = sqrt(gx[f] * gx[f] + gy[f] * gy[f]);
-    iFs[f] = TC(1) / Fs[f];
+    if constexpr (LEAN) {
+      const TC g2 = gx[f] * gx[f] + gy[f] * gy[f];
+      iFs[f] = rsqrt_pos(g2);
+      Fs[f] = g2 * iFs[f];
+    } else {
+      Fs[f] = sqrt(gx[f] * gx[f] + gy[f] * gy[f]);
+      iFs[f] = TC(1) / Fs[f];
+    }
     const TC nx = gx[f] * iFs[f], ny = gy[f] * iFs[f];
     const TC nr = nx * rx + ny * ry, ns = nx * sx + ny * sy;
     // own normal derivative at face node k
@@ -184,10 +232,19 @@ __host__ __device__ __forceinline__ void sipdg_element_src(int e, const Src& src
     const TC Ry = fp == 0 ? pry : (fp == 1 ? psy : qy);
     const TC Sx = fp == 0 ? psx : (fp == 1 ? qx : prx);
     const TC Sy = fp == 0 ? psy : (fp == 1 ? qy : pry);
-    const TC Fsp = sqrt(Sx * Sx + Sy * Sy);
+    const TC S2 = Sx * Sx + Sy * Sy;
+    const TC Fsp = LEAN ? S2 * rsqrt_pos(S2) : sqrt(S2);
     const TC nrp = nx * Rx + ny * Ry, nsp = nx * Sx + ny * Sy;
     const bool inner = (bc == 0);
     const bool dir = (bc == 1);
+    // boundary type as coefficients (no selects): [u] = cu_p u+ + cu_m u-,
+    // [k d_n u] = cd_p d_n u+ + cd_m d_n u- with the mirror ghost states
+    // (Dirichlet: [u] = -2 u-, jump of the flux 0; Neumann: [u] = 0, jump of
+    // the flux -2 k d_n u-)
+    const TC c_in = inner ? TC(1) : TC(0);
+    const TC cu_m = -(c_in + (dir ? TC(2) : TC(0)));
+    const TC cd_p = c_in * kp;
+    const TC cd_m = -(c_in + ((!inner && !dir) ? TC(2) : TC(0))) * ke;
     TC pr[Nfp], ps[Nfp];
 #pragma unroll
     for (int m = 0; m < Nfp; ++m) pr[m] = ps[m] = TC(0);
@@ -219,13 +276,18 @@ __host__ __device__ __forceinline__ void sipdg_element_src(int e, const Src& src
       const TC dnp = nrp * pr[m] + nsp * ps[m];
       const TC um = u[vm];
       const TC pv = DIAG ? TC(0) : xv[m];
-      const TC ji = pv - um;
-      const TC di = kp * dnp - ke * ownk;
-      jmp[f][k] = inner ? ji : (dir ? TC(-2) * um : TC(0));
-      dnj[f][k] = inner ? di : (dir ? TC(0) : TC(-2) * ke * ownk);
+      if constexpr (LEAN) {
+        jmp[f][k] = c_in * pv + cu_m * um;
+        dnj[f][k] = cd_p * dnp + cd_m * ownk;
+      } else {
+        const TC ji = pv - um;
+        const TC di = kp * dnp - ke * ownk;
+        jmp[f][k] = inner ? ji : (dir ? TC(-2) * um : TC(0));
+        dnj[f][k] = inner ? di : (dir ? TC(0) : TC(-2) * ke * ownk);
+      }
     });
     // branch-free: a boundary face takes the element's own side only
-    tau[f] = ctau * fmax(ke * Fs[f], TC(inner ? 1 : 0) * (kp * Fsp));
+    tau[f] = ctau * fmax(ke * Fs[f], (LEAN ? c_in : TC(inner ? 1 : 0)) * (kp * Fsp));
   });
 
   phase_fence();
