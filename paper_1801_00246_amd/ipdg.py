@@ -108,6 +108,10 @@ def check(status: int):
 def default_opts(**kw) -> SolveOpts:
     o = SolveOpts()
     lib().ipdg_default_opts(C.byref(o))
+    known = {f[0] for f in SolveOpts._fields_}
+    for k in kw:
+        if k not in known:
+            raise TypeError(f"unknown solve option {k!r} (known: {sorted(known)})")
     for k, v in kw.items():
         if k in ("degrees", "rho"):
             arr = getattr(o, k)

@@ -106,3 +106,10 @@ def test_operator_variant_table():
     finally:
         for (N, dt), v in saved.items():
             P.set_ax_variant(N, dt, v)
+
+
+def test_default_opts_rejects_unknown_options():
+    o = P.default_opts(pc=P.PC_PMG, prec=P.PREC_MIXED, coarse_max_iters=7)
+    assert (o.pc, o.prec, o.coarse_max_iters) == (P.PC_PMG, P.PREC_MIXED, 7)
+    with pytest.raises(TypeError):
+        P.default_opts(precision=P.PREC_MIXED)
