@@ -201,7 +201,7 @@ ipdg_status ipdg_reference_element(int N, double* r, double* s, double* Dr, doub
  * uses the variant set for (N, dtype), process-wide: bit 1 = the element's
  * own nodal values staged through LDS for coalesced loads and stores, bit
  * 2 = raised occupancy (fewer registers per lane).  Degrees 1..5 take
- * variants 0..3; degrees 6..8 only 0.  All variants give identical results
+ * variants 0..3; degrees 6..8 variants 0 and 1.  All variants give identical results
  * (same arithmetic in the same order); they differ in speed only.  Solves
  * already captured into a graph keep the variant they were captured with.
  * Defaults come from sweeps of the 524,288-triangle operator workload; the

@@ -10,7 +10,7 @@ namespace {
 // Operator kernel variant per precision (FP64, FP32) and degree; bits:
 // 1 = LDS-staged inputs/outputs, 2 = raised occupancy (degrees <= 5).
 // Defaults from measured sweeps of the 524,288-element operator workload.
-std::atomic<int> g_variant[2][9] = {{0, 0, 0, 0, 0, 0, 0, 0, 0}, {0, 2, 2, 0, 0, 1, 0, 0, 0}};
+std::atomic<int> g_variant[2][9] = {{0, 0, 0, 0, 0, 3, 0, 0, 0}, {0, 2, 2, 0, 0, 1, 1, 1, 1}};
 bool env_read = false;
 }  // namespace
 
@@ -20,8 +20,8 @@ int ax_variant(int N, bool fp32) {
     if (const char* v = std::getenv("IPDG_AX_VARIANT")) {
       const int k = std::atoi(v);
       for (int n = 1; n <= 8; ++n) {
-        g_variant[0][n] = n <= 5 ? k : 0;
-        g_variant[1][n] = n <= 5 ? k : 0;
+        g_variant[0][n] = n <= 5 ? k : (k & 1);
+        g_variant[1][n] = n <= 5 ? k : (k & 1);
       }
     }
   }
@@ -31,10 +31,10 @@ int ax_variant(int N, bool fp32) {
 
 void set_ax_variant(int N, bool fp32, int v) {
   ax_variant(N, fp32);   // the environment override is read before any explicit choice
-  if (N >= 1 && N <= 8) g_variant[fp32 ? 1 : 0][N] = (N <= 5) ? v : 0;
+  if (N >= 1 && N <= 8) g_variant[fp32 ? 1 : 0][N] = (N <= 5) ? v : (v & 1);
 }
 
-int ax_variant_count(int N) { return N >= 1 && N <= 5 ? 4 : (N <= 8 ? 1 : 0); }
+int ax_variant_count(int N) { return N >= 1 && N <= 5 ? 4 : (N >= 6 && N <= 8 ? 2 : 0); }
 
 #define IPDG_SWITCH(N_, CALL)      \
   switch (N_) {                    \

@@ -874,8 +874,10 @@ int resident_grid(int K) {
   return g > kMaxPartialsCoarse ? kMaxPartialsCoarse : g;
 }
 
-// degrees whose operator kernel is built with the LDS-staged variant too
-constexpr bool kHasStage = N <= 5;
+// the LDS-staged variant exists at every degree (at N = 8, FP64, its buffer
+// is 92 KB: one block per CU, the occupancy the register use allows anyway);
+// the raised-occupancy variants at degrees <= 5
+constexpr bool kHasBoost = N <= 5;
 
 template <typename TC, typename TX, typename TY, bool KAP, bool STAGE, int WAVES>
 void launch_ax_variant(const ElemArgs& a, int grid, int per, hipStream_t s) {
@@ -894,12 +896,13 @@ hipError_t run_ax(const ElemArgs& a, hipStream_t s) {
   // variant bits: 1 = LDS-staged inputs/outputs, 2 = raised occupancy
   const int v = ax_variant(N, sizeof(TC) == 4);
   constexpr int W = ax_boost_waves<TC>();
-  if constexpr (kHasStage) {
+  if ((v & 3) == 1) {
+    if (a.kap) launch_ax_variant<TC, TX, TY, true, true, 0>(a, grid, per, s);
+    else launch_ax_variant<TC, TX, TY, false, true, 0>(a, grid, per, s);
+    return hipGetLastError();
+  }
+  if constexpr (kHasBoost) {
     switch (v & 3) {
-      case 1:
-        if (a.kap) launch_ax_variant<TC, TX, TY, true, true, 0>(a, grid, per, s);
-        else launch_ax_variant<TC, TX, TY, false, true, 0>(a, grid, per, s);
-        return hipGetLastError();
       case 2:
         if (a.kap) launch_ax_variant<TC, TX, TY, true, false, W>(a, grid, per, s);
         else launch_ax_variant<TC, TX, TY, false, false, W>(a, grid, per, s);

@@ -88,15 +88,13 @@ def test_operator_variant_table():
     rejection of degrees, dtypes and variants that do not exist."""
     saved = {(N, dt): P.ax_variant(N, dt) for N in range(1, 9) for dt in ("f64", "f32")}
     try:
-        for N in range(6, 9):
-            assert saved[(N, "f64")] == 0 and saved[(N, "f32")] == 0
-        for N in range(1, 6):
-            for v in range(4):
+        for N in range(1, 9):
+            for v in range(4 if N <= 5 else 2):
                 P.set_ax_variant(N, "f32", v)
                 assert P.ax_variant(N, "f32") == v
         L = P.lib()
         for args in ((0, P.F64, 0), (9, P.F64, 0), (3, 2, 0), (3, P.F64, 4), (3, P.F64, -1),
-                     (6, P.F64, 1)):
+                     (6, P.F64, 2), (8, P.F32, 3)):
             assert L.ipdg_ax_variant_set(*args) == -1
         import ctypes as C
         v = C.c_int(-7)

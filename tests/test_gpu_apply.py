@@ -162,7 +162,7 @@ def test_autotune_selects_a_variant_with_identical_results(N):
     try:
         for dt, tdt in (("f64", torch.float64), ("f32", torch.float32)):
             chosen, times = g.autotune(lam=2.0, tau=0.0, dtype=dt, reps=5)
-            nvar = 4 if N <= 5 else 1
+            nvar = 4 if N <= 5 else 2
             print(f"N={N} {dt}: chosen {chosen}, ms per apply {times}")
             assert 0 <= chosen < nvar
             assert P.ax_variant(N, dt) == chosen
