@@ -257,12 +257,20 @@ def run_batch_compare(P, torch, nb=64, prec=None, tol=1e-8):
     t_serial, serial_iters = serial()
     t_batch, (xs, iters, rel, st) = batched()
     dofs = sum(g.ndof for g in meshes)
-    return {"workload": f"{nb} solves, n~U{{32..128}}, N~U{{4..8}}, lambda=10^U(0,3), "
-                        "PCG + p-multigrid on halved degrees, tol 1e-8",
-            "total_dofs": dofs, "batched_s": round(t_batch, 3), "serial_s": round(t_serial, 3),
-            "speedup": round(t_serial / t_batch, 2), "iters_max": max(iters), "iters_sum": sum(iters),
-            "serial_iters_sum": sum(serial_iters),
-            "max_relres": max(rel), "status": st}
+    out = {"workload": f"{nb} solves, n~U{{32..128}}, N~U{{4..8}}, lambda=10^U(0,3), "
+                       "PCG + p-multigrid on halved degrees, tol 1e-8",
+           "total_dofs": dofs, "batched_s": round(t_batch, 3), "serial_s": round(t_serial, 3),
+           "speedup": round(t_serial / t_batch, 2), "iters_max": max(iters), "iters_sum": sum(iters),
+           "serial_iters_sum": sum(serial_iters),
+           "max_relres": max(rel), "status": st}
+    if prec is None:
+        # the same batch with the FP32 preconditioner (FP64 CG), batched only
+        o = P.default_opts(pc=P.PC_PMG, prec=P.PREC_MIXED)
+        batched()
+        t_m, (_, it_m, rel_m, st_m) = batched()
+        out["mixed"] = {"batched_s": round(t_m, 3), "iters_sum": sum(it_m), "max_relres": max(rel_m),
+                        "status": st_m}
+    return out
 
 
 def run_grad_compare(P, torch, n=128, N=5, lam=1.0, tol=1e-8, reps=3):
