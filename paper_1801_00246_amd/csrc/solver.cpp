@@ -932,7 +932,7 @@ bool batch_coarse_fused() {
 // Null when the solves' coarsest levels differ in degree or precision (the
 // caller then keeps them separate).
 std::unique_ptr<CoarseBatchSet> make_coarse_batch(std::vector<std::unique_ptr<Solver>>& sv,
-                                                  const ipdg_solve_opts& o, hipStream_t user) {
+                                                  const ipdg_solve_opts& o) {
   const int na = int(sv.size());
   const Level& c0 = sv[0]->coarsest();
   for (int k = 1; k < na; ++k) {
@@ -1060,7 +1060,6 @@ std::unique_ptr<CoarseBatchSet> make_coarse_batch(std::vector<std::unique_ptr<So
   cb->ev.assign(na, nullptr);
   for (int k = 0; k < na; ++k) IPDG_HIP(hipEventCreateWithFlags(&cb->ev[k], hipEventDisableTiming));
   IPDG_HIP(hipEventCreateWithFlags(&cb->ev_done, hipEventDisableTiming));
-  (void)user;
   return cb;
 }
 
@@ -1141,13 +1140,13 @@ ipdg_status solve_batch(int nb, ipdg_mesh_s* const* meshes, const double* lambda
         delete g_cb;
         g_cb = nullptr;
         g_cb_valid = false;
-        g_cb = make_coarse_batch(sv, o, s).release();
+        g_cb = make_coarse_batch(sv, o).release();
         g_cb_key = key;
         g_cb_valid = true;
       }
       cb = g_cb;
     } else {
-      own_cb = make_coarse_batch(sv, o, s);   // another thread holds the cached set
+      own_cb = make_coarse_batch(sv, o);   // another thread holds the cached set
       cb = own_cb.get();
     }
   }
