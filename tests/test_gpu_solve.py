@@ -288,6 +288,32 @@ def test_batch_fused_coarse_matches_separate_coarse(prec, monkeypatch):
             assert np.linalg.norm(a - c) <= 1e-6 * np.linalg.norm(c)
 
 
+def test_batch_fused_coarse_degree_two(monkeypatch):
+    """Fused coarsest levels at degree 2 (explicit levels 4 -> 2), against
+    per-solve coarse launches."""
+    draws = [(9, 1.0), (13, 20.0), (11, 300.0)]
+    o = P.default_opts(pc=P.PC_PMG, degrees=[4, 2], coarse_tol=0.0, coarse_max_iters=30)
+    meshes, bs, As, lams = [], [], [], []
+    for i, (n, lam) in enumerate(draws):
+        msh = synth.square_mesh(n, jitter=0.15, seed=130 + i, bc="mixed")
+        m = OracleMesh(msh.VX, msh.VY, msh.EToV, msh.EToB, 4)
+        b = mass_apply(m, synth.nodal_normal(msh.K, m.Np, seed=140 + i))
+        As.append(assemble(m, lam, 25.0))
+        meshes.append(P.Mesh.from_synth(4, msh))
+        bs.append(dev(b))
+        lams.append(lam)
+    xf, itf, _, st = P.solve_batch(meshes, lams, bs, tol=1e-8, opts=o)
+    monkeypatch.setenv("IPDG_BATCH_COARSE", "separate")
+    xs, its, _, st2 = P.solve_batch(meshes, lams, bs, tol=1e-8, opts=o)
+    assert st == 0 and st2 == 0
+    for i, A in enumerate(As):
+        a, c = host(xf[i]), host(xs[i])
+        print(f"solve {i}: fused {itf[i]}, separate {its[i]}, rel diff {np.linalg.norm(a - c) / np.linalg.norm(c):.2e}")
+        assert true_relres(A, a, host(bs[i])) <= 1e-8
+        assert itf[i] == its[i]
+        assert np.linalg.norm(a - c) <= 1e-10 * np.linalg.norm(c)
+
+
 def test_batch_repeated_calls_reuse_and_rebuild():
     """Repeated batches of the same solves reuse the captured split graphs and
     the fused coarse set; a new right-hand side gives its own solution, and a
