@@ -165,7 +165,11 @@ ipdg_status ipdg_precond_apply(ipdg_mesh mesh, double lambda, double tau,
  * launch per coarse-CG iteration covers all solves (their concatenated
  * coarsest levels), between each solve's captured parts before and after
  * it; the environment variable IPDG_BATCH_COARSE=separate keeps each solve's
- * coarsest level on its own launches.  The persistent single-launch coarse
+ * coarsest level on its own launches.  The library keeps the last fused
+ * batch's concatenated coarsest levels (about a dozen vectors of the
+ * members' degree-1 sizes, plus their metric and connectivity) allocated,
+ * for reuse by the next batch of the same solves, until a different batch
+ * replaces them.  The persistent single-launch coarse
  * form is never used in a batch (its grids could not all be resident).
  * All meshes must live on one device.  opts NULL: defaults with the
  * block inverse-mass preconditioner.  Returns IPDG_NOT_CONVERGED if any
