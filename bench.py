@@ -37,7 +37,7 @@ FP32_PEAK_TFS = 157.3          # vector FP32, published
 # counter's reading for a device-to-device copy of known size.  Valid only for
 # the kernel sources it was measured on (their SHA-256), else reported null.
 MEASURED_TRAFFIC = {"N": 3, "dtype": "f64", "lambda": 100.0, "variant": 0, "bytes": 113019193,
-                    "sources_sha256": "eef9e90bf9e21a95a1cc6a645e7e38cd179b2ab452b13a244becd2997d4c2b3d",
+                    "sources_sha256": "d6ac37a497eecd07abd7c1ddf8785f9c8a7c8a8c73052e41dd3e566a7469dede",
                     "profile": "profiles/k_ax_N3_f64_524288.md"}
 
 KERNEL_SOURCES = ("elem_inst.hip", "sipdg_core.hpp", "tri.hpp", "device_common.hpp",

@@ -579,16 +579,25 @@ __global__ __launch_bounds__(kBlock) void k_coarse_cgcg(
     n_rr = n_g = n_d = d.ntiles;
   }
   const bool b0 = lead && threadIdx.x == 0;
-  if (first) {
-    if (outer && *outer) {               // outer solve finished: keep the last record
-      if (b0) sc->done = 1;
-      return;
+  // true: this launch has nothing to do (the outer solve, or this coarse
+  // solve, is finished)
+  auto finished = [&]() -> bool {
+    if (first) {
+      if (outer && *outer) {             // outer solve finished: keep the last record
+        if (b0) sc->done = 1;
+        return true;
+      }
+      return false;
     }
-  } else if (sc->done) {
-    return;
+    return sc->done != 0;
+  };
+  // In a batch many members finish their coarse solve early: test first.
+  if constexpr (BATCH) {
+    if (finished()) return;
   }
   // The element's own state does not depend on alpha and beta: its loads
-  // are issued before the reduction so that the two latencies overlap.
+  // are issued before the reduction (and, for one solve, before the done
+  // test) so that the latencies overlap.
   const bool live = ltile * kBlock + (int)threadIdx.x < K;
   const int e = base + ltile * kBlock + threadIdx.x;   // element (global id in a batch)
   const size_t o = (size_t)(live ? e : 0) * Np;
@@ -633,6 +642,9 @@ __global__ __launch_bounds__(kBlock) void k_coarse_cgcg(
         });
       });
     }
+  }
+  if constexpr (!BATCH) {
+    if (finished()) return;
   }
   double tot[3];
   slot_totals3(pin, n_rr, n_g, n_d, tot);
