@@ -147,43 +147,111 @@ def copy_probe(torch, nbytes, reps=20):
     return 2 * 8 * n / t / 1e9
 
 
-def cpu_baseline(N, lam, target_s=12.0):
-    """The FP64 oracle timed on the host: block rows of the assembled operator
-    for a contiguous sample of elements of the same mesh, multiplied
-    repeatedly (sparse matrix-vector product over those rows)."""
+_MF = {}
+
+
+def _mf_init(N, n):
+    """Worker set-up (spawned process): the oracle's matrix-free operator on
+    the workload mesh, one BLAS thread."""
+    from threadpoolctl import threadpool_limits
+    import synth
+    from oracle.assemble import OracleMesh
+    from oracle.matfree import MatFree
+    threadpool_limits(1)
+    msh = synth.ax_sweep_mesh(n, seed=0)
+    m = OracleMesh(msh.VX, msh.VY, msh.EToV, msh.EToB, N)
+    _MF["mf"] = MatFree(m)
+    _MF["x"] = synth.nodal_normal(msh.K, m.Np, seed=1)
+
+
+def _mf_rows(args):
+    """Rows of the elements [lo, hi), `reps` times; returns the seconds."""
+    import numpy as np
+    lo, hi, lam, ctau, reps = args
+    mf = _MF["mf"]
+    el = np.arange(lo, hi)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        mf.apply(lam, ctau, _MF["x"], elems=el)
+    return time.perf_counter() - t0
+
+
+def cpu_baseline(N, lam, target_s=6.0):
+    """The FP64 oracle timed on the host's cores, on the operator workload.
+
+    Leg 1 (the reported value): the oracle's matrix-free operator (Alg. AxG +
+    Alg. AxKernel) over all 524,288 elements, split into contiguous element
+    ranges over a pool of spawned worker processes (one BLAS thread each),
+    repeated until about target_s seconds have passed.  Leg 2: the same on one
+    core.  Leg 3: the oracle's assembled block rows of the first 32,768
+    elements multiplied by scipy's CSR product (single-threaded)."""
+    import concurrent.futures as cf
+    import multiprocessing as mp
     import numpy as np
     import scipy.sparse as sp
+    from threadpoolctl import threadpool_limits
     import synth
     from oracle.assemble import OracleMesh, block_rows
-    try:
-        from threadpoolctl import threadpool_info
-        cores = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
-    except Exception:
-        cores = 1
-    msh = synth.ax_sweep_mesh(512, seed=0)
-    m = OracleMesh(msh.VX, msh.VY, msh.EToV, msh.EToB, N)
-    Np = m.Np
-    S = 32768
-    t0 = time.time()
-    r, c, b = block_rows(m, lam, float((N + 1) ** 2), elems=np.arange(S))
-    ii = np.broadcast_to(r[:, None, None] * Np + np.arange(Np)[None, :, None], b.shape).ravel()
-    jj = np.broadcast_to(c[:, None, None] * Np + np.arange(Np)[None, None, :], b.shape).ravel()
-    A = sp.csr_matrix((b.ravel(), (ii, jj)), shape=(S * Np, msh.K * Np))
-    t_asm = time.time() - t0
-    x = synth.nodal_normal(msh.K, Np, seed=1)
-    reps = 0
-    t0 = time.time()
-    while True:
-        A @ x
-        reps += 1
-        dt = time.time() - t0
-        if dt >= target_s or reps >= 20000:
-            break
-    rate = reps * S * Np / dt / 1e9
-    return {"value": rate, "unit": "GDOF/s", "cores": cores, "kind": "oracle",
-            "sample": (f"assembled block rows of elements 0..{S - 1} (of 524,288) at N={N}, "
-                       f"lambda={lam}, multiplied {reps}x in {dt:.1f}s; assembly of the sample "
-                       f"took {t_asm:.1f}s (excluded)")}
+    n = 512
+    K = 2 * n * n
+    Np = np_of(N)
+    ctau = float((N + 1) ** 2)
+    nproc = os.cpu_count() or 1
+    workers = max(1, min(16, nproc))
+    out = {"unit": "GDOF/s", "kind": "oracle"}
+    ctx = mp.get_context("spawn")
+    with cf.ProcessPoolExecutor(max_workers=workers, mp_context=ctx, initializer=_mf_init,
+                                initargs=(N, n)) as ex:
+        bounds = np.linspace(0, K, workers + 1).astype(int)
+        # warm-up round (also makes every worker finish its set-up)
+        list(ex.map(_mf_rows, [(int(bounds[i]), int(bounds[i + 1]), lam, ctau, 1) for i in range(workers)]))
+        t0 = time.perf_counter()
+        t1 = max(ex.map(_mf_rows, [(int(bounds[i]), int(bounds[i + 1]), lam, ctau, 1)
+                                   for i in range(workers)]))
+        reps = max(1, int(target_s / max(t1, 1e-3)))
+        t0 = time.perf_counter()
+        list(ex.map(_mf_rows, [(int(bounds[i]), int(bounds[i + 1]), lam, ctau, reps)
+                               for i in range(workers)]))
+        dt_all = time.perf_counter() - t0
+    out["value"] = reps * K * Np / dt_all / 1e9
+    out["cores"] = workers
+    out["host_cpus"] = nproc
+    out["sample"] = (f"matrix-free oracle (Alg. AxG + AxKernel, numpy FP64) over all {K} elements "
+                     f"at N={N}, lambda={lam}, {reps} applies in {dt_all:.1f}s, element ranges over "
+                     f"{workers} spawned processes of 1 BLAS thread each (set-up excluded)")
+    # one core, in this process
+    _mf_init(N, n)
+    with threadpool_limits(1):
+        S = 65536
+        _mf_rows((0, S, lam, ctau, 1))
+        r1 = 0
+        t0 = time.perf_counter()
+        while time.perf_counter() - t0 < target_s:
+            _mf_rows((0, S, lam, ctau, 1))
+            r1 += 1
+        dt1 = time.perf_counter() - t0
+        out["one_core"] = {"value": r1 * S * Np / dt1 / 1e9, "cores": 1,
+                           "sample": f"elements 0..{S - 1}, {r1} applies in {dt1:.1f}s"}
+        _MF.clear()
+        # assembled CSR rows of a sample, scipy's single-threaded product
+        msh = synth.ax_sweep_mesh(n, seed=0)
+        m = OracleMesh(msh.VX, msh.VY, msh.EToV, msh.EToB, N)
+        S = 32768
+        r, c, b = block_rows(m, lam, ctau, elems=np.arange(S))
+        ii = np.broadcast_to(r[:, None, None] * Np + np.arange(Np)[None, :, None], b.shape).ravel()
+        jj = np.broadcast_to(c[:, None, None] * Np + np.arange(Np)[None, None, :], b.shape).ravel()
+        A = sp.csr_matrix((b.ravel(), (ii, jj)), shape=(S * Np, K * Np))
+        x = synth.nodal_normal(K, Np, seed=1)
+        r2 = 0
+        t0 = time.perf_counter()
+        while time.perf_counter() - t0 < target_s / 2:
+            A @ x
+            r2 += 1
+        dt2 = time.perf_counter() - t0
+        out["assembled_spmv_one_core"] = {"value": r2 * S * Np / dt2 / 1e9, "cores": 1,
+                                          "sample": f"CSR block rows of elements 0..{S - 1}, "
+                                                    f"{r2} products in {dt2:.1f}s (assembly excluded)"}
+    return out
 
 
 def run_pcg_compare(P, torch, coarse_caps=(150, 300)):
@@ -395,7 +463,7 @@ def main():
         for Ns in [int(v) for v in args.sweep_orders.split(",")]:
             for dname, dts, ws in (("f64", torch.float64, 8), ("f32", torch.float32, 4)):
                 for lam in (0.0, 100.0):
-                    msw, _ = time_applies(P, torch, msh, Ns, dts, lam, 50, 5, args.rotate_gb * 1e9)
+                    msw, _ = time_applies(P, torch, msh, Ns, dts, lam, 100, 5, args.rotate_gb * 1e9)
                     rf = roofline(Ns, ws, msw)
                     sweep.append({"N": Ns, "dtype": dname, "lambda": lam, "ms": round(msw, 5),
                                   "GDOF/s": round(msh.K * np_of(Ns) / (msw * 1e-3) / 1e9, 3),

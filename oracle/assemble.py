@@ -134,20 +134,6 @@ class OracleMesh:
         # clockwise
         return xa, ya, xb, yb, length, dy / length, -dx / length
 
-    def penalty(self, e, f, ctau):
-        """tau_F = c_tau max(|F|/|E-|, |F|/|E+|); boundary faces one-sided."""
-        _, _, _, _, length, _, _ = self.face_geometry(e, f)
-        nb = self.EToE[e, f]
-        tau = length / self.area[e]
-        inner = nb >= 0
-        tau = np.where(inner, np.maximum(tau, length / self.area[np.where(inner, nb, 0)]), tau)
-        return ctau * tau
-
-
-def default_ctau(N: int) -> float:
-    """Penalty constant used by the workloads: (N+1)^2."""
-    return float((N + 1) ** 2)
-
 
 def _physical_grad(m, e, Lr, Ls):
     gx = m.rx[e][:, None, None] * Lr + m.sx[e][:, None, None] * Ls

@@ -219,8 +219,29 @@ class RefTriangle:
         L = self.qL
         return (L * self.qw[:, None]).T @ L
 
-    def stiffness_rr(self):
-        return (self.qLr * self.qw[:, None]).T @ self.qLr
+    def face_points(self, f, t):
+        """Reference coordinates of face f at the 1-D parameter t in [-1, 1],
+        running counter-clockwise from vertex f to vertex (f+1) % 3."""
+        t = np.asarray(t, dtype=np.float64)
+        if f == 0:
+            return t, -np.ones_like(t)
+        if f == 1:
+            return -t, t
+        return -np.ones_like(t), -t
+
+    def lift(self):
+        """LIFT = M^{-1} E (Np x 3 Nfp, Eq. elLift on the reference element):
+        column f Nfp + k holds face f's mass against face node k,
+        E_ij = int_{-1}^{1} l_i l_j dt along the face parameter of length 2
+        (the physical length enters through the surface factor), by 1-D
+        Gauss quadrature."""
+        g, w = self.g1, self.w1
+        E = np.zeros((self.Np, 3 * self.Nfp))
+        for f in range(3):
+            Lf, _, _ = self.lagrange(*self.face_points(f, g))
+            Ef = (Lf * w[:, None]).T @ Lf
+            E[:, f * self.Nfp:(f + 1) * self.Nfp] = Ef[:, self.Fmask[f]]
+        return np.linalg.solve(self.mass(), E)
 
     def deriv_matrices(self):
         """D_r, D_s with (D_r u)_i = d/dr of the interpolant at node i,

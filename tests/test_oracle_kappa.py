@@ -82,3 +82,53 @@ def test_kappa_gradient_matches_central_differences(bc):
     Lp = loss_and_grads(m, lam, ctau, kap, f + h * df, ut)[0]
     Lm = loss_and_grads(m, lam, ctau, kap, f - h * df, ut)[0]
     assert gf @ df == pytest.approx((Lp - Lm) / (2 * h), rel=1e-5)
+
+
+def two_material_problem(n, N, k1, k2):
+    """n x n unjittered squares (n even, so x = 1/2 is a mesh line), kappa =
+    k1 left of x = 1/2 and k2 right of it, Dirichlet faces on x = 0 and
+    x = 1, Neumann faces on y = 0 and y = 1; u continuous, piecewise linear
+    in x with the continuous flux kappa du/dx = 1."""
+    msh = synth.square_mesh(n, bc="dirichlet")
+    EToB = msh.EToB.copy()
+    for f in range(3):
+        a, b = msh.EToV[:, f], msh.EToV[:, (f + 1) % 3]
+        horiz = np.abs(msh.VY[a] - msh.VY[b]) < 1e-14
+        EToB[(EToB[:, f] != 0) & horiz, f] = 2
+    msh = synth.Mesh(msh.VX, msh.VY, msh.EToV, EToB, n=n)
+    m = omesh(msh, N)
+    cx = msh.VX[msh.EToV].mean(1)
+    kap = np.where(cx < 0.5, k1, k2)
+    x, _ = m.node_coords()
+    left = (cx < 0.5)[:, None]
+    u = np.where(left, x / k1, 0.5 / k1 + (x - 0.5) / k2).ravel()
+    inner = ~(m.EToB == 1).any(1)          # elements without a Dirichlet face
+    return m, kap, u, inner
+
+
+@pytest.mark.parametrize("N", [1, 2, 4])
+def test_kappa_flux_continuity_closed_form(N):
+    """For u with a continuous flux kappa grad u and no jump, the kappa-weighted
+    form reduces, on every element without a Dirichlet face, to the volume
+    flux balance, which vanishes: (A u)_i = lambda (M u)_i.  This pins the
+    flux average {kappa d_n u} (an average of kappa times an average of
+    d_n u would leave a residual at x = 1/2)."""
+    from oracle.matfree import MatFree
+    m, kap, u, inner = two_material_problem(8, N, 1.0, 5.0)
+    rows = np.repeat(inner, m.Np)
+    for lam in (0.0, 3.0):
+        A = assemble(m, lam, 16.0, kappa=kap)
+        Au = A @ u
+        Mu = (mass_matrix(m) @ u)
+        scale = (abs(A) @ np.abs(u)).max()
+        assert np.abs(Au - lam * Mu)[rows].max() <= 1e-12 * scale
+        y = MatFree(m).apply(lam, 16.0, u, kappa=kap)
+        assert np.abs(y - lam * Mu)[rows].max() <= 1e-12 * scale
+    # the check is sensitive: u = x (a flux jump of 4 at x = 1/2) leaves a
+    # residual on the rows of the elements at the interface
+    x, _ = m.node_coords()
+    A = assemble(m, 0.0, 16.0, kappa=kap)
+    r = (A @ x.ravel()).reshape(m.K, m.Np)
+    cx = m.VX[m.EToV].mean(1)
+    at = np.abs(cx - 0.5) < 1.0 / 8
+    assert np.abs(r[at & inner]).max() > 1e-6 * (abs(A) @ np.abs(x.ravel())).max()
