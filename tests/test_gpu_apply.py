@@ -151,12 +151,16 @@ def test_kappa_one_equals_plain_operator():
     assert np.linalg.norm(a - b) <= 1e-14 * np.linalg.norm(a)
 
 
-@pytest.mark.parametrize("N", [2, 7])
-def test_autotune_selects_a_variant_with_identical_results(N):
+@pytest.mark.parametrize("use_kappa", [False, True])
+@pytest.mark.parametrize("N", list(range(1, 9)))
+def test_autotune_selects_a_variant_with_identical_results(N, use_kappa):
     """The autotuner times every variant of the degree, selects the fastest,
-    and every variant gives the same operator output bit for bit."""
+    and every variant gives the same operator output bit for bit, with and
+    without a coefficient (each variant has its own coefficient-weighted
+    instantiation)."""
     msh = synth.permuted(synth.square_mesh(40, jitter=0.2, seed=21, bc="mixed"), seed=22)
-    g = P.Mesh.from_synth(N, msh)
+    kap = synth.kappa_draw(msh.K, seed=24) if use_kappa else None
+    g = P.Mesh.from_synth(N, msh, kappa=kap)
     x = synth.nodal_normal(msh.K, (N + 1) * (N + 2) // 2, seed=23)
     saved = {dt: P.ax_variant(N, dt) for dt in ("f64", "f32")}
     try:

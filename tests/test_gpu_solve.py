@@ -129,6 +129,72 @@ def test_one_vcycle_matches_oracle():
     assert rel32 <= 1e-4
 
 
+@pytest.fixture(scope="module")
+def large_vcycle():
+    """182 x 182 jittered squares, permuted (66,248 triangles): the degree-1
+    level spans 259 element tiles of 256, so every coarse launch sums more
+    than 256 block partials (and 777 at its first launch), the size class of
+    the 131,072-element p-multigrid workload.  Oracle V-cycle 3 -> 1 with
+    fixed spectral estimates and a fixed coarse iteration count."""
+    degrees = (3, 1)
+    msh = synth.permuted(synth.square_mesh(182, jitter=0.2, seed=4), seed=5)
+    ctau, lam, rho = 16.0, 2.0, [1.8, 1.6]
+    B = S.PMG(msh, degrees, lam, ctau, rho, coarse_tol=0.0, coarse_max=9)
+    r = synth.nodal_normal(msh.K, 10, seed=9)
+    return msh, degrees, ctau, lam, rho, r, B(r)
+
+
+@pytest.mark.parametrize("persistent", [0, 1])
+def test_one_vcycle_large_coarse_level_matches_oracle(large_vcycle, persistent):
+    msh, degrees, ctau, lam, rho, r, zo = large_vcycle
+    assert msh.K // 256 > 256
+    g = P.Mesh.from_synth(3, msh)
+    o = pmg_opts(degrees, rho, coarse_tol=0.0, coarse_max=9, coarse_persistent=persistent)
+    z, info = g.precond(dev(r), lam=lam, tau=ctau, opts=o)
+    rel = np.linalg.norm(host(z) - zo) / np.linalg.norm(zo)
+    assert info["coarse_iters"] == 9
+    o32 = pmg_opts(degrees, rho, prec=P.PREC_MIXED, coarse_tol=0.0, coarse_max=9,
+                   coarse_persistent=persistent)
+    z32, _ = g.precond(dev(r), lam=lam, tau=ctau, opts=o32)
+    rel32 = np.linalg.norm(host(z32) - zo) / np.linalg.norm(zo)
+    print(f"K={msh.K} persistent={persistent}: FP64 V-cycle rel {rel:.2e}, FP32 V-cycle rel {rel32:.2e}")
+    assert rel <= 1e-11
+    assert rel32 <= 1e-4
+    g.close()
+
+
+def test_batch_fused_coarse_with_a_large_member(monkeypatch):
+    """A fused coarse batch whose largest member's degree-1 level spans 259
+    tiles (more than 256 partials per member), against per-solve coarse
+    launches and the oracle's residual."""
+    draws = [(182, 2, 5.0), (10, 4, 1.0), (13, 3, 100.0)]
+    o = P.default_opts(pc=P.PC_PMG, coarse_tol=0.0, coarse_max_iters=20)
+    meshes, bs, As, lams = [], [], [], []
+    for i, (n, N, lam) in enumerate(draws):
+        msh = synth.square_mesh(n, jitter=0.15, seed=150 + i)
+        m = OracleMesh(msh.VX, msh.VY, msh.EToV, msh.EToB, N)
+        b = mass_apply(m, synth.nodal_normal(msh.K, m.Np, seed=160 + i))
+        As.append(assemble(m, lam, float((N + 1) ** 2)))
+        meshes.append(P.Mesh.from_synth(N, msh))
+        bs.append(dev(b))
+        lams.append(lam)
+    assert meshes[0].K // 256 > 256
+    xf, itf, relf, st = P.solve_batch(meshes, lams, bs, tol=1e-8, opts=o)
+    monkeypatch.setenv("IPDG_BATCH_COARSE", "separate")
+    xs, its, _, st2 = P.solve_batch(meshes, lams, bs, tol=1e-8, opts=o)
+    assert st == 0 and st2 == 0
+    for i, A in enumerate(As):
+        a, c = host(xf[i]), host(xs[i])
+        d = np.linalg.norm(a - c) / np.linalg.norm(c)
+        print(f"solve {i}: fused {itf[i]}, separate {its[i]}, rel diff {d:.2e}")
+        assert true_relres(A, a, host(bs[i])) <= 1e-8
+        assert relf[i] <= 1e-8
+        assert itf[i] == its[i]
+        assert d <= 1e-10
+    for g in meshes:
+        g.close()
+
+
 def test_vcycle_coarse_tolerance_stop_matches_oracle():
     """Coarsest-level Jacobi-PCG stopped by its relative tolerance well before
     its cap: the same number of coarse iterations and the same V-cycle output
