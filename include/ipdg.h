@@ -148,6 +148,24 @@ ipdg_status ipdg_pcg_solve(ipdg_mesh mesh, double lambda, double tau, const doub
                            double* x, double tol, const ipdg_solve_opts* opts,
                            ipdg_solve_info* info, void* hip_stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the solve
+ * of ipdg_pcg_solve, same arguments and results, for the identity, Jacobi
+ * and block inverse-mass preconditioners in FP64 (opts->prec must be
+ * IPDG_PREC_FP64, opts->reliable_drop 0), calling no hipMalloc, hipFree or
+ * other allocating routine.  Its work vectors, block partial sums and device
+ * scalars live in one file-scope device array of the library (about 50 MB,
+ * held on every GPU the library runs on until the process ends), so K*Np
+ * must not exceed 1,048,576 (IPDG_EINVAL otherwise).  Every call on a GPU
+ * shares that GPU's array: calls that overlap on one GPU (other streams,
+ * other threads) race and must be serialised by the caller.  Kernels run
+ * directly on hip_stream (no internal stream, no captured graph); the call
+ * synchronises hip_stream before returning.  x (device, FP64) holds x0 on
+ * entry and the solution on exit, and is the iterate throughout. */
+ipdg_status ipdg_pcg_solve_noalloc(ipdg_mesh mesh, double lambda, double tau, const double* b,
+                                   double* x, double tol, const ipdg_solve_opts* opts,
+                                   ipdg_solve_info* info, void* hip_stream);
+
 /* One application z = B r of the preconditioner that ipdg_pcg_solve would use
  * (device FP64 vectors).  Used to check a single V-cycle. */
 ipdg_status ipdg_precond_apply(ipdg_mesh mesh, double lambda, double tau,

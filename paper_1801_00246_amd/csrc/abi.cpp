@@ -5,6 +5,7 @@
 #include <string>
 
 #include "handle.hpp"
+#include "noalloc.hpp"
 #include "refelem.hpp"
 #include "solver.hpp"
 
@@ -127,6 +128,11 @@ ipdg_status ipdg_mesh_create(int N, int Nv, const double* VX, const double* VY, 
                          hipMemcpyHostToDevice));
     }
     upload_kappa(m.get(), kappa);
+    // the degree's operator tables are resident from here on (calls that
+    // must not allocate rely on that)
+    (void)ipdg::device_ops(N, ipdg::Kind::F64);
+    (void)ipdg::device_ops(N, ipdg::Kind::F32);
+    ipdg::noalloc_prepare();
     *out = m.release();
     return IPDG_OK;
   });
@@ -256,12 +262,12 @@ ipdg_status ipdg_autotune_apply(ipdg_mesh mesh, double lambda, double tau, ipdg_
       }
     } catch (...) {
       ipdg::set_ax_variant(N, fp32, prev);
-      hipEventDestroy(e0);
-      hipEventDestroy(e1);
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
       throw;
     }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     ipdg::set_ax_variant(N, fp32, best);
     *chosen = best;
     return IPDG_OK;
@@ -297,6 +303,20 @@ ipdg_status ipdg_pcg_solve(ipdg_mesh mesh, double lambda, double tau, const doub
     else ipdg_default_opts(&o);
     return ipdg::pcg_solve(mesh, lambda, tau, b, x, tol, o, info,
                            static_cast<hipStream_t>(hip_stream));
+  });
+}
+
+ipdg_status ipdg_pcg_solve_noalloc(ipdg_mesh mesh, double lambda, double tau, const double* b,
+                                   double* x, double tol, const ipdg_solve_opts* opts,
+                                   ipdg_solve_info* info, void* hip_stream) {
+  return guarded([&]() -> ipdg_status {
+    if (!mesh) return fail(IPDG_EINVAL, "mesh is null");
+    DeviceGuard dg(mesh);
+    ipdg_solve_opts o;
+    if (opts) o = *opts;
+    else ipdg_default_opts(&o);
+    return ipdg::pcg_solve_noalloc(mesh, lambda, tau, b, x, tol, o, info,
+                                   static_cast<hipStream_t>(hip_stream));
   });
 }
 

@@ -300,6 +300,10 @@ __global__ __launch_bounds__(kBlock) void k_recip(double* __restrict__ d, float*
 
 __global__ void k_set_scal(CGScal* sc, CGScal v) { *sc = v; }
 
+__global__ __launch_bounds__(kBlock) void k_fill(double* __restrict__ p, double v, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)kBlock + threadIdx.x; i < n; i += (size_t)gridDim.x * kBlock) p[i] = v;
+}
+
 __global__ void k_zero_ints(int* p, int n) {
   for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0;
 }
@@ -416,6 +420,11 @@ hipError_t recip(double* d, float* d32, size_t n, hipStream_t s) {
 
 hipError_t zero_ints(void* p, int n, hipStream_t s) {
   hipLaunchKernelGGL(k_zero_ints, dim3(1), dim3(64), 0, s, static_cast<int*>(p), n);
+  return hipGetLastError();
+}
+
+hipError_t fill(double* p, double v, size_t n, hipStream_t s) {
+  LAUNCH(k_fill, n, s, p, v, n);
   return hipGetLastError();
 }
 

@@ -42,5 +42,6 @@ hipError_t cg_pupdate_state(bool fp32, void* p, const void* z, const CGScal* sc,
 hipError_t recip(double* d, float* d32, size_t n, hipStream_t s);
 hipError_t set_scal(CGScal* sc, const CGScal& v, hipStream_t s);
 hipError_t zero_ints(void* p, int n, hipStream_t s);
+hipError_t fill(double* p, double v, size_t n, hipStream_t s);
 
 }  // namespace ipdg

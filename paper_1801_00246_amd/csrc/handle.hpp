@@ -54,6 +54,9 @@ class DevBuf {
 // Reference operators of degree N in the precision of `kind` (F32_IN64 uses
 // FP32 tables), resident on the current device for the process lifetime.
 const void* device_ops(int N, Kind kind);
+// The same table if it is already resident on the current device, else null
+// (never uploads).
+const void* device_ops_resident(int N, Kind kind);
 // Interpolation matrix degree Nc -> Nf (Np(Nf) x Np(Nc)), FP64 or FP32.
 const void* device_interp(int Nc, int Nf, bool fp32);
 

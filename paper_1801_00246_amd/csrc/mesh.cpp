@@ -63,6 +63,14 @@ const void* device_ops(int N, Kind kind) {
   return p;
 }
 
+const void* device_ops_resident(int N, Kind kind) {
+  int dev = 0;
+  IPDG_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_mu);
+  auto it = g_ops.find(std::make_tuple(dev, N, int(kind != Kind::F64)));
+  return it == g_ops.end() ? nullptr : it->second;
+}
+
 const void* device_interp(int Nc, int Nf, bool fp32) {
   int dev = 0;
   IPDG_HIP(hipGetDevice(&dev));

@@ -66,6 +66,8 @@ _SIGS = {
     "ipdg_mass_apply": (C.c_int, [_P, C.c_int, _P, _P, _P]),
     "ipdg_pcg_solve": (C.c_int, [_P, C.c_double, C.c_double, _P, _P, C.c_double,
                                  C.POINTER(SolveOpts), C.POINTER(SolveInfo), _P]),
+    "ipdg_pcg_solve_noalloc": (C.c_int, [_P, C.c_double, C.c_double, _P, _P, C.c_double,
+                                         C.POINTER(SolveOpts), C.POINTER(SolveInfo), _P]),
     "ipdg_precond_apply": (C.c_int, [_P, C.c_double, C.c_double, C.POINTER(SolveOpts), _P, _P,
                                      C.POINTER(SolveInfo), _P]),
     "ipdg_helmholtz_solve_batch": (C.c_int, [C.c_int, _P, _P, C.c_double, _P, _P, C.c_double,
@@ -297,6 +299,18 @@ class Mesh:
         st = check(lib().ipdg_pcg_solve(self._h, float(lam), float(tau), pb, px, float(tol),
                                         C.byref(o), C.byref(info), _stream(stream)))
         return x, info.as_dict(), st
+
+    def pcg_noalloc(self, b, x, lam=0.0, tau=0.0, tol=1e-8, opts=None, stream=None):
+        """ipdg_pcg_solve_noalloc: solve A x = b in place in x (float64 device
+        tensors; x holds x0 on entry).  Returns (info dict, status)."""
+        import torch
+        pb = _dev_vec(b, self.ndof, (torch.float64,), "b")
+        px = _dev_vec(x, self.ndof, (torch.float64,), "x")
+        o = opts if opts is not None else default_opts()
+        info = SolveInfo()
+        st = check(lib().ipdg_pcg_solve_noalloc(self._h, float(lam), float(tau), pb, px, float(tol),
+                                                C.byref(o), C.byref(info), _stream(stream)))
+        return info.as_dict(), st
 
     def precond(self, r, lam=0.0, tau=0.0, opts=None, stream=None):
         import torch
