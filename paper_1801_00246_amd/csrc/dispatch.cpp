@@ -3,6 +3,7 @@
 
 #include <atomic>
 #include <cstdlib>
+#include <mutex>
 
 namespace ipdg {
 
@@ -11,12 +12,12 @@ namespace {
 // 1 = LDS-staged inputs/outputs, 2 = raised occupancy (degrees <= 5).
 // Defaults from measured sweeps of the 524,288-element operator workload.
 std::atomic<int> g_variant[2][9] = {{0, 0, 0, 0, 0, 3, 0, 0, 0}, {0, 2, 2, 0, 0, 1, 1, 1, 1}};
-bool env_read = false;
-}  // namespace
+std::once_flag env_once;
 
-int ax_variant(int N, bool fp32) {
-  if (!env_read) {
-    env_read = true;
+// The environment override, applied once per process before any variant is
+// read or set (thread-safe).
+void read_env() {
+  std::call_once(env_once, [] {
     if (const char* v = std::getenv("IPDG_AX_VARIANT")) {
       const int k = std::atoi(v);
       for (int n = 1; n <= 8; ++n) {
@@ -24,13 +25,18 @@ int ax_variant(int N, bool fp32) {
         g_variant[1][n] = n <= 5 ? k : (k & 1);
       }
     }
-  }
+  });
+}
+}  // namespace
+
+int ax_variant(int N, bool fp32) {
+  read_env();
   if (N < 1 || N > 8) return 0;
   return g_variant[fp32 ? 1 : 0][N].load();
 }
 
 void set_ax_variant(int N, bool fp32, int v) {
-  ax_variant(N, fp32);   // the environment override is read before any explicit choice
+  read_env();   // the environment override is read before any explicit choice
   if (N >= 1 && N <= 8) g_variant[fp32 ? 1 : 0][N] = (N <= 5) ? v : (v & 1);
 }
 
