@@ -33,6 +33,7 @@
 #ifndef IPDG_H
 #define IPDG_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -243,6 +244,18 @@ ipdg_status ipdg_ax_variant_set(int N, ipdg_dtype dtype, int variant);
  * and synchronises hip_stream.  On failure the previous variant is kept. */
 ipdg_status ipdg_autotune_apply(ipdg_mesh mesh, double lambda, double tau, ipdg_dtype dtype,
                                 int reps, int* chosen, double* times_ms, void* hip_stream);
+
+/* Empirical roofs of the current device (Sec. 5.1: the kernels are judged
+ * against a measured device-to-device copy rate).  ipdg_probe_copy: GB/s of
+ * read + write traffic of a vectorised (16 bytes per lane) copy kernel moving
+ * `bytes` per copy, rotating over `sets` source/destination pairs (sets *
+ * 2 * bytes larger than the last-level cache measures HBM) for `reps`
+ * copies on hip_stream.  ipdg_probe_fma: TFLOP/s (two per multiply-add) of
+ * independent FP64 or FP32 multiply-add chains with wave-uniform
+ * multipliers, every SIMD occupied.  Both allocate their buffers for the
+ * duration of the call and synchronise hip_stream. */
+ipdg_status ipdg_probe_copy(size_t bytes, int sets, int reps, double* gbs, void* hip_stream);
+ipdg_status ipdg_probe_fma(ipdg_dtype dtype, int reps, double* tflops, void* hip_stream);
 
 /* Message of the last failed call on this thread ("" after a success). */
 const char* ipdg_last_error(void);

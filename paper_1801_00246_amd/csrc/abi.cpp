@@ -6,6 +6,7 @@
 
 #include "handle.hpp"
 #include "noalloc.hpp"
+#include "probe.hpp"
 #include "refelem.hpp"
 #include "solver.hpp"
 
@@ -208,7 +209,7 @@ ipdg_status ipdg_ax_variant_set(int N, ipdg_dtype dtype, int variant) {
   return guarded([&]() -> ipdg_status {
     if (N < 1 || N > 8) return fail(IPDG_EINVAL, "degree must be 1..8");
     if (dtype != IPDG_F64 && dtype != IPDG_F32) return fail(IPDG_EINVAL, "bad dtype");
-    if (variant < 0 || variant >= ipdg::ax_variant_count(N))
+    if (!ipdg::ax_variant_exists(N, variant))
       return fail(IPDG_EINVAL, "degree " + std::to_string(N) + " has no operator variant " +
                                    std::to_string(variant));
     ipdg::set_ax_variant(N, dtype == IPDG_F32, variant);
@@ -225,9 +226,9 @@ ipdg_status ipdg_autotune_apply(ipdg_mesh mesh, double lambda, double tau, ipdg_
     const int N = mesh->host.N;
     const bool fp32 = dtype == IPDG_F32;
     const int prev = ipdg::ax_variant(N, fp32);
-    const int nvar = ipdg::ax_variant_count(N);
+    constexpr int nvar = 5;
     if (times_ms)
-      for (int v = 0; v < 4; ++v) times_ms[v] = -1.0;
+      for (int v = 0; v < nvar; ++v) times_ms[v] = -1.0;
     *chosen = prev;
     if (mesh->host.K == 0) return IPDG_OK;
     if (reps <= 0) reps = 20;
@@ -247,7 +248,9 @@ ipdg_status ipdg_autotune_apply(ipdg_mesh mesh, double lambda, double tau, ipdg_
     int best = prev;
     double best_ms = 0.0;
     try {
+      bool first = true;
       for (int v = 0; v < nvar; ++v) {
+        if (!ipdg::ax_variant_exists(N, v)) continue;
         ipdg::set_ax_variant(N, fp32, v);
         IPDG_HIP(ipdg::ax(N, k, a, s));
         IPDG_HIP(hipEventRecord(e0, s));
@@ -258,7 +261,8 @@ ipdg_status ipdg_autotune_apply(ipdg_mesh mesh, double lambda, double tau, ipdg_
         IPDG_HIP(hipEventElapsedTime(&ms, e0, e1));
         const double t = double(ms) / reps;
         if (times_ms) times_ms[v] = t;
-        if (v == 0 || t < best_ms) best = v, best_ms = t;
+        if (first || t < best_ms) best = v, best_ms = t;
+        first = false;
       }
     } catch (...) {
       ipdg::set_ax_variant(N, fp32, prev);
@@ -270,6 +274,23 @@ ipdg_status ipdg_autotune_apply(ipdg_mesh mesh, double lambda, double tau, ipdg_
     (void)hipEventDestroy(e1);
     ipdg::set_ax_variant(N, fp32, best);
     *chosen = best;
+    return IPDG_OK;
+  });
+}
+
+ipdg_status ipdg_probe_copy(size_t bytes, int sets, int reps, double* gbs, void* hip_stream) {
+  return guarded([&]() -> ipdg_status {
+    if (!gbs) return fail(IPDG_EINVAL, "gbs is null");
+    *gbs = ipdg::probe_copy_gbs(bytes, sets, reps, static_cast<hipStream_t>(hip_stream));
+    return IPDG_OK;
+  });
+}
+
+ipdg_status ipdg_probe_fma(ipdg_dtype dtype, int reps, double* tflops, void* hip_stream) {
+  return guarded([&]() -> ipdg_status {
+    if (!tflops) return fail(IPDG_EINVAL, "tflops is null");
+    if (dtype != IPDG_F64 && dtype != IPDG_F32) return fail(IPDG_EINVAL, "bad dtype");
+    *tflops = ipdg::probe_fma_tflops(dtype == IPDG_F32, reps, static_cast<hipStream_t>(hip_stream));
     return IPDG_OK;
   });
 }

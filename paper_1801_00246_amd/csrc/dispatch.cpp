@@ -11,7 +11,7 @@ namespace {
 // Operator kernel variant per precision (FP64, FP32) and degree; bits:
 // 1 = LDS-staged inputs/outputs, 2 = raised occupancy (degrees <= 5).
 // Defaults from measured sweeps of the 524,288-element operator workload.
-std::atomic<int> g_variant[2][9] = {{0, 0, 0, 0, 0, 3, 0, 0, 0}, {0, 2, 2, 0, 0, 1, 1, 1, 1}};
+std::atomic<int> g_variant[2][9] = {{0, 0, 0, 0, 4, 4, 4, 4, 4}, {0, 2, 2, 4, 4, 4, 4, 4, 4}};
 std::once_flag env_once;
 
 // The environment override, applied once per process before any variant is
@@ -21,8 +21,9 @@ void read_env() {
     if (const char* v = std::getenv("IPDG_AX_VARIANT")) {
       const int k = std::atoi(v);
       for (int n = 1; n <= 8; ++n) {
-        g_variant[0][n] = n <= 5 ? k : (k & 1);
-        g_variant[1][n] = n <= 5 ? k : (k & 1);
+        const int kn = ax_variant_exists(n, k) ? k : (k & 1);
+        g_variant[0][n] = kn;
+        g_variant[1][n] = kn;
       }
     }
   });
@@ -37,10 +38,22 @@ int ax_variant(int N, bool fp32) {
 
 void set_ax_variant(int N, bool fp32, int v) {
   read_env();   // the environment override is read before any explicit choice
-  if (N >= 1 && N <= 8) g_variant[fp32 ? 1 : 0][N] = (N <= 5) ? v : (v & 1);
+  if (ax_variant_exists(N, v)) g_variant[fp32 ? 1 : 0][N] = v;
 }
 
-int ax_variant_count(int N) { return N >= 1 && N <= 5 ? 4 : (N >= 6 && N <= 8 ? 2 : 0); }
+bool ax_variant_exists(int N, int v) {
+  if (N < 1 || N > 8) return false;
+  if (v == kAxCoop) return true;
+  return v >= 0 && v < (N <= 5 ? 4 : 2);
+}
+
+int ax_partials(int N, bool fp32, int K) {
+  if (ax_variant(N, fp32) == kAxCoop) {
+    int per;
+    return xcd_grid((K + kCoopTileElems - 1) / kCoopTileElems, per);
+  }
+  return elem_grid(K);
+}
 
 #define IPDG_SWITCH(N_, CALL)      \
   switch (N_) {                    \

@@ -4,6 +4,7 @@
 // same die (shared L2 for the neighbour gathers).
 #include "kernels.hpp"
 #include "sipdg_core.hpp"
+#include "sipdg_coop.hpp"
 #include "blas.hpp"
 
 #include <algorithm>
@@ -98,6 +99,145 @@ void k_ax(const TX* __restrict__ x, TY* __restrict__ y,
     block_sum<1>(v);
     if (threadIdx.x == 0) partials[blockIdx.x] = v[0];
   }
+}
+
+#ifndef IPDG_COOP_WAVES
+#define IPDG_COOP_WAVES 1
+#endif
+
+// Cooperative operator (sipdg_coop.hpp): a block of three waves per tile of
+// 64 elements; the partial sum of x . y (optional) is one per block.
+template <typename TC, typename TX, typename TY, bool KAP>
+__global__ __launch_bounds__(kCoopThreads) __attribute__((amdgpu_waves_per_eu(IPDG_COOP_WAVES))) void k_axc(const TX* __restrict__ x, TY* __restrict__ y,
+                                                      const TC* __restrict__ geo,
+                                                      const Conn* __restrict__ conn,
+                                                      const TC* __restrict__ kap,
+                                                      const TC* __restrict__ ops, TC lambda, TC ctau,
+                                                      int K, int per, double* __restrict__ partials,
+                                                      const int* __restrict__ skip) {
+  if (skip && *skip) return;
+  using CL = CoopLayout<N>;
+  constexpr int Nfp = Tri<N>::Nfp, P = kCoopPitch;
+  // degrees >= 5: the row phase on the matrix cores
+  constexpr bool kMf = N >= 5;
+  __shared__ TC U[Np * P];          // the tile's own values, then its outputs
+  __shared__ TC JM[3 * Nfp * P];    // jumps [u]_f at the face nodes
+  __shared__ TC TS[3 * Nfp * P];    // J |F|/|E| s_f at the face nodes
+  __shared__ TC SC[kMf ? sc_slot::kCount * P : 1];   // per-element row-phase factors
+  __shared__ double red[3];
+  const int e0 = xcd_tile(blockIdx.x, per) * kCoopTile;
+  const int ne = K - e0 < kCoopTile ? K - e0 : kCoopTile;
+  if (ne <= 0) {                    // a block past the last tile (the grid is rounded up)
+    if (partials && threadIdx.x == 0) partials[blockIdx.x] = 0.0;
+    return;
+  }
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const bool live = lane < ne;
+  // lanes past the mesh's end work on the tile's first element; their
+  // results are never stored
+  const int e = e0 + (live ? lane : 0);
+  CoopElem<TC> el;
+  el.rx = geo[4 * e + 0];
+  el.sx = geo[4 * e + 1];
+  el.ry = geo[4 * e + 2];
+  el.sy = geo[4 * e + 3];
+  el.ke = KAP ? kap[e] : TC(1);
+  el.c = conn[e];
+  // wave w's neighbour (across face w), in flight during the staging below
+  CoopNbr<N, TC> nb;
+  if (w == 0) coop_gather<N, 0, TC, TX, KAP>(el, x, geo, kap, nb);
+  else if (w == 1) coop_gather<N, 1, TC, TX, KAP>(el, x, geo, kap, nb);
+  else coop_gather<N, 2, TC, TX, KAP>(el, x, geo, kap, nb);
+  {
+    const TX* __restrict__ src = x + (size_t)e0 * Np;
+    for (int t = threadIdx.x; t < ne * Np; t += kCoopThreads) {
+      const int le = t / Np, j = t - le * Np;
+      U[j * P + le] = static_cast<TC>(src[t]);
+    }
+  }
+  el.J = rcp_pos(el.rx * el.sy - el.sx * el.ry);
+  if constexpr (kMf) {
+    if (w == 0) coop_factors(el, lambda, SC, lane);
+  }
+  __syncthreads();
+  TC acc[CL::kMaxRows];
+  if constexpr (!kMf) {
+    auto vol = [&](auto lam) {
+      constexpr bool LAM = decltype(lam)::value;
+      if (w == 0) coop_rows_vol<N, 0, LAM>(el, ops, U, lane, lambda, acc);
+      else if (w == 1) coop_rows_vol<N, 1, LAM>(el, ops, U, lane, lambda, acc);
+      else coop_rows_vol<N, 2, LAM>(el, ops, U, lane, lambda, acc);
+    };
+    if (lambda != TC(0)) vol(std::true_type{});
+    else vol(std::false_type{});
+  }
+  TC dnj[Nfp], tau, Fs, iFs;
+  if (w == 0) coop_face<N, 0, TC, TX>(el, nb, ops, ctau, U, JM, lane, dnj, tau, Fs, iFs);
+  else if (w == 1) coop_face<N, 1, TC, TX>(el, nb, ops, ctau, U, JM, lane, dnj, tau, Fs, iFs);
+  else coop_face<N, 2, TC, TX>(el, nb, ops, ctau, U, JM, lane, dnj, tau, Fs, iFs);
+  __syncthreads();
+  const bool want_dot = partials != nullptr;
+  double dot = 0.0;
+  if constexpr (kMf) {
+    typename Mfma<TC>::v4 macc[4];
+    auto rows = [&](auto lam) {
+      constexpr bool LAM = decltype(lam)::value;
+      if (w == 0) {
+        coop_lift<N, 0>(el, ops, JM, TS, lane, dnj, tau, Fs, iFs);
+        phase_fence();   // keeps the lift's registers apart from the row phase's
+        coop_rows_mfma<N, 0, LAM>(ops, U, JM, SC, lane, macc);
+      } else if (w == 1) {
+        coop_lift<N, 1>(el, ops, JM, TS, lane, dnj, tau, Fs, iFs);
+        phase_fence();   // keeps the lift's registers apart from the row phase's
+        coop_rows_mfma<N, 1, LAM>(ops, U, JM, SC, lane, macc);
+      } else {
+        coop_lift<N, 2>(el, ops, JM, TS, lane, dnj, tau, Fs, iFs);
+        phase_fence();   // keeps the lift's registers apart from the row phase's
+        coop_rows_mfma<N, 2, LAM>(ops, U, JM, SC, lane, macc);
+      }
+    };
+    if (lambda != TC(0)) rows(std::true_type{});
+    else rows(std::false_type{});
+    __syncthreads();
+    if (w == 0) coop_rows_mfma_face<N, 0>(ops, U, TS, lane, ne, macc, want_dot, dot);
+    else if (w == 1) coop_rows_mfma_face<N, 1>(ops, U, TS, lane, ne, macc, want_dot, dot);
+    else coop_rows_mfma_face<N, 2>(ops, U, TS, lane, ne, macc, want_dot, dot);
+    __syncthreads();
+    if (w == 0) coop_rows_mfma_store<N, 0>(U, lane, macc);
+    else if (w == 1) coop_rows_mfma_store<N, 1>(U, lane, macc);
+    else coop_rows_mfma_store<N, 2>(U, lane, macc);
+  } else {
+    if (w == 0) {
+      coop_lift<N, 0>(el, ops, JM, TS, lane, dnj, tau, Fs, iFs);
+      coop_rows_jump<N, 0>(el, ops, JM, lane, acc);
+    } else if (w == 1) {
+      coop_lift<N, 1>(el, ops, JM, TS, lane, dnj, tau, Fs, iFs);
+      coop_rows_jump<N, 1>(el, ops, JM, lane, acc);
+    } else {
+      coop_lift<N, 2>(el, ops, JM, TS, lane, dnj, tau, Fs, iFs);
+      coop_rows_jump<N, 2>(el, ops, JM, lane, acc);
+    }
+    __syncthreads();
+    if (w == 0) coop_rows_out<N, 0>(ops, U, TS, lane, acc, want_dot, dot);
+    else if (w == 1) coop_rows_out<N, 1>(ops, U, TS, lane, acc, want_dot, dot);
+    else coop_rows_out<N, 2>(ops, U, TS, lane, acc, want_dot, dot);
+    dot = live ? dot : 0.0;
+  }
+  if (want_dot) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) dot += __shfl_down(dot, off, 64);
+    if (lane == 0) red[w] = dot;
+  }
+  __syncthreads();
+  {
+    TY* __restrict__ dst = y + (size_t)e0 * Np;
+    for (int t = threadIdx.x; t < ne * Np; t += kCoopThreads) {
+      const int le = t / Np, j = t - le * Np;
+      dst[t] = static_cast<TY>(U[j * P + le]);
+    }
+  }
+  if (want_dot && threadIdx.x == 0) partials[blockIdx.x] = (red[0] + red[1]) + red[2];
 }
 
 template <typename TC, bool KAP>
@@ -902,11 +1042,25 @@ void launch_ax_variant(const ElemArgs& a, int grid, int per, hipStream_t s) {
 
 template <typename TC, typename TX, typename TY>
 hipError_t run_ax(const ElemArgs& a, hipStream_t s) {
+  if (a.K == 0) return hipSuccess;
+  // variant 4: the cooperative kernel; bits of variants 0..3: 1 = LDS-staged
+  // inputs/outputs, 2 = raised occupancy
+  const int v = ax_variant(N, sizeof(TC) == 4);
+  if (v == kAxCoop) {
+    int per;
+    const int grid = xcd_grid((a.K + kCoopTile - 1) / kCoopTile, per);
+    auto go = [&](auto kern) {
+      hipLaunchKernelGGL(kern, dim3(grid), dim3(kCoopThreads), 0, s, static_cast<const TX*>(a.x),
+                         static_cast<TY*>(a.y), static_cast<const TC*>(a.geo), a.conn,
+                         static_cast<const TC*>(a.kap), static_cast<const TC*>(a.ops), TC(a.lambda),
+                         TC(a.ctau), a.K, per, a.partials, a.skip);
+    };
+    if (a.kap) go(k_axc<TC, TX, TY, true>);
+    else go(k_axc<TC, TX, TY, false>);
+    return hipGetLastError();
+  }
   int per;
   const int grid = xcd_grid(elem_tiles(a.K), per);
-  if (a.K == 0) return hipSuccess;
-  // variant bits: 1 = LDS-staged inputs/outputs, 2 = raised occupancy
-  const int v = ax_variant(N, sizeof(TC) == 4);
   constexpr int W = ax_boost_waves<TC>();
   if ((v & 3) == 1) {
     if (a.kap) launch_ax_variant<TC, TX, TY, true, true, 0>(a, grid, per, s);

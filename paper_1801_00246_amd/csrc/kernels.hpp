@@ -39,7 +39,15 @@ inline int elem_grid(int K) {
 // set_ax_variant or IPDG_AX_VARIANT; defaults in dispatch.cpp.
 int ax_variant(int N, bool fp32);
 void set_ax_variant(int N, bool fp32, int v);
-int ax_variant_count(int N);   // variants 0..count-1 exist at degree N
+// Variant kAxCoop, at every degree: the cooperative kernel (three waves per
+// tile of 64 elements).  Degrees 1..5 also have variants 0..3, degrees 6..8
+// variants 0 and 1.
+constexpr int kAxCoop = 4;
+constexpr int kCoopTileElems = 64;   // elements per block of the cooperative kernel
+bool ax_variant_exists(int N, int v);
+// Blocks of the operator launch at degree N in this precision with the
+// current variant: the number of partial sums it writes.
+int ax_partials(int N, bool fp32, int K);
 
 // y = A x (SIPDG operator).  Per degree, defined in the per-degree units.
 template <int N> hipError_t launch_ax(Kind kind, const ElemArgs& a, hipStream_t s);

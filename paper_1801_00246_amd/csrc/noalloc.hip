@@ -121,7 +121,7 @@ ipdg_status pcg_solve_noalloc(ipdg_mesh_s* m, double lambda, double tau, const d
   a.K = K;
   const bool flexible = o.flexible > 0;
   const bool jac = o.pc != IPDG_PC_BLOCK_MASS;
-  const int ne = elem_grid(K), nf = flat_grid(n);
+  const int nf = flat_grid(n);
 
   // preconditioner set-up: the inverse diagonal (or ones)
   if (o.pc == IPDG_PC_JACOBI) {
@@ -166,7 +166,7 @@ ipdg_status pcg_solve_noalloc(ipdg_mesh_s* m, double lambda, double tau, const d
     t.partials = B.partials;
     t.skip = &B.sc->done;
     IPDG_HIP(ax(N, Kind::F64, t, s));
-    IPDG_HIP(finalize(B.partials, ne, 1, B.sc, kFinAlpha, s));
+    IPDG_HIP(finalize(B.partials, ax_partials(N, false, K), 1, B.sc, kFinAlpha, s));
     IPDG_HIP(cg_update(false, jac, x, B.r, B.p, B.Ap, B.dinv, B.z, B.sc, n, B.partials, s));
     if (!jac) {
       ElemArgs mi = a;

@@ -556,7 +556,7 @@ class Solver {
       a.partials = w.cpartials.as<double>();
       a.skip = nullptr;
       IPDG_HIP(ax(v.N, Kind::F64, a, s_));
-      IPDG_HIP(finalize(w.cpartials.as<double>(), elem_grid(K_), 1, sc, kFinAlpha, s_));
+      IPDG_HIP(finalize(w.cpartials.as<double>(), ax_partials(v.N, false, K_), 1, sc, kFinAlpha, s_));
       IPDG_HIP(cg_update_state(false, x.get(), r.get(), p.get(), Ap.get(), v.dinv64.get(), z.get(), sc,
                                v.n, w.cpartials.as<double>(), s_));
       IPDG_HIP(finalize(w.cpartials.as<double>(), flat_grid(v.n), 3, sc, kFinBeta, s_));
@@ -775,7 +775,8 @@ class Solver {
       ca.pin = set[o];
       ca.pout = set[nw];
       ca.n_rr = ca.n_g = it == 0 ? flat_grid(v.n) : ne;
-      ca.n_d = ne;
+      // the first (u, w) partials come from the operator launch above
+      ca.n_d = it == 0 ? ax_partials(v.N, v.fp32, K_) : ne;
       IPDG_HIP(coarse_step(v.N, v.kind, ca, s_));
     }
   }
@@ -821,7 +822,7 @@ class Solver {
     a.partials = w.partials.as<double>();
     a.skip = outer_done();
     IPDG_HIP(ax(N_, Kind::F64, a, s_));
-    IPDG_HIP(finalize(w.partials.as<double>(), elem_grid(K_), 1, sc, kFinAlpha, s_));
+    IPDG_HIP(finalize(w.partials.as<double>(), ax_partials(N_, false, K_), 1, sc, kFinAlpha, s_));
     const bool jac = o_.pc == IPDG_PC_JACOBI || o_.pc == IPDG_PC_NONE;
     IPDG_HIP(cg_update(mixed_, jac, x, w.r.as<double>(), w.p.as<double>(), w.Ap.as<double>(), w.dinv64.as<double>(),
                        w.z.get(), sc, n_, w.partials.as<double>(), s_));

@@ -96,4 +96,67 @@ inline int ops_total(int N) {
   return 7 * Np * Np + 3 * Np * 3 * Nfp + Nfp * Nfp + 2 * Nfp * Np + Np * (4 * Np + 9 * Nfp);
 }
 
+// Operator streams of the cooperative kernel (three waves per tile of 64
+// elements: wave f takes face f, then a third of the output rows), appended
+// after the OpsLayout tables.  All entries a wave reads in one phase are
+// contiguous in the order it reads them.
+//   FD  [f][j][k][d]      D_r (d = 0), D_s (d = 1) at node k of face f,
+//                         column j (own normal derivative, streamed over j)
+//   LF  [f2][p][f][k]     LIFT rows at the nodes of face f2
+//   per wave w, rows [row_begin(w), row_begin(w+1)), nr rows:
+//     CV [j][i][t]        K_rr, K_rs, K_ss (t = 0, 1, 2), column by column
+//     CM [j][i]           M
+//     CQ [f][k][i][t]     M D_r LIFT, M D_s LIFT (t = 0, 1)
+template <int N>
+struct CoopLayout {
+  static constexpr int Np = Tri<N>::Np, Nfp = Tri<N>::Nfp;
+  static constexpr int kWaves = 3;
+  __host__ __device__ static constexpr int row_begin(int w) { return (w * Np + kWaves - 1) / kWaves; }
+  __host__ __device__ static constexpr int nrows(int w) { return row_begin(w + 1) - row_begin(w); }
+  static constexpr int kMaxRows = (Np + kWaves - 1) / kWaves;
+  static constexpr int FD = OpsLayout<N>::total;
+  static constexpr int LF = FD + 3 * Np * Nfp * 2;
+  static constexpr int W0 = LF + 9 * Nfp * Nfp;
+  __host__ __device__ static constexpr int wave_len(int w) { return nrows(w) * (4 * Np + 6 * Nfp); }
+  __host__ __device__ static constexpr int CV(int w) {
+    int o = W0;
+    for (int v = 0; v < w; ++v) o += wave_len(v);
+    return o;
+  }
+  __host__ __device__ static constexpr int CM(int w) { return CV(w) + 3 * Np * nrows(w); }
+  __host__ __device__ static constexpr int CQ(int w) { return CM(w) + Np * nrows(w); }
+  static constexpr int total = W0 + Np * (4 * Np + 6 * Nfp);
+};
+
+// Matrix-core form of the cooperative kernel's row phase: the output rows of
+// a tile are 16 x 16 blocks (16 rows x 16 elements) computed by
+// 16 x 16 x 4 matrix multiply-accumulates.  The operators are stored as the
+// A operands of those instructions, one 64-value block per (operator, row
+// block rb, column block kb) in lane order: lane l holds entry
+// (16 rb + l % 16, 4 kb + l / 16), zero outside the matrix.  Operators:
+// volume t = 0..3: K_rr, K_rs, K_ss, M (Np columns); face q = 0..2:
+// M D_r LIFT, M D_s LIFT, -M LIFT (3 Nfp columns).  Appended after
+// CoopLayout.
+template <int N>
+struct MfmaLayout {
+  static constexpr int Np = Tri<N>::Np, Nfp = Tri<N>::Nfp;
+  static constexpr int RB = (Np + 15) / 16;        // row blocks of 16
+  static constexpr int KBV = (Np + 3) / 4;         // column blocks of the volume operators
+  static constexpr int KBF = (3 * Nfp + 3) / 4;    // column blocks of the face operators
+  static constexpr int BASE = CoopLayout<N>::total;
+  __host__ __device__ static constexpr int vol(int t, int rb, int kb) { return BASE + ((t * RB + rb) * KBV + kb) * 64; }
+  __host__ __device__ static constexpr int face(int q, int rb, int kb) {
+    return BASE + 4 * RB * KBV * 64 + ((q * RB + rb) * KBF + kb) * 64;
+  }
+  static constexpr int total = BASE + 64 * RB * (4 * KBV + 3 * KBF);
+};
+
+// Length of the whole per-degree table (OpsLayout, CoopLayout, MfmaLayout).
+inline int ops_table_len(int N) {
+  const int Np = (N + 1) * (N + 2) / 2, Nfp = N + 1;
+  const int RB = (Np + 15) / 16, KBV = (Np + 3) / 4, KBF = (3 * Nfp + 3) / 4;
+  return ops_total(N) + 3 * Np * Nfp * 2 + 9 * Nfp * Nfp + Np * (4 * Np + 6 * Nfp) +
+         64 * RB * (4 * KBV + 3 * KBF);
+}
+
 }  // namespace ipdg

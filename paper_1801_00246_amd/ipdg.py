@@ -77,6 +77,8 @@ _SIGS = {
     "ipdg_reference_element": (C.c_int, [C.c_int, _P, _P, _P, _P, _P, _P]),
     "ipdg_ax_variant_get": (C.c_int, [C.c_int, C.c_int, C.POINTER(C.c_int)]),
     "ipdg_ax_variant_set": (C.c_int, [C.c_int, C.c_int, C.c_int]),
+    "ipdg_probe_copy": (C.c_int, [C.c_size_t, C.c_int, C.c_int, C.POINTER(C.c_double), _P]),
+    "ipdg_probe_fma": (C.c_int, [C.c_int, C.c_int, C.POINTER(C.c_double), _P]),
     "ipdg_autotune_apply": (C.c_int, [_P, C.c_double, C.c_double, C.c_int, C.c_int, C.POINTER(C.c_int),
                                       _P, _P]),
 }
@@ -144,6 +146,20 @@ def ax_variant(N, dtype="f64"):
 def set_ax_variant(N, dtype, variant):
     """Select the operator-kernel variant for degree N and dtype, process-wide."""
     check(lib().ipdg_ax_variant_set(int(N), F64 if dtype in ("f64", F64) else F32, int(variant)))
+
+
+def probe_copy(nbytes, sets=8, reps=50, stream=None):
+    """GB/s (read + write) of the library's vectorised copy kernel."""
+    v = C.c_double(0.0)
+    check(lib().ipdg_probe_copy(int(nbytes), int(sets), int(reps), C.byref(v), _stream(stream)))
+    return v.value
+
+
+def probe_fma(dtype="f64", reps=5, stream=None):
+    """TFLOP/s of independent multiply-add chains in dtype ("f64"/"f32")."""
+    v = C.c_double(0.0)
+    check(lib().ipdg_probe_fma(F64 if dtype in ("f64", F64) else F32, int(reps), C.byref(v), _stream(stream)))
+    return v.value
 
 
 def _np_ptr(a, dtype):
@@ -268,11 +284,11 @@ class Mesh:
 
     def autotune(self, lam=0.0, tau=0.0, dtype="f64", reps=20, stream=None):
         """Time the operator variants of this degree on this mesh and select the
-        fastest for (N, dtype).  Returns (chosen, [ms per apply of variants 0..3],
+        fastest for (N, dtype).  Returns (chosen, [ms per apply of variants 0..4],
         -1 where the degree has no such variant)."""
         dt = F64 if dtype in ("f64", F64) else F32
         chosen = C.c_int(-1)
-        times = (C.c_double * 4)()
+        times = (C.c_double * 5)()
         check(lib().ipdg_autotune_apply(self._h, float(lam), float(tau), dt, int(reps), C.byref(chosen),
                                         C.cast(times, _P), _stream(stream)))
         return chosen.value, list(times)

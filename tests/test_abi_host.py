@@ -89,12 +89,14 @@ def test_operator_variant_table():
     saved = {(N, dt): P.ax_variant(N, dt) for N in range(1, 9) for dt in ("f64", "f32")}
     try:
         for N in range(1, 9):
-            for v in range(4 if N <= 5 else 2):
+            # variants 0..3 at degrees <= 5, 0 and 1 above, and the cooperative
+            # kernel (4) at every degree
+            for v in (list(range(4)) if N <= 5 else [0, 1]) + [4]:
                 P.set_ax_variant(N, "f32", v)
                 assert P.ax_variant(N, "f32") == v
         L = P.lib()
-        for args in ((0, P.F64, 0), (9, P.F64, 0), (3, 2, 0), (3, P.F64, 4), (3, P.F64, -1),
-                     (6, P.F64, 2), (8, P.F32, 3)):
+        for args in ((0, P.F64, 0), (9, P.F64, 0), (3, 2, 0), (3, P.F64, 5), (3, P.F64, -1),
+                     (6, P.F64, 2), (8, P.F32, 3), (0, P.F64, 4)):
             assert L.ipdg_ax_variant_set(*args) == -1
         import ctypes as C
         v = C.c_int(-7)

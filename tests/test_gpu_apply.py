@@ -62,6 +62,40 @@ def test_apply_matches_oracle(N, bc, lam, use_kappa):
     assert np.all(err <= bound)
 
 
+@pytest.mark.parametrize("N", list(range(1, 9)))
+def test_cooperative_kernel_matches_oracle(N):
+    """The cooperative operator kernel (three waves per tile; matrix-core row
+    phase from degree 5) against the oracle at every degree, with a
+    coefficient, mixed boundary types and lambda, FP64 and FP32."""
+    msh = synth.permuted(synth.square_mesh(17, jitter=0.2, seed=30 + N, bc="mixed"), seed=130 + N)
+    kap = synth.kappa_draw(msh.K, seed=40 + N)
+    ctau = float((N + 1) ** 2)
+    m = OracleMesh(msh.VX, msh.VY, msh.EToV, msh.EToB, N)
+    saved = {dt: P.ax_variant(N, dt) for dt in ("f64", "f32")}
+    try:
+        for lam, kv in ((7.0, kap), (0.0, None)):
+            A = assemble(m, lam, ctau, kappa=kv)
+            x = synth.nodal_normal(msh.K, m.Np, seed=N + 3)
+            yo = A @ x
+            g = P.Mesh.from_synth(N, msh, kappa=kv)
+            P.set_ax_variant(N, "f64", 4)
+            P.set_ax_variant(N, "f32", 4)
+            y = host(g.apply(dev(x), lam=lam, tau=ctau))
+            rel = np.linalg.norm(y - yo) / np.linalg.norm(yo)
+            y32 = host(g.apply(dev(x, torch.float32), lam=lam, tau=ctau))
+            x32 = x.astype(np.float32).astype(np.float64)
+            bound = 10 * m.Np * U32 * (abs(A) @ np.abs(x32)) + 1e-30
+            err = np.abs(y32 - A @ x32)
+            print(f"N={N} lam={lam} kappa={kv is not None}: FP64 rel {rel:.2e}, FP32 max err/bound "
+                  f"{np.max(err / bound):.3f}")
+            assert rel <= 1e-11
+            assert np.all(err <= bound)
+            g.close()
+    finally:
+        for dt, v in saved.items():
+            P.set_ax_variant(N, dt, v)
+
+
 @pytest.mark.parametrize("N", [1, 4, 8])
 def test_mass_apply_matches_oracle(N):
     msh = synth.square_mesh(17, jitter=0.2, seed=2)
@@ -75,22 +109,29 @@ def test_mass_apply_matches_oracle(N):
     assert np.linalg.norm(y32 - yo) <= 1e-6 * np.linalg.norm(yo)
 
 
+@pytest.mark.parametrize("variant", [0, 4])
 @pytest.mark.parametrize("N", [1, 3, 5, 8])
 @pytest.mark.parametrize("lam", [0.0, 100.0])
-def test_full_size_sampled_rows(N, lam):
+def test_full_size_sampled_rows(N, lam, variant):
     """524,288-element jittered mesh (the throughput workload), the launch the
-    benchmark times; the oracle recomputes 300 sampled elements one by one."""
+    benchmark times (either kernel form the autotuner may select); the oracle
+    recomputes 300 sampled elements one by one."""
     msh = synth.ax_sweep_mesh(512, seed=0)
     g = P.Mesh.from_synth(N, msh)
     Np = g.Np
     x = synth.nodal_normal(msh.K, Np, seed=1)
-    y = host(g.apply(dev(x), lam=lam)).reshape(msh.K, Np)
+    saved = P.ax_variant(N, "f64")
+    P.set_ax_variant(N, "f64", variant)
+    try:
+        y = host(g.apply(dev(x), lam=lam)).reshape(msh.K, Np)
+    finally:
+        P.set_ax_variant(N, "f64", saved)
     rng = np.random.default_rng(N)
     sel = np.unique(np.r_[rng.integers(0, msh.K, 296), 0, 1, msh.K - 1, 2 * 512 * 255])
     m = OracleMesh(msh.VX, msh.VY, msh.EToV, msh.EToB, N)
     yo = apply_rows(m, lam, float((N + 1) ** 2), x, sel)
     rel = np.linalg.norm(y[sel] - yo) / np.linalg.norm(yo)
-    print(f"N={N} lam={lam} sampled FP64 rel {rel:.2e}")
+    print(f"N={N} lam={lam} variant={variant} sampled FP64 rel {rel:.2e}")
     assert rel <= 1e-11
 
 
@@ -166,18 +207,22 @@ def test_autotune_selects_a_variant_with_identical_results(N, use_kappa):
     try:
         for dt, tdt in (("f64", torch.float64), ("f32", torch.float32)):
             chosen, times = g.autotune(lam=2.0, tau=0.0, dtype=dt, reps=5)
-            nvar = 4 if N <= 5 else 2
+            have = (list(range(4)) if N <= 5 else [0, 1]) + [4]
             print(f"N={N} {dt}: chosen {chosen}, ms per apply {times}")
-            assert 0 <= chosen < nvar
+            assert chosen in have
             assert P.ax_variant(N, dt) == chosen
-            assert all(t > 0 for t in times[:nvar]) and all(t == -1 for t in times[nvar:])
-            assert times[chosen] == min(times[:nvar])
-            ys = []
-            for v in range(nvar):
+            assert all((times[v] > 0) == (v in have) for v in range(5))
+            assert times[chosen] == min(times[v] for v in have)
+            ys = {}
+            for v in have:
                 P.set_ax_variant(N, dt, v)
-                ys.append(host(g.apply(dev(x, tdt), lam=2.0)))
-            for y in ys[1:]:
-                assert np.array_equal(y, ys[0])
+                ys[v] = host(g.apply(dev(x, tdt), lam=2.0))
+            # variants 0..3 share the element computation: identical bits
+            for v in have[1:-1]:
+                assert np.array_equal(ys[v], ys[0])
+            # the cooperative kernel (4) orders its sums differently
+            rel = np.linalg.norm(ys[4] - ys[0]) / np.linalg.norm(ys[0])
+            assert rel <= (1e-13 if dt == "f64" else 1e-5), rel
     finally:
         for dt, v in saved.items():
             P.set_ax_variant(N, dt, v)
