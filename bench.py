@@ -126,25 +126,13 @@ def roofline(N, dtype_bytes, ms):
             "alg_bytes_per_launch": nbytes, "alg_flops_per_launch": flops}
 
 
-def copy_probe(torch, nbytes, reps=20):
+def copy_probe(P, nbytes, reps=40):
     """Device-to-device copy bandwidth (the paper's empirical roof): GB/s of
-    read + write traffic, rotating over > 1.2 GB."""
-    n = max(1, int(nbytes // 8))
-    R = max(2, math.ceil(1.2e9 / (2 * 8 * n)))
-    src = [torch.empty(n, dtype=torch.float64, device="cuda").fill_(1.0) for _ in range(R)]
-    dst = [torch.empty(n, dtype=torch.float64, device="cuda") for _ in range(R)]
-    for i in range(R):
-        dst[i].copy_(src[i])
-    torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for i in range(reps):
-        dst[i % R].copy_(src[i % R])
-    e1.record()
-    torch.cuda.synchronize()
-    t = e0.elapsed_time(e1) * 1e-3 / reps
-    return 2 * 8 * n / t / 1e9
+    read + write traffic of the library's vectorised HIP copy kernel copying
+    nbytes, rotating over source/destination pairs totalling > 1.2 GB (so
+    that the 256 MB last-level cache cannot hold them)."""
+    sets = max(2, math.ceil(1.2e9 / (2 * nbytes)))
+    return P.probe_copy(int(nbytes), sets, reps)
 
 
 _MF = {}
@@ -268,7 +256,11 @@ def run_pcg_compare(P, torch, coarse_caps=(150, 300)):
     out = {"workload": "256x256 squares (131,072 triangles), N=7, f from sin(pi x) sin(pi y), "
                        "Dirichlet, lambda=0, tol 1e-8, pMG 7->3->1, Chebyshev(2), coarse Jacobi-PCG"}
     for cmax in coarse_caps:
-        for name, prec in (("fp64", P.PREC_FP64), ("mixed", P.PREC_MIXED)):
+        precs = [("fp64", P.PREC_FP64), ("mixed", P.PREC_MIXED)]
+        if cmax == coarse_caps[0]:
+            # FP32 outer operator as well (reliable updates after every 1e3 fall)
+            precs.append(("fp32op", P.PREC_FP32_OPERATOR))
+        for name, prec in precs:
             o = P.default_opts(pc=P.PC_PMG, prec=prec, degrees=[7, 3, 1], coarse_max_iters=cmax)
             g.pcg(b, tol=1e-8, opts=o)                 # setup + warm-up
             torch.cuda.synchronize()
@@ -455,7 +447,9 @@ def main():
         line["autotune"] = tuned
     line["roofline"] = roofline(N, w, ms)
     line["roofline"]["traffic"] = measured_traffic(N, args.dtype, args.lam, variant)
-    line["copy_roof_gbs"] = round(copy_probe(torch, msh.K * alg_bytes(N, w) / 2), 1)
+    # measured roofs (context for the fractions, which use the published peaks)
+    line["copy_roof_gbs"] = round(copy_probe(P, msh.K * alg_bytes(N, w) / 2), 1)
+    line["fma_peak_tflops"] = {"f64": round(P.probe_fma("f64"), 2), "f32": round(P.probe_fma("f32"), 2)}
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(N, args.lam)
     if not args.no_sweep:

@@ -56,17 +56,22 @@ typedef enum {
 typedef enum { IPDG_F64 = 0, IPDG_F32 = 1 } ipdg_dtype;
 typedef enum { IPDG_BC_INTERIOR = 0, IPDG_BC_DIRICHLET = 1, IPDG_BC_NEUMANN = 2 } ipdg_bc;
 typedef enum { IPDG_PC_NONE = 0, IPDG_PC_JACOBI = 1, IPDG_PC_BLOCK_MASS = 2, IPDG_PC_PMG = 3 } ipdg_pc;
-typedef enum { IPDG_PREC_FP64 = 0, IPDG_PREC_MIXED = 1 } ipdg_prec;
+typedef enum { IPDG_PREC_FP64 = 0, IPDG_PREC_MIXED = 1, IPDG_PREC_FP32_OPERATOR = 2 } ipdg_prec;
 
 #define IPDG_MAX_LEVELS 8
 
 /* Options of the PCG solvers.  ipdg_default_opts() fills every field. */
 typedef struct {
   ipdg_pc pc;              /* preconditioner */
-  ipdg_prec prec;          /* FP64 throughout, or an FP32 preconditioner (its
-                              operator applications, smoothing, transfers and
-                              coarse solve) inside FP64 CG: the outer operator,
-                              recurrences, dots and residuals stay FP64 */
+  ipdg_prec prec;          /* FP64 throughout; IPDG_PREC_MIXED: an FP32
+                              preconditioner (its operator applications,
+                              smoothing, transfers and coarse solve) inside
+                              FP64 CG: the outer operator, recurrences, dots and
+                              residuals stay FP64; IPDG_PREC_FP32_OPERATOR: the
+                              outer operator A p in FP32 as well (x, r, p and
+                              the dots FP64), with reliable updates: r = b - A x
+                              recomputed in FP64 and the direction restarted
+                              whenever |r| fell by reliable_drop (1e-3 when 0) */
   int max_iters;           /* outer iteration limit */
   int check_every;         /* host polls convergence every this many iterations */
   int flexible;            /* 1: flexible CG beta = -(z+, Ap)/(p, Ap);

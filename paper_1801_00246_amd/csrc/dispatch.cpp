@@ -11,7 +11,7 @@ namespace {
 // Operator kernel variant per precision (FP64, FP32) and degree; bits:
 // 1 = LDS-staged inputs/outputs, 2 = raised occupancy (degrees <= 5).
 // Defaults from measured sweeps of the 524,288-element operator workload.
-std::atomic<int> g_variant[2][9] = {{0, 0, 0, 0, 4, 4, 4, 4, 4}, {0, 2, 2, 4, 4, 4, 4, 4, 4}};
+std::atomic<int> g_variant[2][9] = {{0, 0, 0, 4, 4, 4, 4, 4, 4}, {0, 2, 2, 4, 4, 4, 4, 4, 4}};
 std::once_flag env_once;
 
 // The environment override, applied once per process before any variant is

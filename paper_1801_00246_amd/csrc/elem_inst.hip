@@ -101,14 +101,18 @@ void k_ax(const TX* __restrict__ x, TY* __restrict__ y,
   }
 }
 
-#ifndef IPDG_COOP_WAVES
-#define IPDG_COOP_WAVES 1
-#endif
+// Waves per SIMD the cooperative kernel's register allocation must leave
+// room for (1: no constraint).  FP64 at degrees <= 3 fits five without
+// spilling.
+template <typename TC>
+constexpr int coop_waves() {
+  return (sizeof(TC) == 8 && N <= 3) ? 5 : 1;
+}
 
 // Cooperative operator (sipdg_coop.hpp): a block of three waves per tile of
 // 64 elements; the partial sum of x . y (optional) is one per block.
 template <typename TC, typename TX, typename TY, bool KAP>
-__global__ __launch_bounds__(kCoopThreads) __attribute__((amdgpu_waves_per_eu(IPDG_COOP_WAVES))) void k_axc(const TX* __restrict__ x, TY* __restrict__ y,
+__global__ __launch_bounds__(kCoopThreads) __attribute__((amdgpu_waves_per_eu(coop_waves<TC>()))) void k_axc(const TX* __restrict__ x, TY* __restrict__ y,
                                                       const TC* __restrict__ geo,
                                                       const Conn* __restrict__ conn,
                                                       const TC* __restrict__ kap,
@@ -161,8 +165,15 @@ __global__ __launch_bounds__(kCoopThreads) __attribute__((amdgpu_waves_per_eu(IP
     if (w == 0) coop_factors(el, lambda, SC, lane);
   }
   __syncthreads();
+  TC dnj[Nfp], tau, Fs, iFs;
+  if (w == 0) coop_face<N, 0, TC, TX>(el, nb, ops, ctau, U, JM, lane, dnj, tau, Fs, iFs);
+  else if (w == 1) coop_face<N, 1, TC, TX>(el, nb, ops, ctau, U, JM, lane, dnj, tau, Fs, iFs);
+  else coop_face<N, 2, TC, TX>(el, nb, ops, ctau, U, JM, lane, dnj, tau, Fs, iFs);
+  // the volume rows after the face phase: the neighbour's values are no
+  // longer live
   TC acc[CL::kMaxRows];
   if constexpr (!kMf) {
+    phase_fence();
     auto vol = [&](auto lam) {
       constexpr bool LAM = decltype(lam)::value;
       if (w == 0) coop_rows_vol<N, 0, LAM>(el, ops, U, lane, lambda, acc);
@@ -172,10 +183,6 @@ __global__ __launch_bounds__(kCoopThreads) __attribute__((amdgpu_waves_per_eu(IP
     if (lambda != TC(0)) vol(std::true_type{});
     else vol(std::false_type{});
   }
-  TC dnj[Nfp], tau, Fs, iFs;
-  if (w == 0) coop_face<N, 0, TC, TX>(el, nb, ops, ctau, U, JM, lane, dnj, tau, Fs, iFs);
-  else if (w == 1) coop_face<N, 1, TC, TX>(el, nb, ops, ctau, U, JM, lane, dnj, tau, Fs, iFs);
-  else coop_face<N, 2, TC, TX>(el, nb, ops, ctau, U, JM, lane, dnj, tau, Fs, iFs);
   __syncthreads();
   const bool want_dot = partials != nullptr;
   double dot = 0.0;

@@ -14,7 +14,9 @@
 // preconditioner runs in FP32 while the outer operator, x, r, p, the dots and
 // the true residual stay in FP64; optionally (reliable_drop > 0) the residual
 // is also replaced whenever ||r|| fell by that factor since the last
-// replacement.
+// replacement.  With the FP32 outer operator (IPDG_PREC_FP32_OPERATOR) A p is
+// applied in FP32 too, and the residual is always replaced (with the
+// direction restarted) after every fall by reliable_drop (default 1e-3).
 //
 // p-multigrid (Sec. 3, the degree-coarsening part of pMG-AMG): levels of
 // degree N_0 > N_1 > ... rediscretise the operator with penalty constant
@@ -72,6 +74,7 @@ struct Work : SolverWork {
 
   size_t n = 0;
   DevBuf r, p, Ap, z, t64, xw, partials, cpartials, scal, cscal, dinv64, dinv32;
+  DevBuf p32, Ap32;                // FP32 outer operator: p and A p in FP32
   DevBuf cbar;                     // persistent coarse solve: 2 barrier counters + 3 status ints
   int coarse_grid = 0;             // resident grid of the persistent coarse solve (0: not used)
   std::vector<Level> lv;
@@ -179,7 +182,11 @@ class Solver {
     n_ = (size_t)K_ * m->Np;
     lambda_ = lambda;
     ctau_ = ctau_of(N_, tau);
-    mixed_ = o.prec == IPDG_PREC_MIXED;
+    mixed_ = o.prec == IPDG_PREC_MIXED || o.prec == IPDG_PREC_FP32_OPERATOR;
+    op32_ = o.prec == IPDG_PREC_FP32_OPERATOR;
+    // the FP32 outer operator's recurrence drifts from the true residual:
+    // reliable updates are always on (default: after every 1e3 fall)
+    drop_ = o.reliable_drop > 0.0 ? o.reliable_drop : (op32_ ? 1e-3 : 0.0);
     flexible_ = o.flexible < 0 ? (o.pc == IPDG_PC_PMG || mixed_) : o.flexible != 0;
     validate();
     if (elem_grid(K_) > kMaxPartials) throw Error(IPDG_EUNSUPPORTED, "mesh too large for one launch");
@@ -261,7 +268,7 @@ class Solver {
       mark_done();
       return R.finished = true;
     }
-    const double drop2 = o_.reliable_drop * o_.reliable_drop;
+    const double drop2 = drop_ * drop_;
     const bool stopped = h.done != 0;
     const bool replace = stopped || (drop2 > 0.0 && h.rr <= drop2 * R.rr_ref);
     if (!replace) return false;
@@ -279,8 +286,9 @@ class Solver {
       // Residual replacement (van der Vorst and Ye): the recurrence continues
       // from the true residual with the current search direction.  Only when
       // the recurrence had already stopped (its last direction update was not
-      // applied) is the direction rebuilt from z = B r.
-      if (stopped) restart(x);
+      // applied), or the outer operator is FP32 (its directions have lost
+      // A-conjugacy at the FP32 level), is the direction rebuilt from z = B r.
+      if (stopped || op32_) restart(x);
       return false;
     }
     mark_done();
@@ -363,7 +371,8 @@ class Solver {
  private:
   void validate() {
     if (o_.pc < IPDG_PC_NONE || o_.pc > IPDG_PC_PMG) throw Error(IPDG_EINVAL, "bad preconditioner");
-    if (o_.prec != IPDG_PREC_FP64 && o_.prec != IPDG_PREC_MIXED) throw Error(IPDG_EINVAL, "bad precision");
+    if (o_.prec != IPDG_PREC_FP64 && o_.prec != IPDG_PREC_MIXED && o_.prec != IPDG_PREC_FP32_OPERATOR)
+      throw Error(IPDG_EINVAL, "bad precision");
     if (o_.max_iters < 0) throw Error(IPDG_EINVAL, "max_iters < 0");
     if (o_.pc == IPDG_PC_PMG) {
       if (o_.n_levels < 1 || o_.n_levels > IPDG_MAX_LEVELS) throw Error(IPDG_EINVAL, "n_levels out of range");
@@ -413,6 +422,10 @@ class Solver {
     w.t64.ensure(n_ * 8);
     w.Ap.ensure(n_ * 8);
     w.z.ensure(n_ * (mixed_ ? 4 : 8));
+    if (op32_) {
+      w.p32.ensure(n_ * 4);
+      w.Ap32.ensure(n_ * 4);
+    }
     w.partials.ensure(3 * kMaxPartials * sizeof(double));
     w.cpartials.ensure(6 * kMaxPartials * sizeof(double));
     w.scal.ensure(sizeof(CGScal));
@@ -812,17 +825,32 @@ class Solver {
   void iteration(double* x) {
     Work& w = *w_;
     CGScal* sc = w.scal.as<CGScal>();
-    // the outer operator is FP64 also in mixed precision: an FP32 product
-    // A p loses relative accuracy ~ u32 cond(A) on the smooth directions late
-    // CG builds, which stalls the recurrence; FP32 stays inside the
-    // preconditioner, where its error only perturbs a flexible preconditioner
-    ElemArgs a = elem_args(m_, N_, Kind::F64, lambda_, ctau_);
-    a.x = w.p.get();
-    a.y = w.Ap.get();
-    a.partials = w.partials.as<double>();
-    a.skip = outer_done();
-    IPDG_HIP(ax(N_, Kind::F64, a, s_));
-    IPDG_HIP(finalize(w.partials.as<double>(), ax_partials(N_, false, K_), 1, sc, kFinAlpha, s_));
+    // With IPDG_PREC_MIXED the outer operator is FP64: an FP32 product A p
+    // loses relative accuracy ~ u32 cond(A) on the smooth directions late CG
+    // builds, which stalls the recurrence; FP32 stays inside the
+    // preconditioner, where its error only perturbs a flexible
+    // preconditioner.  IPDG_PREC_FP32_OPERATOR applies A p in FP32 too (p
+    // rounded to FP32, the product widened back, (p, A p) summed in FP64),
+    // with reliable updates of the residual.
+    if (op32_) {
+      IPDG_HIP(convert(true, w.p32.get(), w.p.get(), n_, outer_done(), s_));
+      ElemArgs a = elem_args(m_, N_, Kind::F32, lambda_, ctau_);
+      a.x = w.p32.get();
+      a.y = w.Ap32.get();
+      a.partials = w.partials.as<double>();
+      a.skip = outer_done();
+      IPDG_HIP(ax(N_, Kind::F32, a, s_));
+      IPDG_HIP(finalize(w.partials.as<double>(), ax_partials(N_, true, K_), 1, sc, kFinAlpha, s_));
+      IPDG_HIP(convert(false, w.Ap.get(), w.Ap32.get(), n_, outer_done(), s_));
+    } else {
+      ElemArgs a = elem_args(m_, N_, Kind::F64, lambda_, ctau_);
+      a.x = w.p.get();
+      a.y = w.Ap.get();
+      a.partials = w.partials.as<double>();
+      a.skip = outer_done();
+      IPDG_HIP(ax(N_, Kind::F64, a, s_));
+      IPDG_HIP(finalize(w.partials.as<double>(), ax_partials(N_, false, K_), 1, sc, kFinAlpha, s_));
+    }
     const bool jac = o_.pc == IPDG_PC_JACOBI || o_.pc == IPDG_PC_NONE;
     IPDG_HIP(cg_update(mixed_, jac, x, w.r.as<double>(), w.p.as<double>(), w.Ap.as<double>(), w.dinv64.as<double>(),
                        w.z.get(), sc, n_, w.partials.as<double>(), s_));
@@ -876,6 +904,8 @@ class Solver {
   size_t n_ = 0;
   double lambda_ = 0, ctau_ = 0;
   bool mixed_ = false, flexible_ = false;
+  bool op32_ = false;                // FP32 outer operator (IPDG_PREC_FP32_OPERATOR)
+  double drop_ = 0.0;                // reliable-update factor in use
   bool splitting_ = false;           // capturing the two halves of a split iteration
   int split_count_ = 0;
 };

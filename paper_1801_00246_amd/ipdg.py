@@ -20,7 +20,7 @@ STATUS = {0: "IPDG_OK", 1: "IPDG_NOT_CONVERGED", -1: "IPDG_EINVAL", -2: "IPDG_EM
 F64, F32 = 0, 1
 BC_INTERIOR, BC_DIRICHLET, BC_NEUMANN = 0, 1, 2
 PC_NONE, PC_JACOBI, PC_BLOCK_MASS, PC_PMG = 0, 1, 2, 3
-PREC_FP64, PREC_MIXED = 0, 1
+PREC_FP64, PREC_MIXED, PREC_FP32_OPERATOR = 0, 1, 2
 MAX_LEVELS = 8
 
 

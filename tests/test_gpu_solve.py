@@ -452,6 +452,27 @@ def test_mixed_precision_keeps_the_fp64_iteration_count(pc):
 
 
 
+@pytest.mark.parametrize("pc", ["jacobi", "pmg"])
+def test_fp32_outer_operator_reaches_the_fp64_tolerance(pc):
+    """FP32 operator and preconditioner inside FP64 CG with reliable updates
+    (the true FP64 residual recomputed, the direction restarted, after every
+    1e3 fall): the solution meets the FP64 tolerance under the oracle's
+    matrix; the iteration count against the FP64 solve is printed."""
+    msh, m, A, b, ctau = problem(24, 6, jitter=0.2, seed=11)
+    g = P.Mesh.from_synth(6, msh)
+    kw = dict(pc=P.PC_PMG, degrees=[6, 3, 1]) if pc == "pmg" else dict(pc=P.PC_JACOBI)
+    res = {}
+    for prec in (P.PREC_FP64, P.PREC_MIXED, P.PREC_FP32_OPERATOR):
+        x, info, st = g.pcg(dev(b), tol=1e-9, tau=ctau, opts=P.default_opts(prec=prec, **kw))
+        assert st == 0
+        rr = true_relres(A, host(x), b)
+        assert rr <= 1e-9
+        res[prec] = (info["iters"], info["restarts"], rr)
+    print(f"{pc}: (iterations, residual replacements, true relres) FP64 {res[P.PREC_FP64]}, "
+          f"FP32 preconditioner {res[P.PREC_MIXED]}, FP32 operator {res[P.PREC_FP32_OPERATOR]}")
+    assert res[P.PREC_FP32_OPERATOR][1] >= 1
+
+
 def test_new_coefficient_values_replace_the_solver_setup():
     """A solver set-up (diagonals, spectral estimates, graph) is kept while the
     coefficient is unchanged and rebuilt when its values change."""
