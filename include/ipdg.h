@@ -89,7 +89,9 @@ typedef struct {
                               rho_steps Lanczos (Jacobi-PCG) steps */
   int rho_steps;
   double coarse_tol;       /* coarsest Jacobi-PCG relative tolerance */
-  int coarse_max_iters;    /* and iteration cap (tol 0 => exactly this many) */
+  int coarse_max_iters;    /* and iteration cap (tol 0 => exactly this many);
+                              < 0 (default): max(20, ceil(0.414 sqrt(K))), per
+                              mesh (150 at K = 131,072) */
   double reliable_drop;    /* > 0: also recompute r = b - A x in FP64 whenever
                               |r| fell by this factor since the last recompute
                               (default 0: only when the recurrence stops) */

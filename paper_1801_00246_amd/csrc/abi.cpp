@@ -97,7 +97,7 @@ void ipdg_default_opts(ipdg_solve_opts* o) {
   o->cheb_hi = 1.1;
   o->rho_steps = 20;
   o->coarse_tol = 1e-2;
-  o->coarse_max_iters = 150;
+  o->coarse_max_iters = -1;
   o->reliable_drop = 0.0;
   o->coarse_persistent = 0;
 }

@@ -356,6 +356,15 @@ class Solver {
     }
   }
   unsigned long long setup_id() const { return w_->setup_id; }
+  // Iteration cap of the coarsest-level Jacobi-PCG: the option, or when it is
+  // negative max(20, ceil(0.414 sqrt(K))).  Jacobi-PCG needs iterations
+  // growing like 1/h on the degree-1 level; the factor puts the cap at 150
+  // for 131,072 triangles, where 150 was the measured optimum of time to
+  // solution (see the design notes for the sweep), and at 75 for 32,768.
+  int coarse_cap() const {
+    if (o_.coarse_max_iters >= 0) return o_.coarse_max_iters;
+    return std::max(20, (int)std::ceil(0.414 * std::sqrt((double)K_)));
+  }
   void launch_pre() { IPDG_HIP(hipGraphLaunch(w_->graph_pre, s_)); }
   void launch_post() { IPDG_HIP(hipGraphLaunch(w_->graph_post, s_)); }
   const Level& coarsest() const { return w_->lv.back(); }
@@ -382,7 +391,7 @@ class Solver {
           throw Error(IPDG_EINVAL, "degrees must be strictly decreasing and >= 1");
       if (o_.cheb_degree < 1) throw Error(IPDG_EINVAL, "cheb_degree < 1");
       if (!(o_.cheb_hi > o_.cheb_lo) || !(o_.cheb_lo > 0)) throw Error(IPDG_EINVAL, "bad Chebyshev interval");
-      if (o_.coarse_max_iters < 0) throw Error(IPDG_EINVAL, "coarse_max_iters < 0");
+      // coarse_max_iters < 0: the automatic cap (coarse_cap())
       if (o_.coarse_persistent != 0 && o_.coarse_persistent != 1)
         throw Error(IPDG_EINVAL, "coarse_persistent must be 0 or 1");
     }
@@ -520,7 +529,7 @@ class Solver {
     }
     CGScal c{};
     c.tol = o_.coarse_tol;
-    c.max_iters = o_.coarse_max_iters;
+    c.max_iters = coarse_cap();
     c.flexible = 0;
     IPDG_HIP(set_scal(w.cscal.as<CGScal>(), c, s_));
     w.cbar.ensure(8 * sizeof(int));
@@ -744,7 +753,7 @@ class Solver {
       ca.dinv = v.dinv();
       ca.op = elem_args(m_, v.N, v.kind, lambda_, v.ctau);
       ca.tol = o_.coarse_tol;
-      ca.max_iters = o_.coarse_max_iters;
+      ca.max_iters = coarse_cap();
       ca.partials = w.cpartials.as<double>();
       ca.bar = w.cbar.as<unsigned>();
       ca.status = w.cbar.as<int>() + 2;
@@ -776,7 +785,7 @@ class Solver {
     ca.sc = sc;
     ca.outer = outer_done();
     const int ne = elem_grid(K_);
-    for (int it = 0; it < o_.coarse_max_iters; ++it) {
+    for (int it = 0; it < coarse_cap(); ++it) {
       const int o = it & 1, nw = 1 - o;
       ca.it = it;
       ca.r_old = rb[o];
@@ -940,6 +949,7 @@ namespace {
 struct CoarseBatchSet {
   DevBuf ent, tile_solve, x, p, u, dinv, r0, r1, w0, w1, s0, s1, geo, conn, kap, partials, sc;
   CoarseBatchArgs a;
+  int max_iters = 0;               // the largest member cap: coarse launches per solve
   hipStream_t stream = nullptr;
   hipGraphExec_t graph = nullptr;
   std::vector<hipEvent_t> ev;
@@ -1044,9 +1054,11 @@ std::unique_ptr<CoarseBatchSet> make_coarse_batch(std::vector<std::unique_ptr<So
   }
   cb->partials.alloc(6 * (size_t)kMaxPartials * sizeof(double));
   std::vector<CGScal> sc(na);
-  for (auto& c : sc) {
-    c.tol = o.coarse_tol;
-    c.max_iters = o.coarse_max_iters;
+  cb->max_iters = 0;
+  for (int k = 0; k < na; ++k) {
+    sc[k].tol = o.coarse_tol;
+    sc[k].max_iters = sv[k]->coarse_cap();
+    cb->max_iters = std::max(cb->max_iters, sc[k].max_iters);
   }
   cb->sc.alloc(na * sizeof(CGScal));
   IPDG_HIP(hipMemcpyAsync(cb->sc.get(), sc.data(), na * sizeof(CGScal), hipMemcpyHostToDevice, cs));
@@ -1077,7 +1089,7 @@ std::unique_ptr<CoarseBatchSet> make_coarse_batch(std::vector<std::unique_ptr<So
   IPDG_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
   try {
     IPDG_HIP(coarse_batch(Nc, kind, a, -1, cs));
-    for (int it = 0; it < o.coarse_max_iters; ++it) IPDG_HIP(coarse_batch(Nc, kind, a, it, cs));
+    for (int it = 0; it < cb->max_iters; ++it) IPDG_HIP(coarse_batch(Nc, kind, a, it, cs));
     IPDG_HIP(coarse_batch(Nc, kind, a, -2, cs));
   } catch (...) {
     (void)hipStreamEndCapture(cs, &g);

@@ -473,6 +473,19 @@ def test_fp32_outer_operator_reaches_the_fp64_tolerance(pc):
     assert res[P.PREC_FP32_OPERATOR][1] >= 1
 
 
+@pytest.mark.parametrize("n,cap", [(24, 20), (120, 71)])
+def test_automatic_coarse_cap(n, cap):
+    """Without an explicit cap the coarsest Jacobi-PCG stops after
+    max(20, ceil(0.414 sqrt(K))) iterations (coarse tolerance 0 forces the
+    cap), and the solve still meets its tolerance."""
+    msh = synth.square_mesh(n)
+    assert max(20, int(np.ceil(0.414 * np.sqrt(msh.K)))) == cap
+    g = P.Mesh.from_synth(3, msh)
+    b = dev(synth.nodal_normal(msh.K, 10, seed=3))
+    x, info, st = g.pcg(b, lam=1.0, tol=1e-8, opts=P.default_opts(pc=P.PC_PMG, coarse_tol=0.0))
+    assert st == 0 and info["coarse_iters"] == cap
+
+
 def test_new_coefficient_values_replace_the_solver_setup():
     """A solver set-up (diagonals, spectral estimates, graph) is kept while the
     coefficient is unchanged and rebuilt when its values change."""
