@@ -290,6 +290,19 @@ def run_pcg_compare(P, torch, coarse_caps=(150, 300)):
                         "iters": info["iters"], "true_relres": info["relres"],
                         "restarts": info["restarts"], "setup_ms": round(info["setup_ms"], 2)}
             print(f"# pcg {key}: {out[key]}", file=sys.stderr, flush=True)
+    # pMG-AMG: the degree-1 level by one V-cycle of the aggregation AMG below it
+    for name, prec in (("fp64", P.PREC_FP64), ("mixed", P.PREC_MIXED)):
+        o = P.default_opts(pc=P.PC_PMG, prec=prec, degrees=[7, 3, 1], coarse_amg=1)
+        g.pcg(b, tol=1e-8, opts=o)                     # setup + warm-up
+        torch.cuda.synchronize()
+        t0 = time.time()
+        xs, info, st = g.pcg(b, tol=1e-8, opts=o)
+        torch.cuda.synchronize()
+        key = f"{name}_amg"
+        out[key] = {"time_to_solution_ms": round((time.time() - t0) * 1e3, 2), "iters": info["iters"],
+                    "true_relres": info["relres"], "amg_sizes": info["amg_sizes"],
+                    "setup_ms": round(info["setup_ms"], 2)}
+        print(f"# pcg {key}: {out[key]}", file=sys.stderr, flush=True)
     return out
 
 

@@ -59,6 +59,7 @@ typedef enum { IPDG_PC_NONE = 0, IPDG_PC_JACOBI = 1, IPDG_PC_BLOCK_MASS = 2, IPD
 typedef enum { IPDG_PREC_FP64 = 0, IPDG_PREC_MIXED = 1, IPDG_PREC_FP32_OPERATOR = 2 } ipdg_prec;
 
 #define IPDG_MAX_LEVELS 8
+#define IPDG_AMG_MAX_LEVELS 12
 
 /* Options of the PCG solvers.  ipdg_default_opts() fills every field. */
 typedef struct {
@@ -100,6 +101,19 @@ typedef struct {
                               (degrees 1..4, single solves only); 0 (default):
                               one short kernel sequence per iteration inside
                               the captured graph, converged iterations skipped */
+  /* pMG-AMG (Sec. 3): coarse_amg = 1 replaces the coarsest-level Jacobi-PCG
+     by amg_cycles V-cycles of an aggregation AMG hierarchy below the degree-1
+     level (the last p-level must be degree 1): the degree-1 level (smoothed
+     as the p-levels), one value per element (the element-block sums of the
+     degree-1 operator), then greedy aggregates of maximal independent node
+     sets with Galerkin operators, smoothed by Chebyshev of cheb_degree steps
+     over [cheb_lo, cheb_hi] times the Gershgorin bound of D^-1 A, until at
+     most amg_coarse_size (<= 2048) unknowns remain or 12 levels exist; the
+     coarsest level is solved by its inverse.  Built on the host at setup.
+     In a batch the solves then keep their own launches. */
+  int coarse_amg;          /* 0 (default) or 1 */
+  int amg_coarse_size;     /* default 512 */
+  int amg_cycles;          /* default 1 */
 } ipdg_solve_opts;
 
 /* Result record of a solve (all fields written). */
@@ -110,7 +124,11 @@ typedef struct {
   double rho_used[IPDG_MAX_LEVELS];   /* Chebyshev radii used per level */
   double setup_ms;         /* preconditioner setup wall time */
   double solve_ms;         /* iteration wall time */
-  int coarse_iters;        /* iterations of the last coarsest-level solve */
+  int coarse_iters;        /* iterations of the last coarsest-level solve (0
+                              with coarse_amg) */
+  int amg_levels;          /* coarse_amg: levels of the algebraic hierarchy,
+                              the degree-1 level included (else 0) */
+  int amg_n[IPDG_AMG_MAX_LEVELS];   /* unknowns per level, degree-1 level first */
 } ipdg_solve_info;
 
 void ipdg_default_opts(ipdg_solve_opts* opts);

@@ -181,14 +181,14 @@ class PMG:
 
     def __init__(self, mesh, degrees, lam, ctau, rho, cheb_lo=0.1, cheb_hi=1.1,
                  cheb_degree=2, coarse_tol=1e-2, coarse_max=200, coarse_exact=False,
-                 coarse_amg=False, amg_cycles=1, amg_coarse_size=1024):
+                 coarse_amg=False, amg_cycles=1, amg_coarse_size=1024, kappa=None):
         self.degrees = list(degrees)
         N0 = self.degrees[0]
         self.levels = []
         for l, Nl in enumerate(self.degrees):
             m = asm.OracleMesh(mesh.VX, mesh.VY, mesh.EToV, mesh.EToB, Nl)
             ct = ctau * ((Nl + 1) / (N0 + 1)) ** 2
-            A = asm.assemble(m, lam, ct)
+            A = asm.assemble(m, lam, ct, kappa=kappa)
             self.levels.append({"m": m, "A": A, "dinv": 1.0 / A.diagonal(), "ctau": ct})
         self.P = []
         for l in range(len(self.degrees) - 1):

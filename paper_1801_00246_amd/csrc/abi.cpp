@@ -100,6 +100,9 @@ void ipdg_default_opts(ipdg_solve_opts* o) {
   o->coarse_max_iters = -1;
   o->reliable_drop = 0.0;
   o->coarse_persistent = 0;
+  o->coarse_amg = 0;
+  o->amg_coarse_size = 512;
+  o->amg_cycles = 1;
 }
 
 const char* ipdg_last_error(void) { return g_last_error.c_str(); }

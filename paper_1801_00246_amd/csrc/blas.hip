@@ -14,12 +14,25 @@ namespace {
 __device__ __forceinline__ double ldd(const double* p, size_t i) { return p[i]; }
 __device__ __forceinline__ double ldd(const float* p, size_t i) { return static_cast<double>(p[i]); }
 
+// Position of a block in its launch: block b of nb.  A direct launch uses
+// blockIdx.x of gridDim.x; a batched launch the member-local block of its
+// block map, so that every member sees the launch shape of its own direct
+// launch (the same partial-sum slots and summation order).
+struct Blk {
+  int b, nb;
+};
+__device__ __forceinline__ Blk direct_blk() { return Blk{(int)blockIdx.x, (int)gridDim.x}; }
+
 template <int NV>
-__device__ __forceinline__ void commit(double (&v)[NV], double* partials) {
+__device__ __forceinline__ void commit(double (&v)[NV], double* partials, int b) {
   block_sum<NV>(v);
   if (threadIdx.x == 0)
 #pragma unroll
-    for (int k = 0; k < NV; ++k) partials[k * kMaxPartials + blockIdx.x] = v[k];
+    for (int k = 0; k < NV; ++k) partials[k * kMaxPartials + b] = v[k];
+}
+template <int NV>
+__device__ __forceinline__ void commit(double (&v)[NV], double* partials) {
+  commit<NV>(v, partials, (int)blockIdx.x);
 }
 
 // r = b - Ax; partials: (r, r), (b, b)
@@ -41,16 +54,15 @@ __global__ __launch_bounds__(kBlock) void k_residual(const double* __restrict__ 
 // x += alpha p; r -= alpha Ap; optionally z = dinv r (Jacobi, z in TZ).
 // partials: (r, r), and with Jacobi (r, z), (z, Ap).
 template <typename TZ, bool JAC>
-__global__ __launch_bounds__(kBlock) void k_update(double* __restrict__ x, double* __restrict__ r,
-                                                   const double* __restrict__ p,
-                                                   const double* __restrict__ Ap,
-                                                   const double* __restrict__ dinv,
-                                                   TZ* __restrict__ z, const CGScal* __restrict__ sc,
-                                                   size_t n, double* __restrict__ partials) {
+__device__ __forceinline__ void update_body(double* __restrict__ x, double* __restrict__ r,
+                                            const double* __restrict__ p, const double* __restrict__ Ap,
+                                            const double* __restrict__ dinv, TZ* __restrict__ z,
+                                            const CGScal* __restrict__ sc, size_t n,
+                                            double* __restrict__ partials, Blk k) {
   if (sc->done) return;
   const double alpha = sc->alpha;
   double v[3] = {0.0, 0.0, 0.0};
-  for (size_t i = blockIdx.x * (size_t)kBlock + threadIdx.x; i < n; i += (size_t)gridDim.x * kBlock) {
+  for (size_t i = k.b * (size_t)kBlock + threadIdx.x; i < n; i += (size_t)k.nb * kBlock) {
     const double api = Ap[i];
     x[i] += alpha * p[i];
     const double ri = r[i] - alpha * api;
@@ -63,54 +75,78 @@ __global__ __launch_bounds__(kBlock) void k_update(double* __restrict__ x, doubl
       v[2] += static_cast<double>(zi) * api;
     }
   }
-  commit<3>(v, partials);
+  commit<3>(v, partials, k.b);
+}
+template <typename TZ, bool JAC>
+__global__ __launch_bounds__(kBlock) void k_update(double* __restrict__ x, double* __restrict__ r,
+                                                   const double* __restrict__ p,
+                                                   const double* __restrict__ Ap,
+                                                   const double* __restrict__ dinv,
+                                                   TZ* __restrict__ z, const CGScal* __restrict__ sc,
+                                                   size_t n, double* __restrict__ partials) {
+  update_body<TZ, JAC>(x, r, p, Ap, dinv, z, sc, n, partials, direct_blk());
 }
 
 // partials slots 1, 2: (r, z), (z, Ap)
 template <typename TZ>
-__global__ __launch_bounds__(kBlock) void k_dots_rz(const double* __restrict__ r,
-                                                    const TZ* __restrict__ z,
-                                                    const double* __restrict__ Ap,
-                                                    const CGScal* __restrict__ sc, size_t n,
-                                                    double* __restrict__ partials) {
+__device__ __forceinline__ void dots_rz_body(const double* __restrict__ r, const TZ* __restrict__ z,
+                                             const double* __restrict__ Ap, const CGScal* __restrict__ sc,
+                                             size_t n, double* __restrict__ partials, Blk k) {
   if (sc->done) return;
   double v[2] = {0.0, 0.0};
-  for (size_t i = blockIdx.x * (size_t)kBlock + threadIdx.x; i < n; i += (size_t)gridDim.x * kBlock) {
+  for (size_t i = k.b * (size_t)kBlock + threadIdx.x; i < n; i += (size_t)k.nb * kBlock) {
     const double zi = ldd(z, i);
     v[0] += r[i] * zi;
     if (Ap) v[1] += zi * Ap[i];
   }
   block_sum<2>(v);
   if (threadIdx.x == 0) {
-    partials[1 * kMaxPartials + blockIdx.x] = v[0];
-    partials[2 * kMaxPartials + blockIdx.x] = v[1];
+    partials[1 * kMaxPartials + k.b] = v[0];
+    partials[2 * kMaxPartials + k.b] = v[1];
   }
+}
+template <typename TZ>
+__global__ __launch_bounds__(kBlock) void k_dots_rz(const double* __restrict__ r,
+                                                    const TZ* __restrict__ z,
+                                                    const double* __restrict__ Ap,
+                                                    const CGScal* __restrict__ sc, size_t n,
+                                                    double* __restrict__ partials) {
+  dots_rz_body<TZ>(r, z, Ap, sc, n, partials, direct_blk());
 }
 
 // p = z + beta p
 template <typename TZ>
-__global__ __launch_bounds__(kBlock) void k_pupdate(double* __restrict__ p, const TZ* __restrict__ z,
-                                                    const CGScal* __restrict__ sc, size_t n) {
+__device__ __forceinline__ void pupdate_body(double* __restrict__ p, const TZ* __restrict__ z,
+                                             const CGScal* __restrict__ sc, size_t n, Blk k) {
   if (sc->done) return;
   const double beta = sc->beta;
-  for (size_t i = blockIdx.x * (size_t)kBlock + threadIdx.x; i < n; i += (size_t)gridDim.x * kBlock)
+  for (size_t i = k.b * (size_t)kBlock + threadIdx.x; i < n; i += (size_t)k.nb * kBlock)
     p[i] = ldd(z, i) + beta * p[i];
+}
+template <typename TZ>
+__global__ __launch_bounds__(kBlock) void k_pupdate(double* __restrict__ p, const TZ* __restrict__ z,
+                                                    const CGScal* __restrict__ sc, size_t n) {
+  pupdate_body<TZ>(p, z, sc, n, direct_blk());
 }
 
 // z = dinv r (TZ) ; partials (r, z) in slot 1
 template <typename TZ>
+__device__ __forceinline__ void jacobi_body(const double* __restrict__ r, const double* __restrict__ dinv,
+                                            TZ* __restrict__ z, size_t n, Blk k) {
+  for (size_t i = k.b * (size_t)kBlock + threadIdx.x; i < n; i += (size_t)k.nb * kBlock)
+    z[i] = static_cast<TZ>(dinv[i] * r[i]);
+}
+template <typename TZ>
 __global__ __launch_bounds__(kBlock) void k_jacobi(const double* __restrict__ r,
                                                    const double* __restrict__ dinv,
                                                    TZ* __restrict__ z, size_t n) {
-  for (size_t i = blockIdx.x * (size_t)kBlock + threadIdx.x; i < n; i += (size_t)gridDim.x * kBlock)
-    z[i] = static_cast<TZ>(dinv[i] * r[i]);
+  jacobi_body<TZ>(r, dinv, z, n, direct_blk());
 }
 
 // Sum the partials of `nslots` slots over nparts blocks (fixed order) and
 // apply one step of the CG scalar recurrence.
-__global__ __launch_bounds__(kBlock) void k_finalize(const double* __restrict__ partials,
-                                                     int nparts, int nslots, CGScal* __restrict__ sc,
-                                                     int op) {
+__device__ __forceinline__ void finalize_body(const double* __restrict__ partials, int nparts, int nslots,
+                                              CGScal* __restrict__ sc, int op) {
   if ((op == kFinAlpha || op == kFinBeta) && sc->done) return;
   __shared__ double red[3][kBlock];
   for (int k = 0; k < nslots; ++k) {
@@ -160,19 +196,23 @@ __global__ __launch_bounds__(kBlock) void k_finalize(const double* __restrict__ 
     }
   }
 }
+__global__ __launch_bounds__(kBlock) void k_finalize(const double* __restrict__ partials,
+                                                     int nparts, int nslots, CGScal* __restrict__ sc,
+                                                     int op) {
+  finalize_body(partials, nparts, nslots, sc, op);
+}
 
 // Chebyshev smoothing on D^{-1} A (Saad Alg. 12.1):
 //   start from zero:     r = f;     d = c0 dinv f;      z = d
 //   start from z:        r = f - t; d = c0 dinv r;      z += d    (t = A z)
 //   step:                r -= t;    d = c1 d + c2 dinv r; z += d  (t = A d)
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_cheb(int mode, const T* __restrict__ f,
-                                                 const T* __restrict__ t, const T* __restrict__ dinv,
-                                                 T* __restrict__ z, T* __restrict__ d,
-                                                 T* __restrict__ r, T c0, T c1, T c2, size_t n,
-                                                 const int* __restrict__ skip) {
+__device__ __forceinline__ void cheb_body(int mode, const T* __restrict__ f, const T* __restrict__ t,
+                                          const T* __restrict__ dinv, T* __restrict__ z, T* __restrict__ d,
+                                          T* __restrict__ r, T c0, T c1, T c2, size_t n,
+                                          const int* __restrict__ skip, Blk k) {
   if (skip && *skip) return;
-  for (size_t i = blockIdx.x * (size_t)kBlock + threadIdx.x; i < n; i += (size_t)gridDim.x * kBlock) {
+  for (size_t i = k.b * (size_t)kBlock + threadIdx.x; i < n; i += (size_t)k.nb * kBlock) {
     if (mode == 0) {
       const T ri = f[i];
       r[i] = ri;
@@ -194,13 +234,86 @@ __global__ __launch_bounds__(kBlock) void k_cheb(int mode, const T* __restrict__
     }
   }
 }
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_cheb(int mode, const T* __restrict__ f,
+                                                 const T* __restrict__ t, const T* __restrict__ dinv,
+                                                 T* __restrict__ z, T* __restrict__ d,
+                                                 T* __restrict__ r, T c0, T c1, T c2, size_t n,
+                                                 const int* __restrict__ skip) {
+  cheb_body<T>(mode, f, t, dinv, z, d, r, c0, c1, c2, n, skip, direct_blk());
+}
 
+template <typename TD, typename TS>
+__device__ __forceinline__ void convert_body(TD* __restrict__ dst, const TS* __restrict__ src, size_t n,
+                                             const int* __restrict__ skip, Blk k) {
+  if (skip && *skip) return;
+  for (size_t i = k.b * (size_t)kBlock + threadIdx.x; i < n; i += (size_t)k.nb * kBlock)
+    dst[i] = static_cast<TD>(src[i]);
+}
 template <typename TD, typename TS>
 __global__ __launch_bounds__(kBlock) void k_convert(TD* __restrict__ dst, const TS* __restrict__ src,
                                                     size_t n, const int* __restrict__ skip) {
-  if (skip && *skip) return;
-  for (size_t i = blockIdx.x * (size_t)kBlock + threadIdx.x; i < n; i += (size_t)gridDim.x * kBlock)
-    dst[i] = static_cast<TD>(src[i]);
+  convert_body<TD, TS>(dst, src, n, skip, direct_blk());
+}
+
+// ---------------------------------------------------------------------------
+// Batched forms: one launch runs the same operation for many solves, each
+// block reading its member's arguments from a table and its member-local
+// block from the block map.
+// ---------------------------------------------------------------------------
+template <typename TZ, bool JAC>
+__global__ __launch_bounds__(kBlock) void kb_update(const VecArgs* __restrict__ tab, const BlockRef* __restrict__ map) {
+  const BlockRef m = map[blockIdx.x];
+  const VecArgs& a = tab[m.s];
+  update_body<TZ, JAC>(in_global((double*)a.x), in_global((double*)a.y), in_global((const double*)a.a),
+                       in_global((const double*)a.b), in_global((const double*)a.c), in_global((TZ*)a.z),
+                       in_global(a.sc), a.n, in_global(a.partials), Blk{m.b, m.nb});
+}
+template <typename TZ>
+__global__ __launch_bounds__(kBlock) void kb_dots_rz(const VecArgs* __restrict__ tab, const BlockRef* __restrict__ map) {
+  const BlockRef m = map[blockIdx.x];
+  const VecArgs& a = tab[m.s];
+  dots_rz_body<TZ>(in_global((const double*)a.a), in_global((const TZ*)a.b), in_global((const double*)a.c),
+                   in_global(a.sc), a.n, in_global(a.partials), Blk{m.b, m.nb});
+}
+template <typename TZ>
+__global__ __launch_bounds__(kBlock) void kb_pupdate(const VecArgs* __restrict__ tab, const BlockRef* __restrict__ map) {
+  const BlockRef m = map[blockIdx.x];
+  const VecArgs& a = tab[m.s];
+  pupdate_body<TZ>(in_global((double*)a.x), in_global((const TZ*)a.a), in_global(a.sc), a.n, Blk{m.b, m.nb});
+}
+template <typename TZ>
+__global__ __launch_bounds__(kBlock) void kb_jacobi(const VecArgs* __restrict__ tab, const BlockRef* __restrict__ map) {
+  const BlockRef m = map[blockIdx.x];
+  const VecArgs& a = tab[m.s];
+  jacobi_body<TZ>(in_global((const double*)a.a), in_global((const double*)a.b), in_global((TZ*)a.z), a.n,
+                  Blk{m.b, m.nb});
+}
+__global__ __launch_bounds__(kBlock) void kb_finalize(const VecArgs* __restrict__ tab, const BlockRef* __restrict__ map) {
+  const BlockRef m = map[blockIdx.x];
+  const VecArgs& a = tab[m.s];
+  finalize_body(in_global((const double*)a.a), a.nparts, a.nslots, in_global(a.scw), a.op);
+}
+template <typename T>
+__global__ __launch_bounds__(kBlock) void kb_cheb(const VecArgs* __restrict__ tab, const BlockRef* __restrict__ map) {
+  const BlockRef m = map[blockIdx.x];
+  const VecArgs& a = tab[m.s];
+  cheb_body<T>(a.mode, in_global((const T*)a.a), in_global((const T*)a.b), in_global((const T*)a.c),
+               in_global((T*)a.z), in_global((T*)a.x), in_global((T*)a.y), T(a.c0), T(a.c1), T(a.c2), a.n,
+               in_global(a.skip), Blk{m.b, m.nb});
+}
+template <typename TD, typename TS>
+__global__ __launch_bounds__(kBlock) void kb_convert(const VecArgs* __restrict__ tab, const BlockRef* __restrict__ map) {
+  const BlockRef m = map[blockIdx.x];
+  const VecArgs& a = tab[m.s];
+  convert_body<TD, TS>(in_global((TD*)a.x), in_global((const TS*)a.a), a.n, in_global(a.skip), Blk{m.b, m.nb});
+}
+
+// dst[i] = *src[i]: the CG scalars of many solves into one array
+__global__ __launch_bounds__(64) void k_scal_gather(const CGScal* const* __restrict__ src, CGScal* __restrict__ dst,
+                                                    int n) {
+  const int i = blockIdx.x * 64 + threadIdx.x;
+  if (i < n) dst[i] = *src[i];
 }
 
 // coarse-solve initialisation: x = 0, r = f, z = dinv f, p = z; partials
@@ -425,6 +538,53 @@ hipError_t zero_ints(void* p, int n, hipStream_t s) {
 
 hipError_t fill(double* p, double v, size_t n, hipStream_t s) {
   LAUNCH(k_fill, n, s, p, v, n);
+  return hipGetLastError();
+}
+
+hipError_t vec_batch(VecOp op, bool fp32, bool flag, const VecArgs* tab, const BlockRef* map, int nblocks,
+                     hipStream_t s) {
+  if (nblocks <= 0) return hipSuccess;
+  const dim3 g(nblocks), b(kBlock);
+  switch (op) {
+    case VecOp::kUpdate:
+      if (fp32) {
+        if (flag) hipLaunchKernelGGL((kb_update<float, true>), g, b, 0, s, tab, map);
+        else hipLaunchKernelGGL((kb_update<float, false>), g, b, 0, s, tab, map);
+      } else {
+        if (flag) hipLaunchKernelGGL((kb_update<double, true>), g, b, 0, s, tab, map);
+        else hipLaunchKernelGGL((kb_update<double, false>), g, b, 0, s, tab, map);
+      }
+      break;
+    case VecOp::kDotsRz:
+      if (fp32) hipLaunchKernelGGL(kb_dots_rz<float>, g, b, 0, s, tab, map);
+      else hipLaunchKernelGGL(kb_dots_rz<double>, g, b, 0, s, tab, map);
+      break;
+    case VecOp::kPupdate:
+      if (fp32) hipLaunchKernelGGL(kb_pupdate<float>, g, b, 0, s, tab, map);
+      else hipLaunchKernelGGL(kb_pupdate<double>, g, b, 0, s, tab, map);
+      break;
+    case VecOp::kJacobi:
+      if (fp32) hipLaunchKernelGGL(kb_jacobi<float>, g, b, 0, s, tab, map);
+      else hipLaunchKernelGGL(kb_jacobi<double>, g, b, 0, s, tab, map);
+      break;
+    case VecOp::kFinalize:
+      hipLaunchKernelGGL(kb_finalize, g, b, 0, s, tab, map);
+      break;
+    case VecOp::kCheb:
+      if (fp32) hipLaunchKernelGGL(kb_cheb<float>, g, b, 0, s, tab, map);
+      else hipLaunchKernelGGL(kb_cheb<double>, g, b, 0, s, tab, map);
+      break;
+    case VecOp::kConvert:
+      if (flag) hipLaunchKernelGGL((kb_convert<float, double>), g, b, 0, s, tab, map);
+      else hipLaunchKernelGGL((kb_convert<double, float>), g, b, 0, s, tab, map);
+      break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t scal_gather(const CGScal* const* src, CGScal* dst, int n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_scal_gather, dim3((n + 63) / 64), dim3(64), 0, s, src, dst, n);
   return hipGetLastError();
 }
 

@@ -19,7 +19,40 @@ constexpr int kMaxPartials = 65536;
 
 enum FinOp { kFinResidual = 0, kFinInit = 1, kFinAlpha = 2, kFinBeta = 3 };
 
+// One member's arguments of a batched vector operation (the parameters of the
+// direct launch, by role):
+//   update   x += alpha p, r -= alpha Ap (+ Jacobi z): x=x, y=r, a=p, b=Ap, c=dinv, z
+//   dots_rz  a=r, b=z, c=Ap        pupdate  x=p, a=z      jacobi  a=r, b=dinv, z
+//   finalize a=partials, scw, nparts, nslots, op
+//   cheb     mode, a=f, b=t, c=dinv, z, x=d, y=r, c0..c2   convert  x=dst, a=src
+struct VecArgs {
+  const void* a = nullptr;
+  const void* b = nullptr;
+  const void* c = nullptr;
+  void* x = nullptr;
+  void* y = nullptr;
+  void* z = nullptr;
+  const CGScal* sc = nullptr;
+  CGScal* scw = nullptr;
+  double c0 = 0, c1 = 0, c2 = 0;
+  size_t n = 0;
+  double* partials = nullptr;
+  const int* skip = nullptr;
+  int nparts = 0, nslots = 0, op = 0, mode = 0;
+};
+
+enum class VecOp { kUpdate, kDotsRz, kPupdate, kJacobi, kFinalize, kCheb, kConvert };
+
+// Batched vector operation: fp32 selects the FP32 form (z of update, dots_rz,
+// pupdate and jacobi; T of cheb), flag the Jacobi update or, for convert, the
+// direction FP64 -> FP32.
+hipError_t vec_batch(VecOp op, bool fp32, bool flag, const VecArgs* tab, const BlockRef* map, int nblocks,
+                     hipStream_t s);
+
 int flat_grid(size_t n);
+
+// dst[i] = *src[i] for i < n (src: device array of n device pointers).
+hipError_t scal_gather(const CGScal* const* src, CGScal* dst, int n, hipStream_t s);
 
 hipError_t residual(const double* b, const double* Ax, double* r, size_t n, double* partials, hipStream_t s);
 hipError_t cg_update(bool fp32z, bool jacobi, double* x, double* r, const double* p, const double* Ap,

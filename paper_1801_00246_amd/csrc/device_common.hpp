@@ -17,6 +17,14 @@ struct alignas(16) Conn {
 __host__ __device__ inline int conn_fp(int info, int f) { return (info >> (2 * f)) & 3; }
 __host__ __device__ inline int conn_bc(int info, int f) { return (info >> (8 + 2 * f)) & 3; }
 
+// Block of a batched launch (one launch running the same kernel for many
+// solves): member s, its member-local block b of nb (the grid of the
+// member's own launch) and, for element kernels, the tile stride of that
+// grid's die mapping.
+struct BlockRef {
+  int s, b, nb, per;
+};
+
 constexpr int kBlock = 256;   // threads per block of the element kernels
 constexpr int kXcd = 8;       // accelerator complex dies of an MI355X
 
@@ -31,6 +39,21 @@ inline int xcd_grid(int ntiles, int& per) {
 }
 
 #ifdef __HIPCC__
+// A pointer read from an argument table in device memory (a batched launch)
+// carries no address space, so loads through it would be generic (flat) and
+// never scalar.  These casts restore what a kernel argument gets: global
+// memory, or constant memory for read-only tables (wave-uniform loads from it
+// become scalar loads).
+// (Through an integer: a direct cast pair folds back to the generic pointer.)
+template <typename T>
+__device__ __forceinline__ T* in_global(T* p) {
+  return (T*)((__attribute__((address_space(1))) T*)(unsigned long long)p);
+}
+template <typename T>
+__device__ __forceinline__ const T* in_constant(const T* p) {
+  return (const T*)((const __attribute__((address_space(4))) T*)(unsigned long long)p);
+}
+
 // Sum of v over the block, valid in thread 0.  Fixed reduction order, so the
 // result is bitwise reproducible for a given launch shape.
 template <int NV>

@@ -73,6 +73,24 @@ hipError_t ax(int N, Kind kind, const ElemArgs& a, hipStream_t s) {
   IPDG_SWITCH(N, C)
 #undef C
 }
+bool ax_batch_variant(int v) { return v == 0 || v == 2 || v == kAxCoop; }
+hipError_t ax_batch(int N, Kind kind, bool kap, int variant, const ElemArgs* tab, const BlockRef* map, int nblocks,
+                    hipStream_t s) {
+#define C(n) launch_ax_batch<n>(kind, kap, variant, tab, map, nblocks, s)
+  IPDG_SWITCH(N, C)
+#undef C
+}
+hipError_t minv_batch(int N, Kind kind, const ElemArgs* tab, const BlockRef* map, int nblocks, hipStream_t s) {
+#define C(n) launch_minv_batch<n>(kind, tab, map, nblocks, s)
+  IPDG_SWITCH(N, C)
+#undef C
+}
+hipError_t transfer_batch(int Nf, int Nc, bool restrict_op, Kind kind, const TransferArgs* tab, const BlockRef* map,
+                          int nblocks, hipStream_t s) {
+#define C(n) launch_transfer_batch<n>(Nc, restrict_op, kind, tab, map, nblocks, s)
+  IPDG_SWITCH(Nf, C)
+#undef C
+}
 hipError_t diag(int N, Kind kind, const ElemArgs& a, hipStream_t s) {
 #define C(n) launch_diag<n>(kind, a, s)
   IPDG_SWITCH(N, C)

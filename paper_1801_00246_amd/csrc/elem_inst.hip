@@ -37,17 +37,15 @@ constexpr int kPitch = kBlock + 1;
 // STAGE: the block's own inputs and outputs go through LDS, so that global
 // loads and stores are fully coalesced (lane t touches word t of the block's
 // contiguous chunk) instead of Np-strided per lane.
-template <typename TC, typename TX, typename TY, bool KAP, bool STAGE, int WAVES>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WAVES > 0 ? WAVES : 1)))
-void k_ax(const TX* __restrict__ x, TY* __restrict__ y,
-                                               const TC* __restrict__ geo,
-                                               const Conn* __restrict__ conn,
-                                               const TC* __restrict__ kap,
-                                               const TC* __restrict__ ops, TC lambda, TC ctau,
-                                               int K, int per, double* __restrict__ partials,
-                                               const int* __restrict__ skip) {
+// blk: the block's position in its (member-local) launch grid, per: that
+// grid's die-mapping stride.
+template <typename TC, typename TX, typename TY, bool KAP, bool STAGE>
+__device__ __forceinline__ void ax_body(const TX* __restrict__ x, TY* __restrict__ y, const TC* __restrict__ geo,
+                                        const Conn* __restrict__ conn, const TC* __restrict__ kap,
+                                        const TC* __restrict__ ops, TC lambda, TC ctau, int K, int per,
+                                        double* __restrict__ partials, const int* __restrict__ skip, int blk) {
   if (skip && *skip) return;
-  const int e0 = xcd_tile(blockIdx.x, per) * kBlock;
+  const int e0 = xcd_tile(blk, per) * kBlock;
   const int e = e0 + threadIdx.x;
   const bool want_dot = partials != nullptr;
   double dot = 0.0;
@@ -97,8 +95,28 @@ void k_ax(const TX* __restrict__ x, TY* __restrict__ y,
   if (partials) {
     double v[1] = {dot};
     block_sum<1>(v);
-    if (threadIdx.x == 0) partials[blockIdx.x] = v[0];
+    if (threadIdx.x == 0) partials[blk] = v[0];
   }
+}
+
+template <typename TC, typename TX, typename TY, bool KAP, bool STAGE, int WAVES>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WAVES > 0 ? WAVES : 1)))
+void k_ax(const TX* __restrict__ x, TY* __restrict__ y, const TC* __restrict__ geo, const Conn* __restrict__ conn,
+          const TC* __restrict__ kap, const TC* __restrict__ ops, TC lambda, TC ctau, int K, int per,
+          double* __restrict__ partials, const int* __restrict__ skip) {
+  ax_body<TC, TX, TY, KAP, STAGE>(x, y, geo, conn, kap, ops, lambda, ctau, K, per, partials, skip, blockIdx.x);
+}
+
+// Batched form (many solves of this degree in one launch; variants 0 and 2).
+template <typename TC, typename TX, typename TY, bool KAP, int WAVES>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WAVES > 0 ? WAVES : 1)))
+void kb_ax(const ElemArgs* __restrict__ tab, const BlockRef* __restrict__ map) {
+  const BlockRef m = map[blockIdx.x];
+  const ElemArgs& a = tab[m.s];
+  ax_body<TC, TX, TY, KAP, false>(in_global(static_cast<const TX*>(a.x)), in_global(static_cast<TY*>(a.y)),
+                                  in_global(static_cast<const TC*>(a.geo)), in_global(a.conn),
+                                  in_global(static_cast<const TC*>(a.kap)), in_constant(static_cast<const TC*>(a.ops)),
+                                  TC(a.lambda), TC(a.ctau), a.K, m.per, in_global(a.partials), in_global(a.skip), m.b);
 }
 
 // Waves per SIMD the cooperative kernel's register allocation must leave
@@ -112,13 +130,10 @@ constexpr int coop_waves() {
 // Cooperative operator (sipdg_coop.hpp): a block of three waves per tile of
 // 64 elements; the partial sum of x . y (optional) is one per block.
 template <typename TC, typename TX, typename TY, bool KAP>
-__global__ __launch_bounds__(kCoopThreads) __attribute__((amdgpu_waves_per_eu(coop_waves<TC>()))) void k_axc(const TX* __restrict__ x, TY* __restrict__ y,
-                                                      const TC* __restrict__ geo,
-                                                      const Conn* __restrict__ conn,
-                                                      const TC* __restrict__ kap,
-                                                      const TC* __restrict__ ops, TC lambda, TC ctau,
-                                                      int K, int per, double* __restrict__ partials,
-                                                      const int* __restrict__ skip) {
+__device__ __forceinline__ void axc_body(const TX* __restrict__ x, TY* __restrict__ y, const TC* __restrict__ geo,
+                                         const Conn* __restrict__ conn, const TC* __restrict__ kap,
+                                         const TC* __restrict__ ops, TC lambda, TC ctau, int K, int per,
+                                         double* __restrict__ partials, const int* __restrict__ skip, int blk) {
   if (skip && *skip) return;
   using CL = CoopLayout<N>;
   constexpr int Nfp = Tri<N>::Nfp, P = kCoopPitch;
@@ -129,10 +144,10 @@ __global__ __launch_bounds__(kCoopThreads) __attribute__((amdgpu_waves_per_eu(co
   __shared__ TC TS[3 * Nfp * P];    // J |F|/|E| s_f at the face nodes
   __shared__ TC SC[kMf ? sc_slot::kCount * P : 1];   // per-element row-phase factors
   __shared__ double red[3];
-  const int e0 = xcd_tile(blockIdx.x, per) * kCoopTile;
+  const int e0 = xcd_tile(blk, per) * kCoopTile;
   const int ne = K - e0 < kCoopTile ? K - e0 : kCoopTile;
   if (ne <= 0) {                    // a block past the last tile (the grid is rounded up)
-    if (partials && threadIdx.x == 0) partials[blockIdx.x] = 0.0;
+    if (partials && threadIdx.x == 0) partials[blk] = 0.0;
     return;
   }
   const int lane = threadIdx.x & 63;
@@ -244,7 +259,27 @@ __global__ __launch_bounds__(kCoopThreads) __attribute__((amdgpu_waves_per_eu(co
       dst[t] = static_cast<TY>(U[j * P + le]);
     }
   }
-  if (want_dot && threadIdx.x == 0) partials[blockIdx.x] = (red[0] + red[1]) + red[2];
+  if (want_dot && threadIdx.x == 0) partials[blk] = (red[0] + red[1]) + red[2];
+}
+
+template <typename TC, typename TX, typename TY, bool KAP>
+__global__ __launch_bounds__(kCoopThreads) __attribute__((amdgpu_waves_per_eu(coop_waves<TC>())))
+void k_axc(const TX* __restrict__ x, TY* __restrict__ y, const TC* __restrict__ geo, const Conn* __restrict__ conn,
+           const TC* __restrict__ kap, const TC* __restrict__ ops, TC lambda, TC ctau, int K, int per,
+           double* __restrict__ partials, const int* __restrict__ skip) {
+  axc_body<TC, TX, TY, KAP>(x, y, geo, conn, kap, ops, lambda, ctau, K, per, partials, skip, blockIdx.x);
+}
+
+// Batched form (many solves of this degree in one launch).
+template <typename TC, typename TX, typename TY, bool KAP>
+__global__ __launch_bounds__(kCoopThreads) __attribute__((amdgpu_waves_per_eu(coop_waves<TC>())))
+void kb_axc(const ElemArgs* __restrict__ tab, const BlockRef* __restrict__ map) {
+  const BlockRef m = map[blockIdx.x];
+  const ElemArgs& a = tab[m.s];
+  axc_body<TC, TX, TY, KAP>(in_global(static_cast<const TX*>(a.x)), in_global(static_cast<TY*>(a.y)),
+                            in_global(static_cast<const TC*>(a.geo)), in_global(a.conn),
+                            in_global(static_cast<const TC*>(a.kap)), in_constant(static_cast<const TC*>(a.ops)),
+                            TC(a.lambda), TC(a.ctau), a.K, m.per, in_global(a.partials), in_global(a.skip), m.b);
 }
 
 template <typename TC, bool KAP>
@@ -267,13 +302,12 @@ __global__ __launch_bounds__(kBlock) void k_diag(TC* __restrict__ d, const TC* _
 
 // y = J M x (INV = false) or y = (J M)^{-1} x (INV = true)
 template <typename TC, typename TX, typename TY, bool INV>
-__global__ __launch_bounds__(kBlock) void k_mass(const TX* __restrict__ x, TY* __restrict__ y,
-                                                 const TC* __restrict__ geo,
-                                                 const TC* __restrict__ ops, int K, int per,
-                                                 const int* __restrict__ skip) {
+__device__ __forceinline__ void mass_body(const TX* __restrict__ x, TY* __restrict__ y, const TC* __restrict__ geo,
+                                          const TC* __restrict__ ops, int K, int per, const int* __restrict__ skip,
+                                          int blk) {
   if (skip && *skip) return;
   using L = OpsLayout<N>;
-  const int e = xcd_tile(blockIdx.x, per) * kBlock + threadIdx.x;
+  const int e = xcd_tile(blk, per) * kBlock + threadIdx.x;
   if (e >= K) return;
   const TC rx = geo[4 * e + 0], sx = geo[4 * e + 1], ry = geo[4 * e + 2], sy = geo[4 * e + 3];
   const TC det = rx * sy - sx * ry;  // 1 / J
@@ -288,15 +322,30 @@ __global__ __launch_bounds__(kBlock) void k_mass(const TX* __restrict__ x, TY* _
     y[(size_t)e * Np + i] = static_cast<TY>(INV ? acc * det : acc / det);
   }
 }
+template <typename TC, typename TX, typename TY, bool INV>
+__global__ __launch_bounds__(kBlock) void k_mass(const TX* __restrict__ x, TY* __restrict__ y,
+                                                 const TC* __restrict__ geo,
+                                                 const TC* __restrict__ ops, int K, int per,
+                                                 const int* __restrict__ skip) {
+  mass_body<TC, TX, TY, INV>(x, y, geo, ops, K, per, skip, blockIdx.x);
+}
+template <typename TC, typename TX, typename TY, bool INV>
+__global__ __launch_bounds__(kBlock) void kb_mass(const ElemArgs* __restrict__ tab, const BlockRef* __restrict__ map) {
+  const BlockRef m = map[blockIdx.x];
+  const ElemArgs& a = tab[m.s];
+  mass_body<TC, TX, TY, INV>(in_global(static_cast<const TX*>(a.x)), in_global(static_cast<TY*>(a.y)),
+                             in_global(static_cast<const TC*>(a.geo)), in_constant(static_cast<const TC*>(a.ops)), a.K,
+                             m.per, in_global(a.skip), m.b);
+}
 
 // Restriction rc = P^T (f - Az) and prolongation z += P zc per element.
 template <int NC, typename T>
-__global__ __launch_bounds__(kBlock) void k_restrict(const T* __restrict__ f, const T* __restrict__ Az,
-                                                     T* __restrict__ rc, const T* __restrict__ P,
-                                                     int K, int per, const int* __restrict__ skip) {
+__device__ __forceinline__ void restrict_body(const T* __restrict__ f, const T* __restrict__ Az, T* __restrict__ rc,
+                                              const T* __restrict__ P, int K, int per, const int* __restrict__ skip,
+                                              int blk) {
   if (skip && *skip) return;
   constexpr int Npc = Tri<NC>::Np;
-  const int e = xcd_tile(blockIdx.x, per) * kBlock + threadIdx.x;
+  const int e = xcd_tile(blk, per) * kBlock + threadIdx.x;
   if (e >= K) return;
   T r[Np];
 #pragma unroll
@@ -309,14 +358,28 @@ __global__ __launch_bounds__(kBlock) void k_restrict(const T* __restrict__ f, co
     rc[(size_t)e * Npc + c] = acc;
   }
 }
+template <int NC, typename T>
+__global__ __launch_bounds__(kBlock) void k_restrict(const T* __restrict__ f, const T* __restrict__ Az,
+                                                     T* __restrict__ rc, const T* __restrict__ P,
+                                                     int K, int per, const int* __restrict__ skip) {
+  restrict_body<NC, T>(f, Az, rc, P, K, per, skip, blockIdx.x);
+}
+template <int NC, typename T>
+__global__ __launch_bounds__(kBlock) void kb_restrict(const TransferArgs* __restrict__ tab,
+                                                      const BlockRef* __restrict__ map) {
+  const BlockRef m = map[blockIdx.x];
+  const TransferArgs& a = tab[m.s];
+  restrict_body<NC, T>(in_global(static_cast<const T*>(a.f)), in_global(static_cast<const T*>(a.Az)),
+                       in_global(static_cast<T*>(a.coarse)), in_constant(static_cast<const T*>(a.P)), a.K, m.per,
+                       in_global(a.skip), m.b);
+}
 
 template <int NC, typename T>
-__global__ __launch_bounds__(kBlock) void k_prolong(const T* __restrict__ zc, T* __restrict__ z,
-                                                    const T* __restrict__ P, int K, int per,
-                                                    const int* __restrict__ skip) {
+__device__ __forceinline__ void prolong_body(const T* __restrict__ zc, T* __restrict__ z, const T* __restrict__ P,
+                                             int K, int per, const int* __restrict__ skip, int blk) {
   if (skip && *skip) return;
   constexpr int Npc = Tri<NC>::Np;
-  const int e = xcd_tile(blockIdx.x, per) * kBlock + threadIdx.x;
+  const int e = xcd_tile(blk, per) * kBlock + threadIdx.x;
   if (e >= K) return;
   T c[Npc];
 #pragma unroll
@@ -328,6 +391,20 @@ __global__ __launch_bounds__(kBlock) void k_prolong(const T* __restrict__ zc, T*
     for (int j = 0; j < Npc; ++j) acc += P[i * Npc + j] * c[j];
     z[(size_t)e * Np + i] = acc;
   }
+}
+template <int NC, typename T>
+__global__ __launch_bounds__(kBlock) void k_prolong(const T* __restrict__ zc, T* __restrict__ z,
+                                                    const T* __restrict__ P, int K, int per,
+                                                    const int* __restrict__ skip) {
+  prolong_body<NC, T>(zc, z, P, K, per, skip, blockIdx.x);
+}
+template <int NC, typename T>
+__global__ __launch_bounds__(kBlock) void kb_prolong(const TransferArgs* __restrict__ tab,
+                                                     const BlockRef* __restrict__ map) {
+  const BlockRef m = map[blockIdx.x];
+  const TransferArgs& a = tab[m.s];
+  prolong_body<NC, T>(in_global(static_cast<const T*>(a.coarse)), in_global(static_cast<T*>(a.fine)),
+                      in_constant(static_cast<const T*>(a.P)), a.K, m.per, in_global(a.skip), m.b);
 }
 
 
@@ -1256,6 +1333,88 @@ hipError_t launch_restrict<N>(int Nc, Kind kind, const TransferArgs& a, hipStrea
 template <>
 hipError_t launch_prolong<N>(int Nc, Kind kind, const TransferArgs& a, hipStream_t s) {
   return transfer(Nc, false, kind, a, s);
+}
+
+template <>
+hipError_t launch_ax_batch<N>(Kind kind, bool kap, int variant, const ElemArgs* tab, const BlockRef* map, int nblocks,
+                              hipStream_t s) {
+  if (nblocks <= 0) return hipSuccess;
+  if (!ax_batch_variant(variant) || !ax_variant_exists(N, variant)) return hipErrorInvalidValue;
+  auto go = [&](auto kern, int threads) {
+    hipLaunchKernelGGL(kern, dim3(nblocks), dim3(threads), 0, s, tab, map);
+    return hipGetLastError();
+  };
+  // the element-per-lane kernel at the variant's occupancy (variant 2 =
+  // raised occupancy, where the degree has it)
+  auto lane = [&](auto tc, auto kp) {
+    using TC = decltype(tc);
+    constexpr bool KP = decltype(kp)::value;
+    if constexpr (kHasBoost && ax_boost_waves<TC>() > 0) {
+      if (variant == 2) return go(kb_ax<TC, TC, TC, KP, ax_boost_waves<TC>()>, kBlock);
+    }
+    return go(kb_ax<TC, TC, TC, KP, 0>, kBlock);
+  };
+  auto one = [&](auto tc) {
+    using TC = decltype(tc);
+    if (variant == kAxCoop) {
+      if (kap) return go(kb_axc<TC, TC, TC, true>, kCoopThreads);
+      return go(kb_axc<TC, TC, TC, false>, kCoopThreads);
+    }
+    if (kap) return lane(tc, std::true_type{});
+    return lane(tc, std::false_type{});
+  };
+  if (kind == Kind::F64) return one(double{});
+  if (kind == Kind::F32) return one(float{});
+  return hipErrorInvalidValue;
+}
+
+template <>
+hipError_t launch_minv_batch<N>(Kind kind, const ElemArgs* tab, const BlockRef* map, int nblocks, hipStream_t s) {
+  if (nblocks <= 0) return hipSuccess;
+  switch (kind) {
+    case Kind::F64:
+      hipLaunchKernelGGL((kb_mass<double, double, double, true>), dim3(nblocks), dim3(kBlock), 0, s, tab, map);
+      break;
+    case Kind::F32:
+      hipLaunchKernelGGL((kb_mass<float, float, float, true>), dim3(nblocks), dim3(kBlock), 0, s, tab, map);
+      break;
+    case Kind::F32_IN64:
+      hipLaunchKernelGGL((kb_mass<float, double, float, true>), dim3(nblocks), dim3(kBlock), 0, s, tab, map);
+      break;
+  }
+  return hipGetLastError();
+}
+
+template <>
+hipError_t launch_transfer_batch<N>(int Nc, bool restrict_op, Kind kind, const TransferArgs* tab, const BlockRef* map,
+                                    int nblocks, hipStream_t s) {
+  if (nblocks <= 0) return hipSuccess;
+  if (Nc >= N || Nc < 1) return hipErrorInvalidValue;
+  auto go = [&](auto nc) -> hipError_t {
+    constexpr int NCC = decltype(nc)::value;
+    if constexpr (NCC < N) {
+      if (kind == Kind::F64) {
+        if (restrict_op) hipLaunchKernelGGL((kb_restrict<NCC, double>), dim3(nblocks), dim3(kBlock), 0, s, tab, map);
+        else hipLaunchKernelGGL((kb_prolong<NCC, double>), dim3(nblocks), dim3(kBlock), 0, s, tab, map);
+      } else {
+        if (restrict_op) hipLaunchKernelGGL((kb_restrict<NCC, float>), dim3(nblocks), dim3(kBlock), 0, s, tab, map);
+        else hipLaunchKernelGGL((kb_prolong<NCC, float>), dim3(nblocks), dim3(kBlock), 0, s, tab, map);
+      }
+      return hipGetLastError();
+    } else {
+      return hipErrorInvalidValue;
+    }
+  };
+  switch (Nc) {
+    case 1: return go(std::integral_constant<int, 1>{});
+    case 2: return go(std::integral_constant<int, 2>{});
+    case 3: return go(std::integral_constant<int, 3>{});
+    case 4: return go(std::integral_constant<int, 4>{});
+    case 5: return go(std::integral_constant<int, 5>{});
+    case 6: return go(std::integral_constant<int, 6>{});
+    case 7: return go(std::integral_constant<int, 7>{});
+    default: return hipErrorInvalidValue;
+  }
 }
 
 }  // namespace ipdg

@@ -51,6 +51,15 @@ int ax_partials(int N, bool fp32, int K);
 
 // y = A x (SIPDG operator).  Per degree, defined in the per-degree units.
 template <int N> hipError_t launch_ax(Kind kind, const ElemArgs& a, hipStream_t s);
+// Batched launches over many solves of degree N: tab holds one argument
+// record per solve, map one entry per block (device memory).  The operator
+// runs variant 0, 2 (element per lane, raised occupancy) or 4 (cooperative);
+// each gives every solve the result of its own launch of that variant.
+bool ax_batch_variant(int v);
+template <int N> hipError_t launch_ax_batch(Kind kind, bool kap, int variant, const ElemArgs* tab,
+                                            const BlockRef* map, int nblocks, hipStream_t s);
+hipError_t ax_batch(int N, Kind kind, bool kap, int variant, const ElemArgs* tab, const BlockRef* map, int nblocks,
+                    hipStream_t s);
 // y = diag(A) (x unused).
 template <int N> hipError_t launch_diag(Kind kind, const ElemArgs& a, hipStream_t s);
 // y = J M x  (block-diagonal mass)
@@ -77,6 +86,14 @@ struct TransferArgs {
   const int* skip = nullptr;
 };
 template <int Nf> hipError_t launch_restrict(int Nc, Kind kind, const TransferArgs& a, hipStream_t s);
+template <int Nf> hipError_t launch_transfer_batch(int Nc, bool restrict_op, Kind kind, const TransferArgs* tab,
+                                                   const BlockRef* map, int nblocks, hipStream_t s);
+hipError_t transfer_batch(int Nf, int Nc, bool restrict_op, Kind kind, const TransferArgs* tab, const BlockRef* map,
+                          int nblocks, hipStream_t s);
+// Batched block inverse mass (kind as for launch_minv).
+template <int N> hipError_t launch_minv_batch(Kind kind, const ElemArgs* tab, const BlockRef* map, int nblocks,
+                                              hipStream_t s);
+hipError_t minv_batch(int N, Kind kind, const ElemArgs* tab, const BlockRef* map, int nblocks, hipStream_t s);
 template <int Nf> hipError_t launch_prolong(int Nc, Kind kind, const TransferArgs& a, hipStream_t s);
 
 // Whole Jacobi-PCG solve of one (coarse) level in a single persistent launch:

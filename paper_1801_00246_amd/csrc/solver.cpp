@@ -36,6 +36,7 @@
 #include <cstdlib>
 #include <random>
 
+#include "amg.hpp"
 #include "blas.hpp"
 #include "refelem.hpp"
 
@@ -61,11 +62,37 @@ struct Level {
   const void* dinv() const { return fp32 ? dinv32.get() : dinv64.get(); }
 };
 
+constexpr int kAmgMaxLevels = 12;     // levels of the algebraic hierarchy, the degree-1 level included
+constexpr int kAmgMaxCoarse = 2048;   // largest coarsest level (inverted densely on the host)
+
+// Algebraic levels below the degree-1 level (pMG-AMG, Sec. 3).  Level 0 is
+// the degree-1 p-multigrid level itself (matrix-free); level 1 holds one
+// value per element; further levels one per aggregate.
+struct AmgLevel {
+  int n = 0;
+  double rho = 0;                  // Gershgorin bound of D^-1 A
+  DevBuf ptr, col, val, dinv;      // A in compressed rows (level precision)
+  DevBuf f, z, t, r, d;            // cycle work
+};
+struct AmgXfer {                   // level l -> l + 1
+  int n = 0, nc = 0;
+  DevBuf agg, mptr, mem;           // aggregate of each node; members of each aggregate
+};
+struct AmgSet {
+  std::vector<int> sizes;          // unknowns per level, the degree-1 level first
+  std::vector<AmgLevel> lv;        // lv[0] unused (the degree-1 level is the p-level)
+  std::vector<AmgXfer> xf;
+  DevBuf inv;                      // inverse of the coarsest matrix (dense, level precision)
+  DevBuf t0, res0, z0;             // degree-1 work of repeated cycles
+};
+
 struct Work : SolverWork {
   // configuration the setup was built for
   double lambda = NAN, ctau = NAN;
   int pc = -1, prec = -1, cheb_degree = 0, coarse_max = 0, nlev = 0, rho_steps = 0;
   double cheb_lo = 0, cheb_hi = 0, coarse_tol = 0;
+  int coarse_amg = 0, amg_coarse_size = 0, amg_cycles = 0;
+  std::unique_ptr<AmgSet> amg;
   int degrees[IPDG_MAX_LEVELS] = {0};
   double rho_in[IPDG_MAX_LEVELS] = {0};
   bool has_kappa = false;
@@ -82,11 +109,10 @@ struct Work : SolverWork {
   hipStream_t gs = nullptr;        // internal stream of the solver (default priority)
   hipGraphExec_t graph = nullptr;  // check_every captured outer iterations
   int graph_iters = 0;
-  // one outer iteration split at its coarsest-level solve (batched coarse
-  // mode), and that solve's right-hand side and solution buffers
-  hipGraphExec_t graph_pre = nullptr, graph_post = nullptr;
-  const void* split_f = nullptr;
-  void* split_x = nullptr;
+  // right-hand side and solution of the coarsest-level solve, as recorded
+  // for a fused batch
+  const void* coarse_f = nullptr;
+  void* coarse_x = nullptr;
   unsigned long long setup_id = 0;   // changes with every new setup (never reused)
 
   void drop_main() {
@@ -94,16 +120,10 @@ struct Work : SolverWork {
     graph = nullptr;
     graph_iters = 0;
   }
-  void drop_split() {
-    if (graph_pre) (void)hipGraphExecDestroy(graph_pre);
-    if (graph_post) (void)hipGraphExecDestroy(graph_post);
-    graph_pre = graph_post = nullptr;
-    split_f = nullptr;
-    split_x = nullptr;
-  }
   void drop_graph() {
     drop_main();
-    drop_split();
+    coarse_f = nullptr;
+    coarse_x = nullptr;
   }
   ~Work() override {
     drop_graph();
@@ -158,6 +178,40 @@ double tridiag_max_eig(const std::vector<double>& a, const std::vector<double>& 
   double mx = -INFINITY;
   for (int i = 0; i < k; ++i) mx = std::max(mx, A[i * k + i]);
   return mx;
+}
+
+// One launch of an outer iteration, recorded for a fused batch (several
+// solves advanced by shared launches): the arguments of the solve's own
+// launch, its grid and, for element kernels, that grid's die stride.
+enum class OpType { kAx, kAxDirect, kMinv, kTransfer, kVec, kCoarse };
+struct BatchOp {
+  OpType type = OpType::kVec;
+  int N = 0, Nc = 0;
+  Kind kind = Kind::F64;
+  bool kap = false, restrict_op = false;
+  int variant = 0;                 // operator variant (kAx)
+  VecOp vop = VecOp::kUpdate;
+  bool fp32 = false, flag = false;
+  ElemArgs ea;
+  TransferArgs ta;
+  VecArgs va;
+  int nb = 0, per = 0;
+};
+
+// Whether two recorded launches can share one batched launch (the same
+// kernel; an operator variant without a batched form never shares).
+bool same_launch(const BatchOp& a, const BatchOp& b) {
+  if (a.type != b.type) return false;
+  switch (a.type) {
+    case OpType::kAx: return a.N == b.N && a.kind == b.kind && a.kap == b.kap && a.variant == b.variant;
+    case OpType::kAxDirect: return false;
+    case OpType::kMinv: return a.N == b.N && a.kind == b.kind;
+    case OpType::kTransfer:
+      return a.N == b.N && a.Nc == b.Nc && a.kind == b.kind && a.restrict_op == b.restrict_op;
+    case OpType::kVec: return a.vop == b.vop && a.fp32 == b.fp32 && a.flag == b.flag;
+    case OpType::kCoarse: return a.N == b.N && a.kind == b.kind;
+  }
+  return false;
 }
 
 class Solver {
@@ -324,37 +378,21 @@ class Solver {
   void launch_iterations(int every) { run_iterations(w_->xw.as<double>(), every); }
   hipStream_t stream() const { return s_; }
 
-  // Batched coarse mode: one outer iteration captured as two graphs, the part
-  // before the coarsest-level solve and the part after it; the caller runs
-  // the coarsest-level solves of all members of a batch together in between
-  // (reading coarse_rhs(), writing coarse_sol()).  Only p-multigrid has one.
-  void capture_split() {
-    Work& w = *w_;
-    if (w.graph_pre && w.graph_post) return;   // captured for this setup already
-    w.drop_split();
-    split_count_ = 0;
-    splitting_ = true;
-    hipGraph_t g = nullptr;
-    IPDG_HIP(hipStreamBeginCapture(s_, hipStreamCaptureModeThreadLocal));
+  // Fused batch: one outer iteration's launches recorded into ops instead of
+  // issued (the coarsest-level solve as one kCoarse op whose right-hand side
+  // and solution buffers coarse_rhs() and coarse_sol() name).
+  void record_iteration(std::vector<BatchOp>& ops) {
+    rec_ = &ops;
     try {
-      iteration(w.xw.as<double>());
+      iteration(w_->xw.as<double>());
     } catch (...) {
-      splitting_ = false;
-      (void)hipStreamEndCapture(s_, &g);
-      if (g) (void)hipGraphDestroy(g);
-      w.drop_split();
+      rec_ = nullptr;
       throw;
     }
-    splitting_ = false;
-    IPDG_HIP(hipStreamEndCapture(s_, &g));
-    hipError_t e = hipGraphInstantiate(&w.graph_post, g, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(g);
-    IPDG_HIP(e);
-    if (split_count_ != 1 || !w.graph_pre) {
-      w.drop_split();
-      throw Error(IPDG_EUNSUPPORTED, "an outer iteration does not reach the coarsest level exactly once");
-    }
+    rec_ = nullptr;
   }
+  const CGScal* scal_dev() const { return w_->scal.as<CGScal>(); }
+  void set_host_scal(const CGScal& c) { *w_->host_scal = c; }
   unsigned long long setup_id() const { return w_->setup_id; }
   // Iteration cap of the coarsest-level Jacobi-PCG: the option, or when it is
   // negative max(20, ceil(0.414 sqrt(K))).  Jacobi-PCG needs iterations
@@ -365,11 +403,9 @@ class Solver {
     if (o_.coarse_max_iters >= 0) return o_.coarse_max_iters;
     return std::max(20, (int)std::ceil(0.414 * std::sqrt((double)K_)));
   }
-  void launch_pre() { IPDG_HIP(hipGraphLaunch(w_->graph_pre, s_)); }
-  void launch_post() { IPDG_HIP(hipGraphLaunch(w_->graph_post, s_)); }
   const Level& coarsest() const { return w_->lv.back(); }
-  const void* coarse_rhs() const { return w_->split_f; }
-  void* coarse_sol() const { return w_->split_x; }
+  const void* coarse_rhs() const { return w_->coarse_f; }
+  void* coarse_sol() const { return w_->coarse_x; }
   ipdg_mesh_s* mesh() const { return m_; }
   double lambda() const { return lambda_; }
   const int* done_flag() const { return outer_done(); }
@@ -394,7 +430,181 @@ class Solver {
       // coarse_max_iters < 0: the automatic cap (coarse_cap())
       if (o_.coarse_persistent != 0 && o_.coarse_persistent != 1)
         throw Error(IPDG_EINVAL, "coarse_persistent must be 0 or 1");
+      if (o_.coarse_amg != 0 && o_.coarse_amg != 1) throw Error(IPDG_EINVAL, "coarse_amg must be 0 or 1");
+      if (o_.coarse_amg == 1) {
+        if (o_.degrees[o_.n_levels - 1] != 1)
+          throw Error(IPDG_EINVAL, "the algebraic levels start below degree 1: the last p-level must be 1");
+        if (o_.amg_coarse_size < 1) throw Error(IPDG_EINVAL, "amg_coarse_size < 1");
+        if (o_.amg_coarse_size > kAmgMaxCoarse)
+          throw Error(IPDG_EINVAL, "amg_coarse_size above " + std::to_string(kAmgMaxCoarse));
+        if (o_.amg_cycles < 1) throw Error(IPDG_EINVAL, "amg_cycles < 1");
+      }
     }
+  }
+
+  // Launch helpers: issue the launch on the solver's stream, or, while an
+  // iteration is being recorded, append it to the recorded ops.
+  void op_ax(int N, Kind k, const ElemArgs& a) {
+    if (!rec_) {
+      IPDG_HIP(ax(N, k, a, s_));
+      return;
+    }
+    BatchOp o;
+    o.N = N;
+    o.kind = k;
+    o.ea = a;
+    o.kap = a.kap != nullptr;
+    const int v = ax_variant(N, k == Kind::F32);
+    o.variant = v;
+    if (!ax_batch_variant(v)) {
+      o.type = OpType::kAxDirect;   // the LDS-staged variants have no batched form
+    } else {
+      o.type = OpType::kAx;
+      if (v == kAxCoop) o.nb = xcd_grid((a.K + kCoopTileElems - 1) / kCoopTileElems, o.per);
+      else o.nb = xcd_grid(elem_tiles(a.K), o.per);
+    }
+    rec_->push_back(o);
+  }
+  void op_minv(int N, Kind k, const ElemArgs& a) {
+    if (!rec_) {
+      IPDG_HIP(minv(N, k, a, s_));
+      return;
+    }
+    BatchOp o;
+    o.type = OpType::kMinv;
+    o.N = N;
+    o.kind = k;
+    o.ea = a;
+    o.nb = xcd_grid(elem_tiles(a.K), o.per);
+    rec_->push_back(o);
+  }
+  void op_transfer(bool restrict_op, int Nf, int Nc, Kind k, const TransferArgs& t) {
+    if (!rec_) {
+      IPDG_HIP(restrict_op ? restrict_(Nf, Nc, k, t, s_) : prolong(Nf, Nc, k, t, s_));
+      return;
+    }
+    BatchOp o;
+    o.type = OpType::kTransfer;
+    o.N = Nf;
+    o.Nc = Nc;
+    o.kind = k;
+    o.restrict_op = restrict_op;
+    o.ta = t;
+    o.nb = xcd_grid(elem_tiles(t.K), o.per);
+    rec_->push_back(o);
+  }
+  void push_vec(VecOp op, bool fp32, bool flag, const VecArgs& v, int nb) {
+    BatchOp o;
+    o.type = OpType::kVec;
+    o.vop = op;
+    o.fp32 = fp32;
+    o.flag = flag;
+    o.va = v;
+    o.nb = nb;
+    rec_->push_back(o);
+  }
+  void op_finalize(double* partials, int nparts, int nslots, CGScal* sc, int op) {
+    if (!rec_) {
+      IPDG_HIP(finalize(partials, nparts, nslots, sc, op, s_));
+      return;
+    }
+    VecArgs v;
+    v.a = partials;
+    v.nparts = nparts;
+    v.nslots = nslots;
+    v.scw = sc;
+    v.op = op;
+    push_vec(VecOp::kFinalize, false, false, v, 1);
+  }
+  void op_convert(bool to_fp32, void* dst, const void* src, size_t n, const int* skip) {
+    if (!rec_) {
+      IPDG_HIP(convert(to_fp32, dst, src, n, skip, s_));
+      return;
+    }
+    VecArgs v;
+    v.x = dst;
+    v.a = src;
+    v.n = n;
+    v.skip = skip;
+    push_vec(VecOp::kConvert, false, to_fp32, v, flat_grid(n));
+  }
+  void op_update(bool fp32z, bool jac, double* x, double* r, const double* p, const double* Ap,
+                 const double* dinv, void* z, const CGScal* sc, size_t n, double* partials) {
+    if (!rec_) {
+      IPDG_HIP(cg_update(fp32z, jac, x, r, p, Ap, dinv, z, sc, n, partials, s_));
+      return;
+    }
+    VecArgs v;
+    v.x = x;
+    v.y = r;
+    v.a = p;
+    v.b = Ap;
+    v.c = dinv;
+    v.z = z;
+    v.sc = sc;
+    v.n = n;
+    v.partials = partials;
+    push_vec(VecOp::kUpdate, fp32z, jac, v, flat_grid(n));
+  }
+  void op_dots_rz(bool fp32z, const double* r, const void* z, const double* Ap, const CGScal* sc, size_t n,
+                  double* partials) {
+    if (!rec_) {
+      IPDG_HIP(dots_rz(fp32z, r, z, Ap, sc, n, partials, s_));
+      return;
+    }
+    VecArgs v;
+    v.a = r;
+    v.b = z;
+    v.c = Ap;
+    v.sc = sc;
+    v.n = n;
+    v.partials = partials;
+    push_vec(VecOp::kDotsRz, fp32z, false, v, flat_grid(n));
+  }
+  void op_pupdate(bool fp32z, double* p, const void* z, const CGScal* sc, size_t n) {
+    if (!rec_) {
+      IPDG_HIP(pupdate(fp32z, p, z, sc, n, s_));
+      return;
+    }
+    VecArgs v;
+    v.x = p;
+    v.a = z;
+    v.sc = sc;
+    v.n = n;
+    push_vec(VecOp::kPupdate, fp32z, false, v, flat_grid(n));
+  }
+  void op_jacobi(bool fp32z, const double* r, const double* dinv, void* z, size_t n) {
+    if (!rec_) {
+      IPDG_HIP(jacobi(fp32z, r, dinv, z, n, s_));
+      return;
+    }
+    VecArgs v;
+    v.a = r;
+    v.b = dinv;
+    v.z = z;
+    v.n = n;
+    push_vec(VecOp::kJacobi, fp32z, false, v, flat_grid(n));
+  }
+  void op_cheb(bool fp32, int mode, const void* f, const void* t, const void* dinv, void* z, void* d, void* r,
+               double c0, double c1, double c2, size_t n, const int* skip) {
+    if (!rec_) {
+      IPDG_HIP(cheb(fp32, mode, f, t, dinv, z, d, r, c0, c1, c2, n, skip, s_));
+      return;
+    }
+    VecArgs v;
+    v.mode = mode;
+    v.a = f;
+    v.b = t;
+    v.c = dinv;
+    v.z = z;
+    v.x = d;
+    v.y = r;
+    v.c0 = c0;
+    v.c1 = c1;
+    v.c2 = c2;
+    v.n = n;
+    v.skip = skip;
+    push_vec(VecOp::kCheb, fp32, false, v, flat_grid(n));
   }
 
   bool same_setup() const {
@@ -406,7 +616,8 @@ class Solver {
     if (o_.pc == IPDG_PC_PMG) {
       if (w.nlev != o_.n_levels || w.cheb_degree != o_.cheb_degree || w.cheb_lo != o_.cheb_lo ||
           w.cheb_hi != o_.cheb_hi || w.coarse_max != o_.coarse_max_iters ||
-          w.coarse_tol != o_.coarse_tol || w.rho_steps != o_.rho_steps)
+          w.coarse_tol != o_.coarse_tol || w.rho_steps != o_.rho_steps || w.coarse_amg != o_.coarse_amg ||
+          (o_.coarse_amg && (w.amg_coarse_size != o_.amg_coarse_size || w.amg_cycles != o_.amg_cycles)))
         return false;
       for (int l = 0; l < o_.n_levels; ++l)
         if (w.degrees[l] != o_.degrees[l] || w.rho_in[l] != o_.rho[l]) return false;
@@ -424,6 +635,7 @@ class Solver {
     w.drop_graph();
     w.setup_id = next_setup_id();
     w.lv.clear();
+    w.amg.reset();
     w.n = n_;
     w.xw.ensure(n_ * 8);
     w.r.ensure(n_ * 8);
@@ -477,6 +689,9 @@ class Solver {
     w.coarse_max = o_.coarse_max_iters;
     w.coarse_tol = o_.coarse_tol;
     w.rho_steps = o_.rho_steps;
+    w.coarse_amg = o_.pc == IPDG_PC_PMG ? o_.coarse_amg : 0;
+    w.amg_coarse_size = o_.amg_coarse_size;
+    w.amg_cycles = o_.amg_cycles;
     for (int l = 0; l < IPDG_MAX_LEVELS; ++l) {
       w.degrees[l] = o_.degrees[l];
       w.rho_in[l] = o_.rho[l];
@@ -535,7 +750,186 @@ class Solver {
     w.cbar.ensure(8 * sizeof(int));
     IPDG_HIP(zero_ints(w.cbar.get(), 8, s_));
     w.coarse_grid = -1;
+    if (o_.coarse_amg == 1) setup_amg();
     select_coarse();
+  }
+
+  // The algebraic levels (see AmgSet): the element-level matrix P0^T A P0
+  // read off the degree-1 operator, then aggregation, Galerkin products and
+  // Gershgorin bounds until at most amg_coarse_size unknowns remain (or 12
+  // levels, counting the degree-1 level, or aggregation stalls); the
+  // coarsest matrix is inverted.
+  void setup_amg() {
+    Work& w = *w_;
+    const Level& v = w.lv.back();
+    const HostMesh& hm = m_->host;
+    const int K = K_;
+    std::unique_ptr<AmgSet> A(new AmgSet);
+    // element graph through interior faces
+    std::vector<int> gptr(K + 1, 0), gadj;
+    for (int e = 0; e < K; ++e) {
+      int nb[3], c = 0;
+      for (int f = 0; f < 3; ++f) {
+        const int o = hm.EToE[3 * e + f];
+        if (o >= 0 && o != e) nb[c++] = o;
+      }
+      std::sort(nb, nb + c);
+      c = int(std::unique(nb, nb + c) - nb);
+      for (int k = 0; k < c; ++k) gadj.push_back(nb[k]);
+      gptr[e + 1] = int(gadj.size());
+    }
+    const Csr AE = element_matrix(v, gptr, gadj);
+    A->sizes = {int(v.n), K};
+    std::vector<Csr> mats{AE};
+    std::vector<std::vector<int>> aggs;
+    Csr cur = AE;
+    for (;;) {
+      if (cur.n <= o_.amg_coarse_size || int(A->sizes.size()) >= kAmgMaxLevels) break;
+      std::vector<int> agg;
+      const int na = amg_aggregate(gptr, gadj, agg);
+      if (na == cur.n) break;
+      std::vector<int> cptr, cadj;
+      amg_coarse_graph(gptr, gadj, agg, na, cptr, cadj);
+      cur = amg_galerkin(cur, agg, na);
+      aggs.push_back(std::move(agg));
+      gptr.swap(cptr);
+      gadj.swap(cadj);
+      mats.push_back(cur);
+      A->sizes.push_back(na);
+    }
+    const int L = int(A->sizes.size());
+    const bool f32 = v.fp32;
+    const size_t w8 = f32 ? 4 : 8;
+    auto upload = [&](DevBuf& b, const void* src, size_t bytes) {
+      b.ensure(std::max<size_t>(bytes, 16));
+      if (bytes) IPDG_HIP(hipMemcpyAsync(b.get(), src, bytes, hipMemcpyHostToDevice, s_));
+    };
+    auto upload_t = [&](DevBuf& b, const std::vector<double>& src) {
+      if (f32) {
+        std::vector<float> t(src.begin(), src.end());
+        upload(b, t.data(), t.size() * 4);
+        IPDG_HIP(hipStreamSynchronize(s_));
+      } else {
+        upload(b, src.data(), src.size() * 8);
+      }
+    };
+    A->lv.resize(L);
+    for (int l = 1; l < L; ++l) {
+      AmgLevel& a = A->lv[l];
+      const Csr& M = mats[l - 1];
+      a.n = M.n;
+      a.f.ensure(a.n * w8);
+      a.z.ensure(a.n * w8);
+      if (l == L - 1) continue;   // the coarsest level is solved by its inverse
+      a.rho = amg_gershgorin(M);
+      std::vector<double> dinv(M.n, 0.0);
+      for (int i = 0; i < M.n; ++i)
+        for (int k = M.ptr[i]; k < M.ptr[i + 1]; ++k)
+          if (M.col[k] == i) dinv[i] = 1.0 / M.val[k];
+      upload(a.ptr, M.ptr.data(), M.ptr.size() * 4);
+      upload(a.col, M.col.data(), M.col.size() * 4);
+      upload_t(a.val, M.val);
+      upload_t(a.dinv, dinv);
+      for (DevBuf* b : {&a.t, &a.r, &a.d}) b->ensure(a.n * w8);
+    }
+    // transfers: degree-1 nodes -> elements (node j of element j / Np), then
+    // the aggregates
+    A->xf.resize(L - 1);
+    for (int l = 0; l + 1 < L; ++l) {
+      AmgXfer& x = A->xf[l];
+      x.n = A->sizes[l];
+      x.nc = A->sizes[l + 1];
+      std::vector<int> agg(x.n);
+      if (l == 0) {
+        for (int j = 0; j < x.n; ++j) agg[j] = j / v.Np;
+      } else {
+        agg = aggs[l - 1];
+      }
+      std::vector<int> mptr(x.nc + 1, 0), mem(x.n);
+      for (int j = 0; j < x.n; ++j) ++mptr[agg[j] + 1];
+      for (int i = 0; i < x.nc; ++i) mptr[i + 1] += mptr[i];
+      std::vector<int> fill(mptr.begin(), mptr.end() - 1);
+      for (int j = 0; j < x.n; ++j) mem[fill[agg[j]]++] = j;   // members ascending
+      upload(x.agg, agg.data(), agg.size() * 4);
+      upload(x.mptr, mptr.data(), mptr.size() * 4);
+      upload(x.mem, mem.data(), mem.size() * 4);
+      IPDG_HIP(hipStreamSynchronize(s_));
+    }
+    std::vector<double> inv;
+    if (!amg_spd_inverse(mats.back(), inv))
+      throw Error(IPDG_EUNSUPPORTED, "the coarsest algebraic level is not positive definite (a pure Neumann "
+                                     "problem with lambda = 0 has constants in its null space)");
+    upload_t(A->inv, inv);
+    if (o_.amg_cycles > 1)
+      for (DevBuf* b : {&A->t0, &A->res0, &A->z0}) b->ensure(v.n * w8);
+    IPDG_HIP(hipStreamSynchronize(s_));
+    w.amg = std::move(A);
+  }
+
+  // P0^T A P0 of the degree-1 operator (P0: one value per element to its
+  // nodes), read off operator applications: elements whose closed
+  // neighbourhoods are disjoint (a distance-2 colouring) are probed together
+  // with x = 1 on their nodes; A x on element e' of the neighbourhood of a
+  // probed element e, summed over the nodes of e', is entry (e', e).
+  Csr element_matrix(const Level& v, const std::vector<int>& gptr, const std::vector<int>& gadj) {
+    const int K = K_, Np = v.Np;
+    std::vector<int> color(K, -1), mark;
+    int ncol = 0;
+    for (int e = 0; e < K; ++e) {
+      mark.clear();
+      for (int k = gptr[e]; k < gptr[e + 1]; ++k) {
+        const int a = gadj[k];
+        if (color[a] >= 0) mark.push_back(color[a]);
+        for (int q = gptr[a]; q < gptr[a + 1]; ++q)
+          if (color[gadj[q]] >= 0) mark.push_back(color[gadj[q]]);
+      }
+      std::sort(mark.begin(), mark.end());
+      int c = 0;
+      for (int m : mark)
+        if (m == c) ++c;
+        else if (m > c) break;
+      color[e] = c;
+      ncol = std::max(ncol, c + 1);
+    }
+    const size_t n = v.n;
+    DevBuf xb(n * 8), yb(n * 8);
+    std::vector<double> x(n), y(n);
+    std::vector<std::vector<std::pair<int, double>>> rows(K);
+    ElemArgs a = elem_args(m_, 1, Kind::F64, lambda_, v.ctau);
+    a.x = xb.get();
+    a.y = yb.get();
+    for (int c = 0; c < ncol; ++c) {
+      std::fill(x.begin(), x.end(), 0.0);
+      for (int e = 0; e < K; ++e)
+        if (color[e] == c)
+          for (int k = 0; k < Np; ++k) x[(size_t)e * Np + k] = 1.0;
+      IPDG_HIP(hipMemcpyAsync(xb.get(), x.data(), n * 8, hipMemcpyHostToDevice, s_));
+      IPDG_HIP(ax(1, Kind::F64, a, s_));
+      IPDG_HIP(hipMemcpyAsync(y.data(), yb.get(), n * 8, hipMemcpyDeviceToHost, s_));
+      IPDG_HIP(hipStreamSynchronize(s_));
+      for (int e = 0; e < K; ++e) {
+        if (color[e] != c) continue;
+        auto put = [&](int r) {
+          double sum = 0.0;
+          for (int k = 0; k < Np; ++k) sum += y[(size_t)r * Np + k];
+          rows[r].emplace_back(e, sum);
+        };
+        put(e);
+        for (int k = gptr[e]; k < gptr[e + 1]; ++k) put(gadj[k]);
+      }
+    }
+    Csr M;
+    M.n = K;
+    M.ptr.assign(K + 1, 0);
+    for (int r = 0; r < K; ++r) {
+      std::sort(rows[r].begin(), rows[r].end());
+      for (const auto& cv : rows[r]) {
+        M.col.push_back(cv.first);
+        M.val.push_back(cv.second);
+      }
+      M.ptr[r + 1] = int(M.col.size());
+    }
+    return M;
   }
 
   // persistent single-launch coarse solve or ordinary launches; a change
@@ -544,7 +938,7 @@ class Solver {
     Work& w = *w_;
     if (o_.pc != IPDG_PC_PMG || w.lv.empty()) return;
     const Level& cl = w.lv.back();
-    const int g = (persistent_ && o_.coarse_persistent == 1) ? coarse_pcg_grid(cl.N, cl.kind, K_) : 0;
+    const int g = (persistent_ && o_.coarse_persistent == 1 && !w.amg) ? coarse_pcg_grid(cl.N, cl.kind, K_) : 0;
     if (g != w.coarse_grid) {
       w.drop_graph();
       w.coarse_grid = g;
@@ -641,7 +1035,7 @@ class Solver {
     switch (o_.pc) {
       case IPDG_PC_NONE:
       case IPDG_PC_JACOBI:
-        IPDG_HIP(jacobi(mixed_, w.r.as<double>(), w.dinv64.as<double>(), w.z.get(), n_, s_));
+        op_jacobi(mixed_, w.r.as<double>(), w.dinv64.as<double>(), w.z.get(), n_);
         break;
       case IPDG_PC_BLOCK_MASS: {
         const Kind k = mixed_ ? Kind::F32_IN64 : Kind::F64;
@@ -649,12 +1043,12 @@ class Solver {
         a.x = w.r.get();
         a.y = w.z.get();
         a.skip = outer_done();
-        IPDG_HIP(minv(N_, k, a, s_));
+        op_minv(N_, k, a);
         break;
       }
       case IPDG_PC_PMG: {
         Level& v0 = w.lv[0];
-        if (mixed_) IPDG_HIP(convert(true, v0.f.get(), w.r.get(), n_, outer_done(), s_));
+        if (mixed_) op_convert(true, v0.f.get(), w.r.get(), n_, outer_done());
         vcycle(0, mixed_ ? v0.f.get() : w.r.get(), w.z.get());
         break;
       }
@@ -666,27 +1060,89 @@ class Solver {
     a.x = x;
     a.y = y;
     a.skip = outer_done();
-    IPDG_HIP(ax(v.N, v.kind, a, s_));
+    op_ax(v.N, v.kind, a);
   }
 
-  void smooth(const Level& v, const void* f, void* z, bool from_zero) {
-    const double lo = o_.cheb_lo * v.rho, hi = o_.cheb_hi * v.rho;
+  // Chebyshev smoothing of D^-1 A over [lo rho, hi rho] (Saad Alg. 12.1),
+  // from zero or from z; apply(x, y) is y = A x on the level
+  template <typename Apply>
+  void cheb_smooth(bool fp32, double rho_l, size_t n, const void* dinv, void* d, void* r, void* t, const void* f,
+                   void* z, bool from_zero, Apply apply) {
+    const double lo = o_.cheb_lo * rho_l, hi = o_.cheb_hi * rho_l;
     const double theta = 0.5 * (hi + lo), delta = 0.5 * (hi - lo), sigma = theta / delta;
     double rho = 1.0 / sigma;
     if (from_zero) {
-      IPDG_HIP(cheb(v.fp32, 0, f, nullptr, v.dinv(), z, v.d.get(), v.r.get(), 1.0 / theta, 0, 0, v.n,
-                    outer_done(), s_));
+      op_cheb(fp32, 0, f, nullptr, dinv, z, d, r, 1.0 / theta, 0, 0, n, outer_done());
     } else {
-      level_ax(v, z, v.t.get());
-      IPDG_HIP(cheb(v.fp32, 1, f, v.t.get(), v.dinv(), z, v.d.get(), v.r.get(), 1.0 / theta, 0, 0, v.n,
-                    outer_done(), s_));
+      apply(z, t);
+      op_cheb(fp32, 1, f, t, dinv, z, d, r, 1.0 / theta, 0, 0, n, outer_done());
     }
     for (int k = 1; k < o_.cheb_degree; ++k) {
       const double rho_new = 1.0 / (2.0 * sigma - rho);
-      level_ax(v, v.d.get(), v.t.get());
-      IPDG_HIP(cheb(v.fp32, 2, nullptr, v.t.get(), v.dinv(), z, v.d.get(), v.r.get(), 0,
-                    rho_new * rho, 2.0 * rho_new / delta, v.n, outer_done(), s_));
+      apply(d, t);
+      op_cheb(fp32, 2, nullptr, t, dinv, z, d, r, 0, rho_new * rho, 2.0 * rho_new / delta, n, outer_done());
       rho = rho_new;
+    }
+  }
+
+  void smooth(const Level& v, const void* f, void* z, bool from_zero) {
+    cheb_smooth(v.fp32, v.rho, v.n, v.dinv(), v.d.get(), v.r.get(), v.t.get(), f, z, from_zero,
+                [&](const void* x, void* y) { level_ax(v, x, y); });
+  }
+
+  void amg_spmv_level(const AmgLevel& a, bool fp32, const void* x, void* y) {
+    IPDG_HIP(amg_spmv(fp32, a.ptr.as<int>(), a.col.as<int>(), a.val.get(), x, y, a.n, outer_done(), s_));
+  }
+
+  // One V-cycle of the algebraic hierarchy from zero on level l (0: the
+  // degree-1 level), the same smoother before and after the coarse
+  // correction, the coarsest level solved by its inverse.
+  void amg_cycle(int l, const void* f, void* z) {
+    AmgSet& A = *w_->amg;
+    const Level& v = w_->lv.back();
+    const bool f32 = v.fp32;
+    const int L = int(A.sizes.size());
+    if (l == L - 1) {
+      IPDG_HIP(amg_dense(f32, A.inv.get(), f, z, A.sizes[l], outer_done(), s_));
+      return;
+    }
+    const void* t;
+    if (l == 0) {
+      smooth(v, f, z, true);
+      level_ax(v, z, v.t.get());
+      t = v.t.get();
+    } else {
+      AmgLevel& a = A.lv[l];
+      cheb_smooth(f32, a.rho, a.n, a.dinv.get(), a.d.get(), a.r.get(), a.t.get(), f, z, true,
+                  [&](const void* x, void* y) { amg_spmv_level(a, f32, x, y); });
+      amg_spmv_level(a, f32, z, a.t.get());
+      t = a.t.get();
+    }
+    AmgLevel& c = A.lv[l + 1];
+    const AmgXfer& x = A.xf[l];
+    IPDG_HIP(amg_restrict(f32, x.mptr.as<int>(), x.mem.as<int>(), f, t, c.f.get(), x.nc, outer_done(), s_));
+    amg_cycle(l + 1, c.f.get(), c.z.get());
+    IPDG_HIP(amg_prolong(f32, x.agg.as<int>(), c.z.get(), z, x.n, outer_done(), s_));
+    if (l == 0) {
+      smooth(v, f, z, false);
+    } else {
+      AmgLevel& a = A.lv[l];
+      cheb_smooth(f32, a.rho, a.n, a.dinv.get(), a.d.get(), a.r.get(), a.t.get(), f, z, false,
+                  [&](const void* x, void* y) { amg_spmv_level(a, f32, x, y); });
+    }
+  }
+
+  // amg_cycles V-cycles on the degree-1 level: the first from zero, each
+  // further one on the residual of the current x (iterative refinement)
+  void amg_solve(const void* f, void* x) {
+    AmgSet& A = *w_->amg;
+    const Level& v = w_->lv.back();
+    amg_cycle(0, f, x);
+    for (int c = 1; c < o_.amg_cycles; ++c) {
+      level_ax(v, x, A.t0.get());
+      IPDG_HIP(amg_sub(v.fp32, f, A.t0.get(), A.res0.get(), v.n, outer_done(), s_));
+      amg_cycle(0, A.res0.get(), A.z0.get());
+      IPDG_HIP(amg_add(v.fp32, x, A.z0.get(), v.n, outer_done(), s_));
     }
   }
 
@@ -707,7 +1163,7 @@ class Solver {
     ta.P = v.P;
     ta.K = K_;
     ta.skip = outer_done();
-    IPDG_HIP(restrict_(v.N, c.N, v.kind, ta, s_));
+    op_transfer(true, v.N, c.N, v.kind, ta);
     vcycle(l + 1, c.f.get(), c.z.get());
     TransferArgs tp;
     tp.coarse = c.z.get();
@@ -715,27 +1171,27 @@ class Solver {
     tp.P = v.P;
     tp.K = K_;
     tp.skip = outer_done();
-    IPDG_HIP(prolong(v.N, c.N, v.kind, tp, s_));
+    op_transfer(false, v.N, c.N, v.kind, tp);
     smooth(v, f, z, false);
   }
 
   // Jacobi-PCG from zero on the coarsest level, coarse_max iterations at most
   void coarse_solve(Level& v, const void* f, void* x) {
     Work& w = *w_;
-    if (splitting_) {
-      // batched coarse mode: close the graph of the part before, open the
-      // one of the part after; the batch solves this level in between
-      w.split_f = f;
-      w.split_x = x;
-      ++split_count_;
-      hipGraph_t g = nullptr;
-      IPDG_HIP(hipStreamEndCapture(s_, &g));
-      if (w.graph_pre) (void)hipGraphExecDestroy(w.graph_pre);
-      w.graph_pre = nullptr;
-      hipError_t e = hipGraphInstantiate(&w.graph_pre, g, nullptr, nullptr, 0);
-      (void)hipGraphDestroy(g);
-      IPDG_HIP(e);
-      IPDG_HIP(hipStreamBeginCapture(s_, hipStreamCaptureModeThreadLocal));
+    if (w.amg) {
+      if (rec_) throw Error(IPDG_EUNSUPPORTED, "a fused batch solves its coarsest levels by Jacobi-PCG");
+      amg_solve(f, x);
+      return;
+    }
+    if (rec_) {
+      // fused batch: the batch solves this level for all its solves at once
+      w.coarse_f = f;
+      w.coarse_x = x;
+      BatchOp o;
+      o.type = OpType::kCoarse;
+      o.N = v.N;
+      o.kind = v.kind;
+      rec_->push_back(o);
       return;
     }
     if (w.coarse_grid > 0) {
@@ -842,33 +1298,33 @@ class Solver {
     // rounded to FP32, the product widened back, (p, A p) summed in FP64),
     // with reliable updates of the residual.
     if (op32_) {
-      IPDG_HIP(convert(true, w.p32.get(), w.p.get(), n_, outer_done(), s_));
+      op_convert(true, w.p32.get(), w.p.get(), n_, outer_done());
       ElemArgs a = elem_args(m_, N_, Kind::F32, lambda_, ctau_);
       a.x = w.p32.get();
       a.y = w.Ap32.get();
       a.partials = w.partials.as<double>();
       a.skip = outer_done();
-      IPDG_HIP(ax(N_, Kind::F32, a, s_));
-      IPDG_HIP(finalize(w.partials.as<double>(), ax_partials(N_, true, K_), 1, sc, kFinAlpha, s_));
-      IPDG_HIP(convert(false, w.Ap.get(), w.Ap32.get(), n_, outer_done(), s_));
+      op_ax(N_, Kind::F32, a);
+      op_finalize(w.partials.as<double>(), ax_partials(N_, true, K_), 1, sc, kFinAlpha);
+      op_convert(false, w.Ap.get(), w.Ap32.get(), n_, outer_done());
     } else {
       ElemArgs a = elem_args(m_, N_, Kind::F64, lambda_, ctau_);
       a.x = w.p.get();
       a.y = w.Ap.get();
       a.partials = w.partials.as<double>();
       a.skip = outer_done();
-      IPDG_HIP(ax(N_, Kind::F64, a, s_));
-      IPDG_HIP(finalize(w.partials.as<double>(), ax_partials(N_, false, K_), 1, sc, kFinAlpha, s_));
+      op_ax(N_, Kind::F64, a);
+      op_finalize(w.partials.as<double>(), ax_partials(N_, false, K_), 1, sc, kFinAlpha);
     }
     const bool jac = o_.pc == IPDG_PC_JACOBI || o_.pc == IPDG_PC_NONE;
-    IPDG_HIP(cg_update(mixed_, jac, x, w.r.as<double>(), w.p.as<double>(), w.Ap.as<double>(), w.dinv64.as<double>(),
-                       w.z.get(), sc, n_, w.partials.as<double>(), s_));
+    op_update(mixed_, jac, x, w.r.as<double>(), w.p.as<double>(), w.Ap.as<double>(), w.dinv64.as<double>(),
+              w.z.get(), sc, n_, w.partials.as<double>());
     if (!jac) {
       precond();
-      IPDG_HIP(dots_rz(mixed_, w.r.as<double>(), w.z.get(), w.Ap.as<double>(), sc, n_, w.partials.as<double>(), s_));
+      op_dots_rz(mixed_, w.r.as<double>(), w.z.get(), w.Ap.as<double>(), sc, n_, w.partials.as<double>());
     }
-    IPDG_HIP(finalize(w.partials.as<double>(), flat_grid(n_), 3, sc, kFinBeta, s_));
-    IPDG_HIP(pupdate(mixed_, w.p.as<double>(), w.z.get(), sc, n_, s_));
+    op_finalize(w.partials.as<double>(), flat_grid(n_), 3, sc, kFinBeta);
+    op_pupdate(mixed_, w.p.as<double>(), w.z.get(), sc, n_);
   }
 
   // status of the persistent coarse solve: [0] iterations, [1] barrier
@@ -876,6 +1332,7 @@ class Solver {
   int coarse_status() {
     Work& w = *w_;
     if (o_.pc != IPDG_PC_PMG || w.lv.empty()) return -1;
+    if (w.amg) return 0;
     if (w.coarse_grid == 0) {
       CGScal c{};
       IPDG_HIP(hipMemcpyAsync(&c, w.cscal.get(), sizeof(c), hipMemcpyDeviceToHost, s_));
@@ -894,6 +1351,10 @@ class Solver {
     if (!info) return;
     std::memset(info, 0, sizeof(*info));
     info->coarse_iters = citers;
+    if (w_->amg) {
+      info->amg_levels = int(w_->amg->sizes.size());
+      for (int l = 0; l < info->amg_levels && l < IPDG_AMG_MAX_LEVELS; ++l) info->amg_n[l] = w_->amg->sizes[l];
+    }
     info->iters = iters;
     info->relres = relres;
     info->restarts = restarts;
@@ -915,8 +1376,7 @@ class Solver {
   bool mixed_ = false, flexible_ = false;
   bool op32_ = false;                // FP32 outer operator (IPDG_PREC_FP32_OPERATOR)
   double drop_ = 0.0;                // reliable-update factor in use
-  bool splitting_ = false;           // capturing the two halves of a split iteration
-  int split_count_ = 0;
+  std::vector<BatchOp>* rec_ = nullptr;   // recording an iteration (fused batch)
 };
 
 }  // namespace
@@ -943,37 +1403,25 @@ ipdg_status precond_apply(ipdg_mesh_s* m, double lambda, double tau, const ipdg_
 
 namespace {
 
-// The coarsest levels of a batch's solves, concatenated (CoarseBatchArgs),
-// with the captured graph of one batched coarse solve and the events that
-// order it against the solves' own streams.
+// The coarsest levels of a batch's solves, concatenated (CoarseBatchArgs).
 struct CoarseBatchSet {
   DevBuf ent, tile_solve, x, p, u, dinv, r0, r1, w0, w1, s0, s1, geo, conn, kap, partials, sc;
   CoarseBatchArgs a;
+  int N = 0;
+  Kind kind = Kind::F64;
   int max_iters = 0;               // the largest member cap: coarse launches per solve
-  hipStream_t stream = nullptr;
-  hipGraphExec_t graph = nullptr;
-  std::vector<hipEvent_t> ev;
-  hipEvent_t ev_done = nullptr;
-  ~CoarseBatchSet() {
-    if (graph) (void)hipGraphExecDestroy(graph);
-    for (hipEvent_t e : ev)
-      if (e) (void)hipEventDestroy(e);
-    if (ev_done) (void)hipEventDestroy(ev_done);
-    if (stream) (void)hipStreamDestroy(stream);
-  }
 };
 
-// IPDG_BATCH_COARSE=separate keeps every solve's coarsest level on its own
-// launches (the fused form is the default).
-bool batch_coarse_fused() {
-  const char* v = std::getenv("IPDG_BATCH_COARSE");
+// IPDG_BATCH=separate advances every solve of a batch on its own stream with
+// its own launches (the fused form is the default).
+bool batch_fused() {
+  const char* v = std::getenv("IPDG_BATCH");
   return !(v && std::strcmp(v, "separate") == 0);
 }
 
-// Null when the solves' coarsest levels differ in degree or precision (the
-// caller then keeps them separate).
+// Null when the solves' coarsest levels differ in degree or precision.
 std::unique_ptr<CoarseBatchSet> make_coarse_batch(std::vector<std::unique_ptr<Solver>>& sv,
-                                                  const ipdg_solve_opts& o) {
+                                                  const ipdg_solve_opts& o, hipStream_t cs) {
   const int na = int(sv.size());
   const Level& c0 = sv[0]->coarsest();
   for (int k = 1; k < na; ++k) {
@@ -984,7 +1432,8 @@ std::unique_ptr<CoarseBatchSet> make_coarse_batch(std::vector<std::unique_ptr<So
   const Kind kind = c0.kind;
   const size_t w = c0.fp32 ? 4 : 8;
   std::unique_ptr<CoarseBatchSet> cb(new CoarseBatchSet);
-  IPDG_HIP(hipStreamCreateWithFlags(&cb->stream, hipStreamNonBlocking));
+  cb->N = Nc;
+  cb->kind = kind;
   std::vector<CoarseBatchEntry> ent(na);
   int off = 0;
   bool any_kappa = false;
@@ -1020,7 +1469,6 @@ std::unique_ptr<CoarseBatchSet> make_coarse_batch(std::vector<std::unique_ptr<So
     }
   }
   const size_t nv = (size_t)Kt * Np * w;
-  hipStream_t cs = cb->stream;
   cb->ent.alloc(na * sizeof(CoarseBatchEntry));
   cb->tile_solve.alloc(grid * sizeof(int));
   cb->conn.alloc((size_t)Kt * sizeof(Conn));
@@ -1084,73 +1532,256 @@ std::unique_ptr<CoarseBatchSet> make_coarse_batch(std::vector<std::unique_ptr<So
   a.ops = device_ops(Nc, kind);
   a.partials = cb->partials.as<double>();
   a.sc = cb->sc.as<CGScal>();
-  // one batched coarse solve: start, coarse_max iterations, copy-out
-  hipGraph_t g = nullptr;
-  IPDG_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-  try {
-    IPDG_HIP(coarse_batch(Nc, kind, a, -1, cs));
-    for (int it = 0; it < cb->max_iters; ++it) IPDG_HIP(coarse_batch(Nc, kind, a, it, cs));
-    IPDG_HIP(coarse_batch(Nc, kind, a, -2, cs));
-  } catch (...) {
-    (void)hipStreamEndCapture(cs, &g);
-    if (g) (void)hipGraphDestroy(g);
-    throw;
-  }
-  IPDG_HIP(hipStreamEndCapture(cs, &g));
-  hipError_t e = hipGraphInstantiate(&cb->graph, g, nullptr, nullptr, 0);
-  (void)hipGraphDestroy(g);
-  IPDG_HIP(e);
-  cb->ev.assign(na, nullptr);
-  for (int k = 0; k < na; ++k) IPDG_HIP(hipEventCreateWithFlags(&cb->ev[k], hipEventDisableTiming));
-  IPDG_HIP(hipEventCreateWithFlags(&cb->ev_done, hipEventDisableTiming));
   return cb;
 }
 
-// What a batched coarse set was built for: the solves' setups (ids are never
-// reused, so a destroyed mesh never matches), their coarse buffers and
-// constants, the coarse options and the device.
-struct CoarseBatchKey {
-  std::vector<unsigned long long> ids;
-  std::vector<const void*> ptrs;
-  std::vector<double> lambdas;
-  double coarse_tol = 0;
-  int coarse_max = 0, device = -1;
-  bool operator==(const CoarseBatchKey& o) const {
-    return ids == o.ids && ptrs == o.ptrs && lambdas == o.lambdas && coarse_tol == o.coarse_tol &&
-           coarse_max == o.coarse_max && device == o.device;
+// One launch of a fused batch: the recorded launches of several solves that
+// share a kernel (their argument records and block map at the given arena
+// offsets), a solve's own launch (an operator variant without a batched
+// form), or the coarsest-level solves of all solves.
+struct FusedStep {
+  BatchOp proto;
+  std::vector<BatchOp> ops;        // the members' recorded launches
+  size_t tab_off = 0, map_off = 0;
+  int nblocks = 0;
+};
+
+// Merge the solves' recorded launch sequences into shared launches.  Each
+// solve keeps its own order; a step takes the next launch of the solve with
+// the most launches left before its coarsest-level solve (so that solves
+// with more levels run ahead until the others can join their launches) and
+// every solve whose next launch has the same kernel; the coarsest-level
+// solve runs when every solve has reached it.
+std::vector<FusedStep> merge_launches(const std::vector<std::vector<BatchOp>>& ops) {
+  const int na = int(ops.size());
+  std::vector<size_t> pos(na, 0);
+  std::vector<FusedStep> steps;
+  auto before_coarse = [&](int k) {
+    size_t j = pos[k];
+    while (j < ops[k].size() && ops[k][j].type != OpType::kCoarse) ++j;
+    return j - pos[k];
+  };
+  for (;;) {
+    int lead = -1;
+    size_t most = 0;
+    int left = 0, at_coarse = 0;
+    for (int k = 0; k < na; ++k) {
+      if (pos[k] >= ops[k].size()) continue;
+      ++left;
+      const size_t r = before_coarse(k);
+      if (r == 0) {
+        ++at_coarse;
+      } else if (lead < 0 || r > most) {
+        lead = k;
+        most = r;
+      }
+    }
+    if (left == 0) break;
+    FusedStep st;
+    if (lead < 0) {
+      if (at_coarse != na) throw Error(IPDG_EUNSUPPORTED, "the batch's solves reach their coarsest levels unevenly");
+      st.proto = ops[0][pos[0]];
+      for (int k = 0; k < na; ++k) {
+        if (!same_launch(st.proto, ops[k][pos[k]]))
+          throw Error(IPDG_EUNSUPPORTED, "the batch's coarsest levels differ in degree or precision");
+        st.ops.push_back(ops[k][pos[k]]);
+        ++pos[k];
+      }
+      steps.push_back(std::move(st));
+      continue;
+    }
+    st.proto = ops[lead][pos[lead]];
+    for (int k = 0; k < na; ++k) {
+      if (pos[k] >= ops[k].size()) continue;
+      if (k == lead || same_launch(st.proto, ops[k][pos[k]])) {
+        st.ops.push_back(ops[k][pos[k]]);
+        ++pos[k];
+      }
+    }
+    steps.push_back(std::move(st));
+  }
+  return steps;
+}
+
+// A fused batch: `every` outer iterations of all its solves as one launch
+// sequence (captured as one graph), followed by a gather of every solve's CG
+// scalars for one copy to the host.
+struct FusedBatch {
+  std::unique_ptr<CoarseBatchSet> cb;
+  std::vector<FusedStep> steps;
+  DevBuf arena, scal_src, scal_all;
+  CGScal* host = nullptr;          // pinned, one record per solve
+  int na = 0, every = 0;
+  hipStream_t stream = nullptr;
+  hipGraphExec_t graph = nullptr;
+  ~FusedBatch() {
+    if (graph) (void)hipGraphExecDestroy(graph);
+    if (stream) (void)hipStreamDestroy(stream);
+    if (host) (void)hipHostFree(host);
+  }
+
+  void issue(hipStream_t s) const {
+    const char* base = arena.as<char>();
+    for (int it = 0; it < every; ++it)
+      for (const FusedStep& st : steps) {
+        const BatchOp& p = st.proto;
+        const BlockRef* map = reinterpret_cast<const BlockRef*>(base + st.map_off);
+        const void* tab = base + st.tab_off;
+        switch (p.type) {
+          case OpType::kAx:
+            IPDG_HIP(ax_batch(p.N, p.kind, p.kap, p.variant, static_cast<const ElemArgs*>(tab), map, st.nblocks, s));
+            break;
+          case OpType::kAxDirect:
+            IPDG_HIP(ax(p.N, p.kind, p.ea, s));
+            break;
+          case OpType::kMinv:
+            IPDG_HIP(minv_batch(p.N, p.kind, static_cast<const ElemArgs*>(tab), map, st.nblocks, s));
+            break;
+          case OpType::kTransfer:
+            IPDG_HIP(transfer_batch(p.N, p.Nc, p.restrict_op, p.kind, static_cast<const TransferArgs*>(tab), map,
+                                    st.nblocks, s));
+            break;
+          case OpType::kVec:
+            IPDG_HIP(vec_batch(p.vop, p.fp32, p.flag, static_cast<const VecArgs*>(tab), map, st.nblocks, s));
+            break;
+          case OpType::kCoarse:
+            // start, the iterations up to the largest member cap, copy-out
+            IPDG_HIP(coarse_batch(cb->N, cb->kind, cb->a, -1, s));
+            for (int c = 0; c < cb->max_iters; ++c) IPDG_HIP(coarse_batch(cb->N, cb->kind, cb->a, c, s));
+            IPDG_HIP(coarse_batch(cb->N, cb->kind, cb->a, -2, s));
+            break;
+        }
+      }
+    IPDG_HIP(scal_gather(scal_src.as<const CGScal* const>(), scal_all.as<CGScal>(), na, s));
+  }
+
+  // `every` iterations of every solve, then their scalars on the host
+  void run(bool use_graph) {
+    if (use_graph) IPDG_HIP(hipGraphLaunch(graph, stream));
+    else issue(stream);
+    IPDG_HIP(hipMemcpyAsync(host, scal_all.get(), na * sizeof(CGScal), hipMemcpyDeviceToHost, stream));
+    IPDG_HIP(hipStreamSynchronize(stream));
   }
 };
 
-CoarseBatchKey coarse_batch_key(const std::vector<std::unique_ptr<Solver>>& sv, const ipdg_solve_opts& o) {
-  CoarseBatchKey k;
-  for (const auto& s : sv) {
-    k.ids.push_back(s->setup_id());
-    k.ptrs.push_back(s->coarse_rhs());
-    k.ptrs.push_back(s->coarse_sol());
-    k.ptrs.push_back(s->done_flag());
-    k.lambdas.push_back(s->lambda());
+std::unique_ptr<FusedBatch> make_fused_batch(std::vector<std::unique_ptr<Solver>>& sv, const ipdg_solve_opts& o,
+                                             int every, bool use_graph) {
+  const int na = int(sv.size());
+  std::unique_ptr<FusedBatch> fb(new FusedBatch);
+  fb->na = na;
+  fb->every = every;
+  IPDG_HIP(hipStreamCreateWithFlags(&fb->stream, hipStreamNonBlocking));
+  std::vector<std::vector<BatchOp>> ops(na);
+  bool coarse = false;
+  for (int k = 0; k < na; ++k) {
+    sv[k]->record_iteration(ops[k]);
+    for (const BatchOp& b : ops[k]) coarse = coarse || b.type == OpType::kCoarse;
   }
-  k.coarse_tol = o.coarse_tol;
-  k.coarse_max = o.coarse_max_iters;
+  if (coarse) {
+    fb->cb = make_coarse_batch(sv, o, fb->stream);
+    if (!fb->cb) return nullptr;
+  }
+  fb->steps = merge_launches(ops);
+  // argument records and block maps of every shared launch, in one arena
+  std::vector<char> img;
+  auto put = [&img](const void* p, size_t bytes) {
+    const size_t off = (img.size() + 63) / 64 * 64;
+    img.resize(off + bytes);
+    std::memcpy(img.data() + off, p, bytes);
+    return off;
+  };
+  for (FusedStep& st : fb->steps) {
+    const OpType t = st.proto.type;
+    if (t == OpType::kCoarse || t == OpType::kAxDirect) continue;
+    std::vector<BlockRef> map;
+    for (size_t i = 0; i < st.ops.size(); ++i)
+      for (int b = 0; b < st.ops[i].nb; ++b) map.push_back(BlockRef{int(i), b, st.ops[i].nb, st.ops[i].per});
+    if (t == OpType::kAx || t == OpType::kMinv) {
+      std::vector<ElemArgs> tab;
+      for (const BatchOp& b : st.ops) tab.push_back(b.ea);
+      st.tab_off = put(tab.data(), tab.size() * sizeof(ElemArgs));
+    } else if (t == OpType::kTransfer) {
+      std::vector<TransferArgs> tab;
+      for (const BatchOp& b : st.ops) tab.push_back(b.ta);
+      st.tab_off = put(tab.data(), tab.size() * sizeof(TransferArgs));
+    } else {
+      std::vector<VecArgs> tab;
+      for (const BatchOp& b : st.ops) tab.push_back(b.va);
+      st.tab_off = put(tab.data(), tab.size() * sizeof(VecArgs));
+    }
+    st.map_off = put(map.data(), map.size() * sizeof(BlockRef));
+    st.nblocks = int(map.size());
+  }
+  fb->arena.alloc(std::max<size_t>(img.size(), 64));
+  IPDG_HIP(hipMemcpyAsync(fb->arena.get(), img.data(), img.size(), hipMemcpyHostToDevice, fb->stream));
+  std::vector<const CGScal*> src(na);
+  for (int k = 0; k < na; ++k) src[k] = sv[k]->scal_dev();
+  fb->scal_src.alloc(na * sizeof(const CGScal*));
+  fb->scal_all.alloc(na * sizeof(CGScal));
+  IPDG_HIP(hipMemcpyAsync(fb->scal_src.get(), src.data(), na * sizeof(const CGScal*), hipMemcpyHostToDevice,
+                          fb->stream));
+  IPDG_HIP(hipHostMalloc(reinterpret_cast<void**>(&fb->host), na * sizeof(CGScal), hipHostMallocDefault));
+  IPDG_HIP(hipStreamSynchronize(fb->stream));
+  if (use_graph) {
+    hipGraph_t g = nullptr;
+    IPDG_HIP(hipStreamBeginCapture(fb->stream, hipStreamCaptureModeThreadLocal));
+    try {
+      fb->issue(fb->stream);
+    } catch (...) {
+      (void)hipStreamEndCapture(fb->stream, &g);
+      if (g) (void)hipGraphDestroy(g);
+      throw;
+    }
+    IPDG_HIP(hipStreamEndCapture(fb->stream, &g));
+    hipError_t e = hipGraphInstantiate(&fb->graph, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    IPDG_HIP(e);
+  }
+  return fb;
+}
+
+// What a fused batch was built for: the solves' setups in batch order (ids
+// are never reused, so a destroyed mesh never matches; a setup fixes every
+// buffer and constant its launches name), the iterations per check, the
+// operator variants in force, graph use and the device.
+struct FusedKey {
+  std::vector<unsigned long long> ids;
+  std::vector<int> variants;
+  int every = 0, device = -1;
+  bool graph = true;
+  bool operator==(const FusedKey& o) const {
+    return ids == o.ids && variants == o.variants && every == o.every && device == o.device && graph == o.graph;
+  }
+};
+
+FusedKey fused_key(const std::vector<std::unique_ptr<Solver>>& sv, int every, bool graph) {
+  FusedKey k;
+  for (const auto& s : sv) k.ids.push_back(s->setup_id());
+  for (int N = 1; N <= kMaxN; ++N) {
+    k.variants.push_back(ax_variant(N, false));
+    k.variants.push_back(ax_variant(N, true));
+  }
+  k.every = every;
+  k.graph = graph;
   (void)hipGetDevice(&k.device);
   return k;
 }
 
-// The last batched coarse set, reused by the next batch of the same solves
-// (a serving loop); held until it is replaced (never freed at process exit,
+// The last fused batch, reused by the next batch of the same solves (a
+// serving loop); held until it is replaced (never freed at process exit,
 // when the runtime may already be gone).
-std::mutex g_cb_mu;
-CoarseBatchSet* g_cb = nullptr;
-bool g_cb_valid = false;
-CoarseBatchKey g_cb_key;
+std::mutex g_fb_mu;
+FusedBatch* g_fb = nullptr;
+bool g_fb_valid = false;
+FusedKey g_fb_key;
 
 }  // namespace
 
 ipdg_status solve_batch(int nb, ipdg_mesh_s* const* meshes, const double* lambdas, double tau,
                         const double* const* b, double* const* x, double tol, const ipdg_solve_opts& o,
                         int* iters, double* relres, hipStream_t s) {
-  // Every solve keeps its own device state, stream and captured graph; the
-  // host advances all of them by check_every iterations per round.
+  // Every solve keeps its own device state and stream; the host advances all
+  // of them by check_every iterations per round.
   for (int i = 0; i < nb; ++i) {
     if (!meshes[i]) throw Error(IPDG_EINVAL, "null mesh in batch");
     if (!b[i] || !x[i]) throw Error(IPDG_EINVAL, "null vector in batch");
@@ -1172,57 +1803,41 @@ ipdg_status solve_batch(int nb, ipdg_mesh_s* const* meshes, const double* lambda
   const int every = std::max(1, o.check_every);
   int left = 0;
   for (int k = 0; k < na; ++k) left += !runs[k].finished;
-  std::unique_ptr<CoarseBatchSet> own_cb;
-  CoarseBatchSet* cb = nullptr;
-  std::unique_lock<std::mutex> lk(g_cb_mu, std::defer_lock);
-  if (left > 0 && o.pc == IPDG_PC_PMG && na >= 2 && batch_coarse_fused()) {
-    for (int k = 0; k < na; ++k) sv[k]->capture_split();
-    const CoarseBatchKey key = coarse_batch_key(sv, o);
+  std::unique_ptr<FusedBatch> own_fb;
+  FusedBatch* fb = nullptr;
+  std::unique_lock<std::mutex> lk(g_fb_mu, std::defer_lock);
+  const bool use_graph = std::getenv("IPDG_NO_GRAPH") == nullptr;
+  if (left > 0 && na >= 2 && batch_fused() && !(o.pc == IPDG_PC_PMG && o.coarse_amg == 1)) {
+    const FusedKey key = fused_key(sv, every, use_graph);
     if (lk.try_lock()) {
-      if (!g_cb_valid || !(g_cb_key == key)) {
-        delete g_cb;
-        g_cb = nullptr;
-        g_cb_valid = false;
-        g_cb = make_coarse_batch(sv, o).release();
-        g_cb_key = key;
-        g_cb_valid = true;
+      if (!g_fb_valid || !(g_fb_key == key)) {
+        delete g_fb;
+        g_fb = nullptr;
+        g_fb_valid = false;
+        g_fb = make_fused_batch(sv, o, every, use_graph).release();
+        g_fb_key = key;
+        g_fb_valid = g_fb != nullptr;
       }
-      cb = g_cb;
+      fb = g_fb;
     } else {
-      own_cb = make_coarse_batch(sv, o);   // another thread holds the cached set
-      cb = own_cb.get();
+      own_fb = make_fused_batch(sv, o, every, use_graph);   // another thread holds the cached batch
+      fb = own_fb.get();
     }
   }
-  if (cb) {
-    // Fused coarse mode: every outer iteration runs each solve's part before
-    // its coarsest-level solve on its own stream, then the coarsest-level
-    // solves of all solves together (one launch per coarse iteration over the
-    // concatenated levels), then each solve's part after it.
-    int it = 0;
+  if (fb) {
+    // Fused mode: one launch per operation and kernel for all solves (a
+    // finished solve's launches are no-ops on its done flag); residual
+    // replacements and stops run on the solves' own streams in between.
     while (left > 0) {
-      for (int k = 0; k < na; ++k) {
-        if (runs[k].finished) continue;
-        sv[k]->launch_pre();
-        IPDG_HIP(hipEventRecord(cb->ev[k], sv[k]->stream()));
-        IPDG_HIP(hipStreamWaitEvent(cb->stream, cb->ev[k], 0));
-      }
-      IPDG_HIP(hipGraphLaunch(cb->graph, cb->stream));
-      IPDG_HIP(hipEventRecord(cb->ev_done, cb->stream));
-      for (int k = 0; k < na; ++k) {
-        if (runs[k].finished) continue;
-        IPDG_HIP(hipStreamWaitEvent(sv[k]->stream(), cb->ev_done, 0));
-        sv[k]->launch_post();
-      }
-      if (++it % every != 0) continue;
-      for (int k = 0; k < na; ++k)
-        if (!runs[k].finished) sv[k]->copy_scal();
       for (int k = 0; k < na; ++k) IPDG_HIP(hipStreamSynchronize(sv[k]->stream()));
-      IPDG_HIP(hipStreamSynchronize(cb->stream));
+      fb->run(use_graph);
       left = 0;
-      for (int k = 0; k < na; ++k)
-        if (!runs[k].finished) left += !sv[k]->after_step(runs[k]);
+      for (int k = 0; k < na; ++k) {
+        if (runs[k].finished) continue;
+        sv[k]->set_host_scal(fb->host[k]);
+        left += !sv[k]->after_step(runs[k]);
+      }
     }
-    IPDG_HIP(hipStreamSynchronize(cb->stream));
   }
   // Otherwise each solve replays its own captured graph of `every`
   // iterations on its own stream; the launches of all unfinished solves are

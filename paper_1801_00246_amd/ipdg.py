@@ -22,6 +22,7 @@ BC_INTERIOR, BC_DIRICHLET, BC_NEUMANN = 0, 1, 2
 PC_NONE, PC_JACOBI, PC_BLOCK_MASS, PC_PMG = 0, 1, 2, 3
 PREC_FP64, PREC_MIXED, PREC_FP32_OPERATOR = 0, 1, 2
 MAX_LEVELS = 8
+AMG_MAX_LEVELS = 12
 
 
 class IpdgError(RuntimeError):
@@ -37,18 +38,21 @@ class SolveOpts(C.Structure):
                 ("cheb_lo", C.c_double), ("cheb_hi", C.c_double),
                 ("rho", C.c_double * MAX_LEVELS), ("rho_steps", C.c_int),
                 ("coarse_tol", C.c_double), ("coarse_max_iters", C.c_int),
-                ("reliable_drop", C.c_double), ("coarse_persistent", C.c_int)]
+                ("reliable_drop", C.c_double), ("coarse_persistent", C.c_int),
+                ("coarse_amg", C.c_int), ("amg_coarse_size", C.c_int), ("amg_cycles", C.c_int)]
 
 
 class SolveInfo(C.Structure):
     _fields_ = [("iters", C.c_int), ("relres", C.c_double), ("restarts", C.c_int),
                 ("rho_used", C.c_double * MAX_LEVELS), ("setup_ms", C.c_double),
-                ("solve_ms", C.c_double), ("coarse_iters", C.c_int)]
+                ("solve_ms", C.c_double), ("coarse_iters", C.c_int),
+                ("amg_levels", C.c_int), ("amg_n", C.c_int * AMG_MAX_LEVELS)]
 
     def as_dict(self):
         return {"iters": self.iters, "relres": self.relres, "restarts": self.restarts,
                 "rho_used": list(self.rho_used), "setup_ms": self.setup_ms,
-                "solve_ms": self.solve_ms, "coarse_iters": self.coarse_iters}
+                "solve_ms": self.solve_ms, "coarse_iters": self.coarse_iters,
+                "amg_sizes": list(self.amg_n)[:self.amg_levels]}
 
 
 _lib = None

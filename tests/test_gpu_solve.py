@@ -164,9 +164,9 @@ def test_one_vcycle_large_coarse_level_matches_oracle(large_vcycle, persistent):
 
 
 def test_batch_fused_coarse_with_a_large_member(monkeypatch):
-    """A fused coarse batch whose largest member's degree-1 level spans 259
-    tiles (more than 256 partials per member), against per-solve coarse
-    launches and the oracle's residual."""
+    """A fused batch whose largest member's degree-1 level spans 259 tiles
+    (more than 256 partials per member), against per-solve launches and the
+    oracle's residual."""
     draws = [(182, 2, 5.0), (10, 4, 1.0), (13, 3, 100.0)]
     o = P.default_opts(pc=P.PC_PMG, coarse_tol=0.0, coarse_max_iters=20)
     meshes, bs, As, lams = [], [], [], []
@@ -180,7 +180,7 @@ def test_batch_fused_coarse_with_a_large_member(monkeypatch):
         lams.append(lam)
     assert meshes[0].K // 256 > 256
     xf, itf, relf, st = P.solve_batch(meshes, lams, bs, tol=1e-8, opts=o)
-    monkeypatch.setenv("IPDG_BATCH_COARSE", "separate")
+    monkeypatch.setenv("IPDG_BATCH", "separate")
     xs, its, _, st2 = P.solve_batch(meshes, lams, bs, tol=1e-8, opts=o)
     assert st == 0 and st2 == 0
     for i, A in enumerate(As):
@@ -320,9 +320,10 @@ def test_batch_pmg_auto_levels(prec):
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 def test_batch_fused_coarse_matches_separate_coarse(prec, monkeypatch):
-    """The batch's coarsest levels solved together (one launch per coarse
-    iteration over all solves, the default) against each solve's own coarse
-    launches: the same preconditioner up to the order of the partial sums.
+    """The fused batch (one launch per operation and kernel over all solves,
+    the coarsest levels solved together: the default) against each solve's
+    own launches: the same preconditioner up to the order of the coarse
+    level's partial sums.
     A fixed coarse iteration count (tolerance 0) keeps both on the same
     number of coarse steps; one mesh carries a coefficient."""
     draws = [(10, 4, 1.0, False), (12, 7, 30.0, True), (8, 8, 1000.0, False), (14, 5, 3.0, False)]
@@ -340,7 +341,7 @@ def test_batch_fused_coarse_matches_separate_coarse(prec, monkeypatch):
         lams.append(lam)
     xf, itf, relf, st = P.solve_batch(meshes, lams, bs, tol=1e-8, opts=o)
     assert st == 0
-    monkeypatch.setenv("IPDG_BATCH_COARSE", "separate")
+    monkeypatch.setenv("IPDG_BATCH", "separate")
     xs, its, rels, st2 = P.solve_batch(meshes, lams, bs, tol=1e-8, opts=o)
     assert st2 == 0
     for i, A in enumerate(As):
@@ -355,8 +356,8 @@ def test_batch_fused_coarse_matches_separate_coarse(prec, monkeypatch):
 
 
 def test_batch_fused_coarse_degree_two(monkeypatch):
-    """Fused coarsest levels at degree 2 (explicit levels 4 -> 2), against
-    per-solve coarse launches."""
+    """Fused batch with its coarsest levels at degree 2 (explicit levels
+    4 -> 2), against per-solve launches."""
     draws = [(9, 1.0), (13, 20.0), (11, 300.0)]
     o = P.default_opts(pc=P.PC_PMG, degrees=[4, 2], coarse_tol=0.0, coarse_max_iters=30)
     meshes, bs, As, lams = [], [], [], []
@@ -369,7 +370,7 @@ def test_batch_fused_coarse_degree_two(monkeypatch):
         bs.append(dev(b))
         lams.append(lam)
     xf, itf, _, st = P.solve_batch(meshes, lams, bs, tol=1e-8, opts=o)
-    monkeypatch.setenv("IPDG_BATCH_COARSE", "separate")
+    monkeypatch.setenv("IPDG_BATCH", "separate")
     xs, its, _, st2 = P.solve_batch(meshes, lams, bs, tol=1e-8, opts=o)
     assert st == 0 and st2 == 0
     for i, A in enumerate(As):
@@ -380,10 +381,54 @@ def test_batch_fused_coarse_degree_two(monkeypatch):
         assert np.linalg.norm(a - c) <= 1e-10 * np.linalg.norm(c)
 
 
+@pytest.mark.parametrize("pc,prec", [("block", "fp64"), ("block", "mixed"), ("jacobi", "fp64"),
+                                     ("jacobi", "fp32op")])
+def test_batch_fused_launches_match_separate(pc, prec, monkeypatch):
+    """Without a coarsest-level solve every fused launch runs the body of the
+    solve's own launch on the solve's own block decomposition: the fused
+    batch and per-solve launches agree to rounding (the same iteration
+    counts), over mixed degrees, a coefficient mesh, a mesh of 259 element
+    tiles, and degrees whose FP32 operator has no batched form (N = 1, 2)."""
+    draws = [(9, 4, 10.0, False), (12, 2, 300.0, True), (17, 5, 1.0, False), (7, 8, 1000.0, False),
+             (182, 1, 5.0, False), (11, 3, 30.0, False)]
+    pcs = {"block": P.PC_BLOCK_MASS, "jacobi": P.PC_JACOBI}
+    precs = {"fp64": P.PREC_FP64, "mixed": P.PREC_MIXED, "fp32op": P.PREC_FP32_OPERATOR}
+    o = P.default_opts(pc=pcs[pc], prec=precs[prec])
+    meshes, bs, As, lams = [], [], [], []
+    for i, (n, N, lam, kap) in enumerate(draws):
+        msh = synth.square_mesh(n, jitter=0.1, seed=170 + i)
+        kv = synth.kappa_draw(msh.K, seed=180 + i) if kap else None
+        m = OracleMesh(msh.VX, msh.VY, msh.EToV, msh.EToB, N)
+        b = mass_apply(m, synth.nodal_normal(msh.K, m.Np, seed=190 + i))
+        if msh.K < 20000:
+            As.append(assemble(m, lam, float((N + 1) ** 2), kappa=kv))
+        else:
+            As.append(None)
+        meshes.append(P.Mesh.from_synth(N, msh, kappa=kv))
+        bs.append(dev(b))
+        lams.append(lam)
+    xf, itf, relf, st = P.solve_batch(meshes, lams, bs, tol=1e-8, opts=o)
+    monkeypatch.setenv("IPDG_BATCH", "separate")
+    xs, its, rels, st2 = P.solve_batch(meshes, lams, bs, tol=1e-8, opts=o)
+    assert st == 0 and st2 == 0
+    for i, A in enumerate(As):
+        a, c = host(xf[i]), host(xs[i])
+        d = np.linalg.norm(a - c) / np.linalg.norm(c)
+        print(f"solve {i} (N={draws[i][1]}): fused {itf[i]}, separate {its[i]}, rel diff {d:.2e}, "
+              f"bitwise {np.array_equal(a, c)}")
+        assert itf[i] == its[i]
+        assert d <= 1e-12
+        assert relf[i] <= 1e-8
+        if A is not None:
+            assert true_relres(A, a, host(bs[i])) <= 1e-8
+    for g in meshes:
+        g.close()
+
+
 def test_batch_repeated_calls_reuse_and_rebuild():
-    """Repeated batches of the same solves reuse the captured split graphs and
-    the fused coarse set; a new right-hand side gives its own solution, and a
-    changed lambda (a new setup) is picked up."""
+    """Repeated batches of the same solves reuse the fused batch (its captured
+    graph and argument tables); a new right-hand side gives its own solution,
+    and a changed lambda (a new setup) is picked up."""
     draws = [(9, 4), (11, 6), (8, 5)]
     o = P.default_opts(pc=P.PC_PMG)
     meshes, ms = [], []
