@@ -287,20 +287,25 @@ def run_pcg_compare(P, torch, coarse_caps=(150, 300)):
             key = f"{name}_coarse{cmax}"
             out[key] = {"time_to_solution_ms": round((time.time() - t0) * 1e3, 2),
                         "coarse_iters_last": info["coarse_iters"],
+                        "precond_bytes_per_element": round(info["precond_bytes"] / msh.K),
                         "iters": info["iters"], "true_relres": info["relres"],
                         "restarts": info["restarts"], "setup_ms": round(info["setup_ms"], 2)}
             print(f"# pcg {key}: {out[key]}", file=sys.stderr, flush=True)
-    # pMG-AMG: the degree-1 level by one V-cycle of the aggregation AMG below it
-    for name, prec in (("fp64", P.PREC_FP64), ("mixed", P.PREC_MIXED)):
-        o = P.default_opts(pc=P.PC_PMG, prec=prec, degrees=[7, 3, 1], coarse_amg=1)
+    # pMG-AMG: the degree-1 level by one cycle of the aggregation AMG below it
+    # (K-cycle on its two finest levels); "amg_top": the degree-1 level by two
+    # flexible-CG steps, each preconditioned by one such cycle
+    for name, prec, top in (("fp64", P.PREC_FP64, 0), ("mixed", P.PREC_MIXED, 0), ("fp64", P.PREC_FP64, 1),
+                            ("mixed", P.PREC_MIXED, 1)):
+        o = P.default_opts(pc=P.PC_PMG, prec=prec, degrees=[7, 3, 1], coarse_amg=1, amg_top_krylov=top)
         g.pcg(b, tol=1e-8, opts=o)                     # setup + warm-up
         torch.cuda.synchronize()
         t0 = time.time()
         xs, info, st = g.pcg(b, tol=1e-8, opts=o)
         torch.cuda.synchronize()
-        key = f"{name}_amg"
+        key = f"{name}_amg" + ("_top" if top else "")
         out[key] = {"time_to_solution_ms": round((time.time() - t0) * 1e3, 2), "iters": info["iters"],
                     "true_relres": info["relres"], "amg_sizes": info["amg_sizes"],
+                    "precond_bytes_per_element": round(info["precond_bytes"] / msh.K),
                     "setup_ms": round(info["setup_ms"], 2)}
         print(f"# pcg {key}: {out[key]}", file=sys.stderr, flush=True)
     return out

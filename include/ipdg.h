@@ -102,18 +102,27 @@ typedef struct {
                               one short kernel sequence per iteration inside
                               the captured graph, converged iterations skipped */
   /* pMG-AMG (Sec. 3): coarse_amg = 1 replaces the coarsest-level Jacobi-PCG
-     by amg_cycles V-cycles of an aggregation AMG hierarchy below the degree-1
+     by amg_cycles cycles of an aggregation AMG hierarchy below the degree-1
      level (the last p-level must be degree 1): the degree-1 level (smoothed
      as the p-levels), one value per element (the element-block sums of the
      degree-1 operator), then greedy aggregates of maximal independent node
      sets with Galerkin operators, smoothed by Chebyshev of cheb_degree steps
      over [cheb_lo, cheb_hi] times the Gershgorin bound of D^-1 A, until at
      most amg_coarse_size (<= 2048) unknowns remain or 12 levels exist; the
-     coarsest level is solved by its inverse.  Built on the host at setup.
+     coarsest level is solved by its inverse.  The cycle is a K-cycle on the
+     first amg_kcycle_levels levels (the coarse correction by two flexible-CG
+     steps on the next level, each preconditioned by one cycle there; the
+     second step skipped once the first reduced the coarse residual norm to
+     0.25 of its start) and a V-cycle below.  Built on the host at setup.
      In a batch the solves then keep their own launches. */
   int coarse_amg;          /* 0 (default) or 1 */
   int amg_coarse_size;     /* default 512 */
   int amg_cycles;          /* default 1 */
+  int amg_kcycle_levels;   /* default 2 (the paper's two finest levels); 0: V-cycle */
+  int amg_top_krylov;      /* 1: the degree-1 level solved by two flexible-CG
+                              steps on it, each preconditioned by one AMG
+                              cycle (the K-cycle's step one level higher;
+                              needs amg_cycles = 1); default 0 */
 } ipdg_solve_opts;
 
 /* Result record of a solve (all fields written). */
@@ -129,6 +138,11 @@ typedef struct {
   int amg_levels;          /* coarse_amg: levels of the algebraic hierarchy,
                               the degree-1 level included (else 0) */
   int amg_n[IPDG_AMG_MAX_LEVELS];   /* unknowns per level, degree-1 level first */
+  int64_t precond_bytes;   /* device memory the preconditioner's set-up holds
+                              beyond the outer CG's vectors (p-multigrid
+                              levels' diagonals and work vectors, coarse-solve
+                              work, the algebraic levels' matrices, transfers,
+                              inverse and work); 0 for the diagonal ones */
 } ipdg_solve_info;
 
 void ipdg_default_opts(ipdg_solve_opts* opts);

@@ -23,9 +23,15 @@ is silent (each implemented independently in the GPU library):
   * Smoothing: Chebyshev of degree ``cheb_degree`` on D^{-1} A over
     [lo rho, hi rho]; on the algebraic levels rho is the Gershgorin bound
     max_i sum_j |A_ij| / A_ii, on the degree-1 level it is given.
-  * One cycle is a V-cycle from a zero initial guess, the same smoother
-    before and after the coarse correction (the paper's K-cycle on the two
-    finest levels is not used).
+  * One cycle starts from a zero initial guess, with the same smoother
+    before and after the coarse correction.  On the first ``kcycle_levels``
+    levels (the paper's K-cycle on the two finest levels, default 2) the
+    coarse correction is two steps of flexible CG on the next level,
+    preconditioned by that level's cycle (Notay and Vassilevski's K-cycle,
+    with their early exit: one step only when it already reduced the coarse
+    residual norm to ``kcycle_t`` = 0.25 of its start or less); where the next
+    level is the coarsest it is solved exactly instead.  Below them the
+    cycle is a V-cycle (``vcycle`` is the V-cycle on every level).
 """
 from __future__ import annotations
 
@@ -82,10 +88,11 @@ class AMG:
     oracle mesh at degree 1) with operator ``A1`` (assembled, degree 1)."""
 
     def __init__(self, m, A1, rho0, cheb_lo=0.1, cheb_hi=1.1, cheb_degree=2, coarse_size=1024,
-                 max_levels=12):
+                 max_levels=12, kcycle_levels=2, kcycle_t=0.25):
         if m.N != 1:
             raise ValueError("the algebraic levels start from degree 1")
         self.lo, self.hi, self.deg = cheb_lo, cheb_hi, cheb_degree
+        self.kcycle_levels, self.kcycle_t = kcycle_levels, kcycle_t
         A1 = sp.csr_matrix(A1)
         K = m.K
         P0 = sp.csr_matrix((np.ones(3 * K), (np.arange(3 * K), np.repeat(np.arange(K), 3))),
@@ -130,9 +137,41 @@ class AMG:
         z = z + self.P[l] @ zc
         return self.smooth(l, r, z)
 
+    def krylov_correction(self, l, rc):
+        """Approximate solution of A_l e = rc by at most two flexible-CG steps
+        from zero, each preconditioned by one cycle on level l."""
+        A = self.A[l]
+        v1 = self.cycle(l, rc)
+        w1 = A @ v1
+        rho1, alpha1 = v1 @ rc, v1 @ w1
+        r2 = rc - (rho1 / alpha1) * w1
+        if np.linalg.norm(r2) <= self.kcycle_t * np.linalg.norm(rc):
+            return (rho1 / alpha1) * v1
+        v2 = self.cycle(l, r2)
+        w2 = A @ v2
+        gamma, beta, rho2 = v2 @ w1, v2 @ w2, v2 @ r2
+        # second direction made A-orthogonal to the first: v2 - (gamma/alpha1) v1
+        alpha2 = beta - gamma * gamma / alpha1
+        return (rho1 / alpha1 - gamma * rho2 / (alpha1 * alpha2)) * v1 + (rho2 / alpha2) * v2
+
+    def cycle(self, l, r):
+        """One preconditioner cycle from zero on level l: K-cycle on the first
+        kcycle_levels levels, V-cycle below."""
+        last = len(self.A) - 1
+        if l == last:
+            return self.coarse @ r
+        z = self.smooth(l, r, None)
+        rc = self.P[l].T @ (r - self.A[l] @ z)
+        if l < self.kcycle_levels and l + 1 < last:
+            zc = self.krylov_correction(l + 1, rc)
+        else:
+            zc = self.cycle(l + 1, rc)
+        z = z + self.P[l] @ zc
+        return self.smooth(l, r, z)
+
     def solve(self, r, cycles=1):
-        """``cycles`` V-cycles from zero (iterative refinement)."""
-        x = self.vcycle(0, r)
+        """``cycles`` cycles from zero (iterative refinement)."""
+        x = self.cycle(0, r)
         for _ in range(cycles - 1):
-            x = x + self.vcycle(0, r - self.A[0] @ x)
+            x = x + self.cycle(0, r - self.A[0] @ x)
         return x

@@ -181,7 +181,8 @@ class PMG:
 
     def __init__(self, mesh, degrees, lam, ctau, rho, cheb_lo=0.1, cheb_hi=1.1,
                  cheb_degree=2, coarse_tol=1e-2, coarse_max=200, coarse_exact=False,
-                 coarse_amg=False, amg_cycles=1, amg_coarse_size=1024, kappa=None):
+                 coarse_amg=False, amg_cycles=1, amg_coarse_size=1024, kappa=None, amg_kcycle_levels=2,
+                 amg_top_krylov=False):
         self.degrees = list(degrees)
         N0 = self.degrees[0]
         self.levels = []
@@ -202,12 +203,15 @@ class PMG:
         self.coarse_iters = []
         self.amg = None
         self.amg_cycles = amg_cycles
+        # the degree-1 level solved by the K-cycle's two flexible-CG steps on
+        # it, each preconditioned by one AMG cycle, instead of plain cycles
+        self.amg_top_krylov = amg_top_krylov
         if coarse_amg:
             # the algebraic levels below the degree-1 level (pMG-AMG, Sec. 3)
             from .amg import AMG
             L = self.levels[-1]
             self.amg = AMG(L["m"], L["A"], self.rho[-1], cheb_lo, cheb_hi, cheb_degree,
-                           coarse_size=amg_coarse_size)
+                           coarse_size=amg_coarse_size, kcycle_levels=amg_kcycle_levels)
 
     def smooth(self, l, f, x0):
         L = self.levels[l]
@@ -217,6 +221,8 @@ class PMG:
         L = self.levels[l]
         if l == len(self.levels) - 1:
             if self.amg is not None:
+                if self.amg_top_krylov:
+                    return self.amg.krylov_correction(0, r)
                 return self.amg.solve(r, self.amg_cycles)
             if self.coarse_exact:
                 import scipy.sparse.linalg as spla

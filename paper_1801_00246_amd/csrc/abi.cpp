@@ -103,6 +103,8 @@ void ipdg_default_opts(ipdg_solve_opts* o) {
   o->coarse_amg = 0;
   o->amg_coarse_size = 512;
   o->amg_cycles = 1;
+  o->amg_kcycle_levels = 2;
+  o->amg_top_krylov = 0;
 }
 
 const char* ipdg_last_error(void) { return g_last_error.c_str(); }

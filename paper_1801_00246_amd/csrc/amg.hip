@@ -80,7 +80,157 @@ __global__ __launch_bounds__(kThreads) void k_add(T* __restrict__ x, const T* __
   if (i < n) x[i] += y[i];
 }
 
+// ---- K-cycle: one block of kRed threads sums each dot product ----
+constexpr int kRed = 1024;
+
+template <int NV>
+__device__ __forceinline__ void red_block(double (&v)[NV]) {
+  __shared__ double red[kRed / 64][NV];
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    double s = v[k];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+    v[k] = s;
+  }
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0)
+#pragma unroll
+    for (int k = 0; k < NV; ++k) red[w][k] = v[k];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      double s = red[0][k];
+      for (int ww = 1; ww < kRed / 64; ++ww) s += red[ww][k];
+      v[k] = s;
+    }
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kRed) void k_kdot1(const T* __restrict__ v1, const T* __restrict__ rc,
+                                                const T* __restrict__ w1, int n, KScal* __restrict__ S,
+                                                const int* __restrict__ skip) {
+  if (skip && *skip) return;
+  double a[3] = {0.0, 0.0, 0.0};
+  for (int i = threadIdx.x; i < n; i += kRed) {
+    const double v = v1[i], r = rc[i];
+    a[0] += v * r;
+    a[1] += v * static_cast<double>(w1[i]);
+    a[2] += r * r;
+  }
+  red_block<3>(a);
+  if (threadIdx.x == 0) {
+    S->rho1 = a[0];
+    S->a1 = a[1];
+    S->rr = a[2];
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kRed) void k_kres(const T* __restrict__ rc, const T* __restrict__ w1,
+                                               T* __restrict__ r2, int n, KScal* __restrict__ S, double t2,
+                                               const int* __restrict__ skip) {
+  if (skip && *skip) {
+    if (threadIdx.x == 0) S->flag = 1;
+    return;
+  }
+  const double c = S->rho1 / S->a1;
+  double a[1] = {0.0};
+  for (int i = threadIdx.x; i < n; i += kRed) {
+    const T r = static_cast<T>(static_cast<double>(rc[i]) - c * static_cast<double>(w1[i]));
+    r2[i] = r;
+    a[0] += static_cast<double>(r) * static_cast<double>(r);
+  }
+  red_block<1>(a);
+  if (threadIdx.x == 0) S->flag = a[0] <= t2 * S->rr ? 1 : 0;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kRed) void k_kdot2(const T* __restrict__ v2, const T* __restrict__ w1,
+                                                const T* __restrict__ w2, const T* __restrict__ r2, int n,
+                                                KScal* __restrict__ S) {
+  if (S->flag) return;
+  double a[3] = {0.0, 0.0, 0.0};
+  for (int i = threadIdx.x; i < n; i += kRed) {
+    const double v = v2[i];
+    a[0] += v * static_cast<double>(w1[i]);
+    a[1] += v * static_cast<double>(w2[i]);
+    a[2] += v * static_cast<double>(r2[i]);
+  }
+  red_block<3>(a);
+  if (threadIdx.x == 0) {
+    S->g = a[0];
+    S->b = a[1];
+    S->rho2 = a[2];
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_kcomb(const T* __restrict__ v1, const T* __restrict__ v2,
+                                                    T* __restrict__ ec, int n, const KScal* __restrict__ S,
+                                                    const int* __restrict__ skip) {
+  if (skip && *skip) return;
+  const int i = blockIdx.x * kThreads + threadIdx.x;
+  if (i >= n) return;
+  if (S->flag) {
+    ec[i] = static_cast<T>((S->rho1 / S->a1) * static_cast<double>(v1[i]));
+  } else {
+    const double a2 = S->b - S->g * S->g / S->a1;
+    const double c1 = S->rho1 / S->a1 - S->g * S->rho2 / (S->a1 * a2), c2 = S->rho2 / a2;
+    ec[i] = static_cast<T>(c1 * static_cast<double>(v1[i]) + c2 * static_cast<double>(v2[i]));
+  }
+}
+
 }  // namespace
+
+hipError_t amg_kdot1(bool fp32, const void* v1, const void* rc, const void* w1, int n, KScal* S, const int* skip,
+                     hipStream_t s) {
+  if (fp32)
+    hipLaunchKernelGGL(k_kdot1<float>, dim3(1), dim3(kRed), 0, s, static_cast<const float*>(v1),
+                       static_cast<const float*>(rc), static_cast<const float*>(w1), n, S, skip);
+  else
+    hipLaunchKernelGGL(k_kdot1<double>, dim3(1), dim3(kRed), 0, s, static_cast<const double*>(v1),
+                       static_cast<const double*>(rc), static_cast<const double*>(w1), n, S, skip);
+  return hipGetLastError();
+}
+
+hipError_t amg_kres(bool fp32, const void* rc, const void* w1, void* r2, int n, KScal* S, double t2, const int* skip,
+                    hipStream_t s) {
+  if (fp32)
+    hipLaunchKernelGGL(k_kres<float>, dim3(1), dim3(kRed), 0, s, static_cast<const float*>(rc),
+                       static_cast<const float*>(w1), static_cast<float*>(r2), n, S, t2, skip);
+  else
+    hipLaunchKernelGGL(k_kres<double>, dim3(1), dim3(kRed), 0, s, static_cast<const double*>(rc),
+                       static_cast<const double*>(w1), static_cast<double*>(r2), n, S, t2, skip);
+  return hipGetLastError();
+}
+
+hipError_t amg_kdot2(bool fp32, const void* v2, const void* w1, const void* w2, const void* r2, int n, KScal* S,
+                     hipStream_t s) {
+  if (fp32)
+    hipLaunchKernelGGL(k_kdot2<float>, dim3(1), dim3(kRed), 0, s, static_cast<const float*>(v2),
+                       static_cast<const float*>(w1), static_cast<const float*>(w2), static_cast<const float*>(r2),
+                       n, S);
+  else
+    hipLaunchKernelGGL(k_kdot2<double>, dim3(1), dim3(kRed), 0, s, static_cast<const double*>(v2),
+                       static_cast<const double*>(w1), static_cast<const double*>(w2),
+                       static_cast<const double*>(r2), n, S);
+  return hipGetLastError();
+}
+
+hipError_t amg_kcomb(bool fp32, const void* v1, const void* v2, void* ec, int n, const KScal* S, const int* skip,
+                     hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  if (fp32)
+    hipLaunchKernelGGL(k_kcomb<float>, dim3(blocks_for(n)), dim3(kThreads), 0, s, static_cast<const float*>(v1),
+                       static_cast<const float*>(v2), static_cast<float*>(ec), n, S, skip);
+  else
+    hipLaunchKernelGGL(k_kcomb<double>, dim3(blocks_for(n)), dim3(kThreads), 0, s, static_cast<const double*>(v1),
+                       static_cast<const double*>(v2), static_cast<double*>(ec), n, S, skip);
+  return hipGetLastError();
+}
 
 hipError_t amg_spmv(bool fp32, const int* ptr, const int* col, const void* val, const void* x, void* y, int n,
                     const int* skip, hipStream_t s) {

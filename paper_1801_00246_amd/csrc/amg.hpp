@@ -40,6 +40,15 @@ double amg_gershgorin(const Csr& A);
 // by Cholesky factorisation; false when a pivot is not positive.
 bool amg_spd_inverse(const Csr& A, std::vector<double>& inv);
 
+// Scalars of one K-cycle coarse correction (two flexible-CG steps on the next
+// level): (v1, rc), (v1, w1), (rc, rc), (v2, w1), (v2, w2), (v2, r2), and the
+// flag that skips the second step (set when the first reduced |rc| to
+// kcycle_t of its start or less, or when the correction itself is skipped).
+struct KScal {
+  double rho1 = 0, a1 = 0, rr = 0, g = 0, b = 0, rho2 = 0;
+  int flag = 0, pad = 0;
+};
+
 // ---- device kernels (T = float when fp32, else double); every launch is a
 // no-op while *skip is set (skip may be null) ----
 // y = A x (compressed rows)
@@ -57,5 +66,21 @@ hipError_t amg_dense(bool fp32, const void* inv, const void* f, void* z, int n, 
 hipError_t amg_sub(bool fp32, const void* f, const void* t, void* r, size_t n, const int* skip, hipStream_t s);
 // x += y
 hipError_t amg_add(bool fp32, void* x, const void* y, size_t n, const int* skip, hipStream_t s);
+
+// K-cycle steps (dots summed in FP64 by one block, in a fixed order):
+//   kdot1: S.rho1 = (v1, rc), S.a1 = (v1, w1), S.rr = (rc, rc)
+//   kres:  r2 = rc - (rho1 / a1) w1; S.flag = (r2, r2) <= t2 S.rr (1 also when
+//          *skip is set, so that the second step is skipped with it)
+//   kdot2: S.g = (v2, w1), S.b = (v2, w2), S.rho2 = (v2, r2) (no-op on S.flag)
+//   kcomb: ec = (rho1 / a1) v1 when S.flag, else the two-step combination
+//          (rho1 / a1 - g rho2 / (a1 a2)) v1 + (rho2 / a2) v2, a2 = b - g^2 / a1
+hipError_t amg_kdot1(bool fp32, const void* v1, const void* rc, const void* w1, int n, KScal* S, const int* skip,
+                     hipStream_t s);
+hipError_t amg_kres(bool fp32, const void* rc, const void* w1, void* r2, int n, KScal* S, double t2, const int* skip,
+                    hipStream_t s);
+hipError_t amg_kdot2(bool fp32, const void* v2, const void* w1, const void* w2, const void* r2, int n, KScal* S,
+                     hipStream_t s);
+hipError_t amg_kcomb(bool fp32, const void* v1, const void* v2, void* ec, int n, const KScal* S, const int* skip,
+                     hipStream_t s);
 
 }  // namespace ipdg

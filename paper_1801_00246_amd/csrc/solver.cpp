@@ -68,12 +68,20 @@ constexpr int kAmgMaxCoarse = 2048;   // largest coarsest level (inverted densel
 // Algebraic levels below the degree-1 level (pMG-AMG, Sec. 3).  Level 0 is
 // the degree-1 p-multigrid level itself (matrix-free); level 1 holds one
 // value per element; further levels one per aggregate.
+// Two flexible-CG steps on one level (the K-cycle's coarse correction): the
+// two inner cycles' results, their products with A, the second residual, the
+// combined correction and the scalars (KScal)
+struct KBufs {
+  DevBuf v1, w1, r2, v2, w2, ec, s;
+};
 struct AmgLevel {
   int n = 0;
   double rho = 0;                  // Gershgorin bound of D^-1 A
   DevBuf ptr, col, val, dinv;      // A in compressed rows (level precision)
   DevBuf f, z, t, r, d;            // cycle work
+  KBufs k;                         // K-cycle steps on this level
 };
+constexpr double kKcycleT = 0.25;   // second K-cycle step only while |r2| > 0.25 |rc|
 struct AmgXfer {                   // level l -> l + 1
   int n = 0, nc = 0;
   DevBuf agg, mptr, mem;           // aggregate of each node; members of each aggregate
@@ -84,6 +92,7 @@ struct AmgSet {
   std::vector<AmgXfer> xf;
   DevBuf inv;                      // inverse of the coarsest matrix (dense, level precision)
   DevBuf t0, res0, z0;             // degree-1 work of repeated cycles
+  KBufs k0;                        // the flexible-CG steps on the degree-1 level (amg_top_krylov)
 };
 
 struct Work : SolverWork {
@@ -91,7 +100,7 @@ struct Work : SolverWork {
   double lambda = NAN, ctau = NAN;
   int pc = -1, prec = -1, cheb_degree = 0, coarse_max = 0, nlev = 0, rho_steps = 0;
   double cheb_lo = 0, cheb_hi = 0, coarse_tol = 0;
-  int coarse_amg = 0, amg_coarse_size = 0, amg_cycles = 0;
+  int coarse_amg = 0, amg_coarse_size = 0, amg_cycles = 0, amg_kcycle = 0, amg_top = 0;
   std::unique_ptr<AmgSet> amg;
   int degrees[IPDG_MAX_LEVELS] = {0};
   double rho_in[IPDG_MAX_LEVELS] = {0};
@@ -432,6 +441,11 @@ class Solver {
         throw Error(IPDG_EINVAL, "coarse_persistent must be 0 or 1");
       if (o_.coarse_amg != 0 && o_.coarse_amg != 1) throw Error(IPDG_EINVAL, "coarse_amg must be 0 or 1");
       if (o_.coarse_amg == 1) {
+        if (o_.amg_kcycle_levels < 0) throw Error(IPDG_EINVAL, "amg_kcycle_levels < 0");
+        if (o_.amg_top_krylov != 0 && o_.amg_top_krylov != 1)
+          throw Error(IPDG_EINVAL, "amg_top_krylov must be 0 or 1");
+        if (o_.amg_top_krylov == 1 && o_.amg_cycles != 1)
+          throw Error(IPDG_EINVAL, "amg_top_krylov takes one cycle per step (amg_cycles = 1)");
         if (o_.degrees[o_.n_levels - 1] != 1)
           throw Error(IPDG_EINVAL, "the algebraic levels start below degree 1: the last p-level must be 1");
         if (o_.amg_coarse_size < 1) throw Error(IPDG_EINVAL, "amg_coarse_size < 1");
@@ -617,7 +631,8 @@ class Solver {
       if (w.nlev != o_.n_levels || w.cheb_degree != o_.cheb_degree || w.cheb_lo != o_.cheb_lo ||
           w.cheb_hi != o_.cheb_hi || w.coarse_max != o_.coarse_max_iters ||
           w.coarse_tol != o_.coarse_tol || w.rho_steps != o_.rho_steps || w.coarse_amg != o_.coarse_amg ||
-          (o_.coarse_amg && (w.amg_coarse_size != o_.amg_coarse_size || w.amg_cycles != o_.amg_cycles)))
+          (o_.coarse_amg && (w.amg_coarse_size != o_.amg_coarse_size || w.amg_cycles != o_.amg_cycles ||
+                             w.amg_kcycle != o_.amg_kcycle_levels || w.amg_top != o_.amg_top_krylov)))
         return false;
       for (int l = 0; l < o_.n_levels; ++l)
         if (w.degrees[l] != o_.degrees[l] || w.rho_in[l] != o_.rho[l]) return false;
@@ -692,6 +707,8 @@ class Solver {
     w.coarse_amg = o_.pc == IPDG_PC_PMG ? o_.coarse_amg : 0;
     w.amg_coarse_size = o_.amg_coarse_size;
     w.amg_cycles = o_.amg_cycles;
+    w.amg_kcycle = o_.amg_kcycle_levels;
+    w.amg_top = o_.amg_top_krylov;
     for (int l = 0; l < IPDG_MAX_LEVELS; ++l) {
       w.degrees[l] = o_.degrees[l];
       w.rho_in[l] = o_.rho[l];
@@ -832,6 +849,14 @@ class Solver {
       upload_t(a.dinv, dinv);
       for (DevBuf* b : {&a.t, &a.r, &a.d}) b->ensure(a.n * w8);
     }
+    // K-cycle corrections: level l < amg_kcycle_levels whose next level is
+    // not the coarsest corrects from level l + 1 by two flexible-CG steps
+    auto kbufs = [&](KBufs& k, size_t n) {
+      for (DevBuf* b : {&k.v1, &k.w1, &k.r2, &k.v2, &k.w2, &k.ec}) b->ensure(n * w8);
+      k.s.ensure(sizeof(KScal));
+    };
+    for (int l = 0; l < o_.amg_kcycle_levels && l + 2 < L; ++l) kbufs(A->lv[l + 1].k, A->lv[l + 1].n);
+    if (o_.amg_top_krylov) kbufs(A->k0, v.n);
     // transfers: degree-1 nodes -> elements (node j of element j / Np), then
     // the aggregates
     A->xf.resize(L - 1);
@@ -1055,11 +1080,11 @@ class Solver {
     }
   }
 
-  void level_ax(const Level& v, const void* x, void* y) {
+  void level_ax(const Level& v, const void* x, void* y, const int* skip = nullptr) {
     ElemArgs a = elem_args(m_, v.N, v.kind, lambda_, v.ctau);
     a.x = x;
     a.y = y;
-    a.skip = outer_done();
+    a.skip = skip ? skip : outer_done();
     op_ax(v.N, v.kind, a);
   }
 
@@ -1067,81 +1092,123 @@ class Solver {
   // from zero or from z; apply(x, y) is y = A x on the level
   template <typename Apply>
   void cheb_smooth(bool fp32, double rho_l, size_t n, const void* dinv, void* d, void* r, void* t, const void* f,
-                   void* z, bool from_zero, Apply apply) {
+                   void* z, bool from_zero, const int* skip, Apply apply) {
     const double lo = o_.cheb_lo * rho_l, hi = o_.cheb_hi * rho_l;
     const double theta = 0.5 * (hi + lo), delta = 0.5 * (hi - lo), sigma = theta / delta;
     double rho = 1.0 / sigma;
     if (from_zero) {
-      op_cheb(fp32, 0, f, nullptr, dinv, z, d, r, 1.0 / theta, 0, 0, n, outer_done());
+      op_cheb(fp32, 0, f, nullptr, dinv, z, d, r, 1.0 / theta, 0, 0, n, skip);
     } else {
       apply(z, t);
-      op_cheb(fp32, 1, f, t, dinv, z, d, r, 1.0 / theta, 0, 0, n, outer_done());
+      op_cheb(fp32, 1, f, t, dinv, z, d, r, 1.0 / theta, 0, 0, n, skip);
     }
     for (int k = 1; k < o_.cheb_degree; ++k) {
       const double rho_new = 1.0 / (2.0 * sigma - rho);
       apply(d, t);
-      op_cheb(fp32, 2, nullptr, t, dinv, z, d, r, 0, rho_new * rho, 2.0 * rho_new / delta, n, outer_done());
+      op_cheb(fp32, 2, nullptr, t, dinv, z, d, r, 0, rho_new * rho, 2.0 * rho_new / delta, n, skip);
       rho = rho_new;
     }
   }
 
-  void smooth(const Level& v, const void* f, void* z, bool from_zero) {
-    cheb_smooth(v.fp32, v.rho, v.n, v.dinv(), v.d.get(), v.r.get(), v.t.get(), f, z, from_zero,
-                [&](const void* x, void* y) { level_ax(v, x, y); });
+  void smooth(const Level& v, const void* f, void* z, bool from_zero, const int* skip = nullptr) {
+    if (!skip) skip = outer_done();
+    cheb_smooth(v.fp32, v.rho, v.n, v.dinv(), v.d.get(), v.r.get(), v.t.get(), f, z, from_zero, skip,
+                [&](const void* x, void* y) { level_ax(v, x, y, skip); });
   }
 
-  void amg_spmv_level(const AmgLevel& a, bool fp32, const void* x, void* y) {
-    IPDG_HIP(amg_spmv(fp32, a.ptr.as<int>(), a.col.as<int>(), a.val.get(), x, y, a.n, outer_done(), s_));
+  void amg_spmv_level(const AmgLevel& a, bool fp32, const void* x, void* y, const int* skip) {
+    IPDG_HIP(amg_spmv(fp32, a.ptr.as<int>(), a.col.as<int>(), a.val.get(), x, y, a.n, skip, s_));
   }
 
-  // One V-cycle of the algebraic hierarchy from zero on level l (0: the
+  // One cycle of the algebraic hierarchy from zero on level l (0: the
   // degree-1 level), the same smoother before and after the coarse
-  // correction, the coarsest level solved by its inverse.
-  void amg_cycle(int l, const void* f, void* z) {
+  // correction, the coarsest level solved by its inverse.  On the first
+  // amg_kcycle_levels levels (while the next level is not the coarsest) the
+  // coarse correction is the K-cycle's two flexible-CG steps on the next
+  // level, each preconditioned by one cycle there (the second skipped when
+  // the first already reduced the coarse residual to 0.25 of its norm);
+  // below, a V-cycle.  Every launch is a no-op while *skip is set.
+  void amg_cycle(int l, const void* f, void* z, const int* skip) {
     AmgSet& A = *w_->amg;
     const Level& v = w_->lv.back();
     const bool f32 = v.fp32;
     const int L = int(A.sizes.size());
     if (l == L - 1) {
-      IPDG_HIP(amg_dense(f32, A.inv.get(), f, z, A.sizes[l], outer_done(), s_));
+      IPDG_HIP(amg_dense(f32, A.inv.get(), f, z, A.sizes[l], skip, s_));
       return;
     }
     const void* t;
     if (l == 0) {
-      smooth(v, f, z, true);
-      level_ax(v, z, v.t.get());
+      smooth(v, f, z, true, skip);
+      level_ax(v, z, v.t.get(), skip);
       t = v.t.get();
     } else {
       AmgLevel& a = A.lv[l];
-      cheb_smooth(f32, a.rho, a.n, a.dinv.get(), a.d.get(), a.r.get(), a.t.get(), f, z, true,
-                  [&](const void* x, void* y) { amg_spmv_level(a, f32, x, y); });
-      amg_spmv_level(a, f32, z, a.t.get());
+      cheb_smooth(f32, a.rho, a.n, a.dinv.get(), a.d.get(), a.r.get(), a.t.get(), f, z, true, skip,
+                  [&](const void* x, void* y) { amg_spmv_level(a, f32, x, y, skip); });
+      amg_spmv_level(a, f32, z, a.t.get(), skip);
       t = a.t.get();
     }
     AmgLevel& c = A.lv[l + 1];
     const AmgXfer& x = A.xf[l];
-    IPDG_HIP(amg_restrict(f32, x.mptr.as<int>(), x.mem.as<int>(), f, t, c.f.get(), x.nc, outer_done(), s_));
-    amg_cycle(l + 1, c.f.get(), c.z.get());
-    IPDG_HIP(amg_prolong(f32, x.agg.as<int>(), c.z.get(), z, x.n, outer_done(), s_));
+    IPDG_HIP(amg_restrict(f32, x.mptr.as<int>(), x.mem.as<int>(), f, t, c.f.get(), x.nc, skip, s_));
+    const void* ec = c.z.get();
+    if (l < o_.amg_kcycle_levels && l + 2 < L) {
+      krylov_step(l + 1, c.f.get(), c.k.ec.get(), skip);
+      ec = c.k.ec.get();
+    } else {
+      amg_cycle(l + 1, c.f.get(), c.z.get(), skip);
+    }
+    IPDG_HIP(amg_prolong(f32, x.agg.as<int>(), ec, z, x.n, skip, s_));
     if (l == 0) {
-      smooth(v, f, z, false);
+      smooth(v, f, z, false, skip);
     } else {
       AmgLevel& a = A.lv[l];
-      cheb_smooth(f32, a.rho, a.n, a.dinv.get(), a.d.get(), a.r.get(), a.t.get(), f, z, false,
-                  [&](const void* x, void* y) { amg_spmv_level(a, f32, x, y); });
+      cheb_smooth(f32, a.rho, a.n, a.dinv.get(), a.d.get(), a.r.get(), a.t.get(), f, z, false, skip,
+                  [&](const void* x, void* y) { amg_spmv_level(a, f32, x, y, skip); });
     }
   }
 
-  // amg_cycles V-cycles on the degree-1 level: the first from zero, each
+  // Approximate solution of A_lk e = rc on level lk (0: the degree-1 level)
+  // by two flexible-CG steps from zero, each preconditioned by one cycle on
+  // that level; the second step is skipped (device flag) once the first
+  // reduced |rc| to 0.25 of its norm or less.
+  void krylov_step(int lk, const void* rc, void* e, const int* skip) {
+    AmgSet& A = *w_->amg;
+    const Level& v = w_->lv.back();
+    const bool f32 = v.fp32;
+    KBufs& B = lk == 0 ? A.k0 : A.lv[lk].k;
+    const int n = A.sizes[lk];
+    auto apply = [&](const void* x, void* y, const int* sk) {
+      if (lk == 0) level_ax(v, x, y, sk);
+      else amg_spmv_level(A.lv[lk], f32, x, y, sk);
+    };
+    KScal* S = B.s.as<KScal>();
+    const int* second = &S->flag;
+    amg_cycle(lk, rc, B.v1.get(), skip);
+    apply(B.v1.get(), B.w1.get(), skip);
+    IPDG_HIP(amg_kdot1(f32, B.v1.get(), rc, B.w1.get(), n, S, skip, s_));
+    IPDG_HIP(amg_kres(f32, rc, B.w1.get(), B.r2.get(), n, S, kKcycleT * kKcycleT, skip, s_));
+    amg_cycle(lk, B.r2.get(), B.v2.get(), second);
+    apply(B.v2.get(), B.w2.get(), second);
+    IPDG_HIP(amg_kdot2(f32, B.v2.get(), B.w1.get(), B.w2.get(), B.r2.get(), n, S, s_));
+    IPDG_HIP(amg_kcomb(f32, B.v1.get(), B.v2.get(), e, n, S, skip, s_));
+  }
+
+  // amg_cycles cycles on the degree-1 level: the first from zero, each
   // further one on the residual of the current x (iterative refinement)
   void amg_solve(const void* f, void* x) {
     AmgSet& A = *w_->amg;
     const Level& v = w_->lv.back();
-    amg_cycle(0, f, x);
+    if (o_.amg_top_krylov) {
+      krylov_step(0, f, x, outer_done());
+      return;
+    }
+    amg_cycle(0, f, x, outer_done());
     for (int c = 1; c < o_.amg_cycles; ++c) {
       level_ax(v, x, A.t0.get());
       IPDG_HIP(amg_sub(v.fp32, f, A.t0.get(), A.res0.get(), v.n, outer_done(), s_));
-      amg_cycle(0, A.res0.get(), A.z0.get());
+      amg_cycle(0, A.res0.get(), A.z0.get(), outer_done());
       IPDG_HIP(amg_add(v.fp32, x, A.z0.get(), v.n, outer_done(), s_));
     }
   }
@@ -1351,6 +1418,7 @@ class Solver {
     if (!info) return;
     std::memset(info, 0, sizeof(*info));
     info->coarse_iters = citers;
+    info->precond_bytes = (int64_t)precond_bytes();
     if (w_->amg) {
       info->amg_levels = int(w_->amg->sizes.size());
       for (int l = 0; l < info->amg_levels && l < IPDG_AMG_MAX_LEVELS; ++l) info->amg_n[l] = w_->amg->sizes[l];
@@ -1361,6 +1429,29 @@ class Solver {
     for (size_t l = 0; l < w_->lv.size() && l < IPDG_MAX_LEVELS; ++l) info->rho_used[l] = w_->lv[l].rho;
     info->setup_ms = w_->setup_ms;
     info->solve_ms = solve_ms;
+  }
+
+  // device bytes of the p-multigrid levels and the algebraic hierarchy
+  size_t precond_bytes() const {
+    const Work& w = *w_;
+    size_t b = 0;
+    for (const Level& v : w.lv)
+      for (const DevBuf* d : {&v.dinv64, &v.dinv32, &v.f, &v.z, &v.r, &v.d, &v.t, &v.cr, &v.cr2, &v.cz, &v.cp,
+                              &v.cp2, &v.cs2, &v.cAp, &v.cw2})
+        b += d->size();
+    if (w.amg) {
+      const AmgSet& A = *w.amg;
+      for (const DevBuf* d : {&A.inv, &A.t0, &A.res0, &A.z0, &A.k0.v1, &A.k0.w1, &A.k0.r2, &A.k0.v2, &A.k0.w2,
+                              &A.k0.ec, &A.k0.s})
+        b += d->size();
+      for (const AmgLevel& a : A.lv)
+        for (const DevBuf* d : {&a.ptr, &a.col, &a.val, &a.dinv, &a.f, &a.z, &a.t, &a.r, &a.d, &a.k.v1, &a.k.w1,
+                                &a.k.r2, &a.k.v2, &a.k.w2, &a.k.ec, &a.k.s})
+          b += d->size();
+      for (const AmgXfer& x : A.xf)
+        for (const DevBuf* d : {&x.agg, &x.mptr, &x.mem}) b += d->size();
+    }
+    return b;
   }
 
   ipdg_mesh_s* m_;

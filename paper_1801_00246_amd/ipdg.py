@@ -39,20 +39,22 @@ class SolveOpts(C.Structure):
                 ("rho", C.c_double * MAX_LEVELS), ("rho_steps", C.c_int),
                 ("coarse_tol", C.c_double), ("coarse_max_iters", C.c_int),
                 ("reliable_drop", C.c_double), ("coarse_persistent", C.c_int),
-                ("coarse_amg", C.c_int), ("amg_coarse_size", C.c_int), ("amg_cycles", C.c_int)]
+                ("coarse_amg", C.c_int), ("amg_coarse_size", C.c_int), ("amg_cycles", C.c_int),
+                ("amg_kcycle_levels", C.c_int), ("amg_top_krylov", C.c_int)]
 
 
 class SolveInfo(C.Structure):
     _fields_ = [("iters", C.c_int), ("relres", C.c_double), ("restarts", C.c_int),
                 ("rho_used", C.c_double * MAX_LEVELS), ("setup_ms", C.c_double),
                 ("solve_ms", C.c_double), ("coarse_iters", C.c_int),
-                ("amg_levels", C.c_int), ("amg_n", C.c_int * AMG_MAX_LEVELS)]
+                ("amg_levels", C.c_int), ("amg_n", C.c_int * AMG_MAX_LEVELS),
+                ("precond_bytes", C.c_int64)]
 
     def as_dict(self):
         return {"iters": self.iters, "relres": self.relres, "restarts": self.restarts,
                 "rho_used": list(self.rho_used), "setup_ms": self.setup_ms,
                 "solve_ms": self.solve_ms, "coarse_iters": self.coarse_iters,
-                "amg_sizes": list(self.amg_n)[:self.amg_levels]}
+                "amg_sizes": list(self.amg_n)[:self.amg_levels], "precond_bytes": self.precond_bytes}
 
 
 _lib = None

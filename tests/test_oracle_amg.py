@@ -135,3 +135,83 @@ def test_pmg_with_amg_coarse_level_solves():
         assert rel <= 1e-8
     _, it_j, _, _ = S.pcg(A, b, S.jacobi(A), tol=1e-8)
     assert its[2] <= its[1] < it_j / 10
+
+
+def test_kcycle_without_krylov_levels_is_the_vcycle():
+    m, A, amg = mesh_and_amg()
+    amg.kcycle_levels = 0
+    r = np.random.default_rng(5).standard_normal(A.shape[0])
+    assert np.array_equal(amg.cycle(0, r), amg.vcycle(0, r))
+
+
+def test_krylov_correction_is_the_a_norm_projection_on_the_krylov_space():
+    """With a fixed SPD preconditioner B in place of the inner cycle, the two
+    flexible-CG steps give the A-norm best approximation of A^-1 rc in
+    span{B rc, B A B rc}: solved here from the 2 x 2 Galerkin system."""
+    m, A, amg = mesh_and_amg(n=10)
+    l = 1
+    Al = amg.A[l].toarray()
+    rng = np.random.default_rng(6)
+    d = 1.0 / np.diag(Al) * (1.0 + 0.5 * rng.random(Al.shape[0]))   # SPD diagonal B, not A's inverse
+    amg.cycle = lambda lev, q: d * q
+    rc = rng.standard_normal(Al.shape[0])
+    amg.kcycle_t = 0.0                                                # always take both steps
+    e = amg.krylov_correction(l, rc)
+    V = np.stack([d * rc, d * (Al @ (d * rc))], axis=1)
+    c = np.linalg.solve(V.T @ Al @ V, V.T @ rc)
+    assert np.linalg.norm(e - V @ c) <= 1e-12 * np.linalg.norm(V @ c)
+
+
+def test_krylov_correction_with_an_exact_inner_solve_is_exact():
+    m, A, amg = mesh_and_amg(n=10)
+    l = 1
+    Al = amg.A[l].toarray()
+    Ainv = np.linalg.inv(Al)
+    amg.cycle = lambda lev, q: Ainv @ q
+    rc = np.random.default_rng(7).standard_normal(Al.shape[0])
+    e = amg.krylov_correction(l, rc)                                 # early exit after one step
+    assert np.linalg.norm(e - Ainv @ rc) <= 1e-10 * np.linalg.norm(Ainv @ rc)
+
+
+def test_kcycle_preconditions_better_than_the_vcycle():
+    m, A, amg = mesh_and_amg(n=24, lam=0.0)
+    b = np.random.default_rng(8).standard_normal(A.shape[0])
+    _, it_v, _, _ = S.pcg(A, b, lambda r: amg.vcycle(0, r), tol=1e-8)
+    _, it_k, rel, _ = S.pcg(A, b, lambda r: amg.cycle(0, r), tol=1e-8, flexible=True)
+    assert rel <= 1e-8
+    assert it_k < it_v
+
+
+def test_top_krylov_step_on_the_degree_one_level():
+    """The two flexible-CG steps on the degree-1 level itself (each
+    preconditioned by one AMG cycle) give the A-norm best approximation over
+    the span of their two preconditioned directions (a linear SPD stand-in
+    for the cycle, as above), and in p-multigrid a solve needs no more
+    iterations than with one cycle."""
+    m, A, amg = mesh_and_amg(n=10)
+    Ad = A.toarray()
+    rng = np.random.default_rng(9)
+    d = 1.0 / np.diag(Ad) * (1.0 + 0.5 * rng.random(Ad.shape[0]))
+    cyc = amg.cycle
+    amg.cycle = lambda lev, q: d * q
+    amg.kcycle_t = 0.0
+    rc = rng.standard_normal(Ad.shape[0])
+    e = amg.krylov_correction(0, rc)
+    V = np.stack([d * rc, d * (Ad @ (d * rc))], axis=1)
+    c = np.linalg.solve(V.T @ Ad @ V, V.T @ rc)
+    assert np.linalg.norm(e - V @ c) <= 1e-12 * np.linalg.norm(V @ c)
+    amg.cycle = cyc
+    msh = synth.square_mesh(10, jitter=0.2, seed=5)
+    mk = OracleMesh(msh.VX, msh.VY, msh.EToV, msh.EToB, 4)
+    A4 = assemble(mk, 0.0, 25.0)
+    rho = []
+    for N in (4, 2, 1):
+        mN = OracleMesh(msh.VX, msh.VY, msh.EToV, msh.EToB, N)
+        rho.append(S.lanczos_rho(assemble(mN, 0.0, 25.0 * ((N + 1) / 5) ** 2)))
+    b = np.random.default_rng(3).standard_normal(A4.shape[0])
+    its = {}
+    for top in (False, True):
+        B = S.PMG(msh, [4, 2, 1], 0.0, 25.0, rho, coarse_amg=True, amg_coarse_size=16, amg_top_krylov=top)
+        _, its[top], rel, _ = S.pcg(A4, b, B, tol=1e-8, flexible=True)
+        assert rel <= 1e-8
+    assert its[True] <= its[False]
