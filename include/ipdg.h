@@ -244,6 +244,42 @@ ipdg_status ipdg_helmholtz_solve_batch(int nb, const ipdg_mesh* meshes, const do
 ipdg_status ipdg_kappa_grad(ipdg_mesh mesh, double tau, const double* u, const double* w,
                             double* dLdkappa, void* hip_stream);
 
+/* ---- Around the elliptic solves of the algebraic splitting scheme (Sec. 2.2,
+ * Eq. INS_TD_3); device FP64 vectors of K*Np values, asynchronous on
+ * hip_stream, outputs must not overlap inputs.  Boundary faces take the
+ * mesh's flags as velocity conditions: on Dirichlet faces u* = g_D and
+ * p* = p-, on Neumann (outflow) faces u* = u- and p* = 0 (Sec. 2.1). ---- */
+
+/* DG gradient with the central flux p* = {p} (Sec. 2.1, Eq. INS_SD_4_1):
+ * (gx, gy) = G p. */
+ipdg_status ipdg_grad(ipdg_mesh mesh, const double* p, double* gx, double* gy, void* hip_stream);
+
+/* DG divergence with the central flux u* = {u} (Eq. INS_SD_4_2):
+ * out = D (u, v).  gu, gv: Dirichlet data g_D as nodal fields (only their
+ * values on Dirichlet face nodes are read), or NULL for g_D = 0. */
+ipdg_status ipdg_div(ipdg_mesh mesh, const double* u, const double* v, const double* gu,
+                     const double* gv, double* out, void* hip_stream);
+
+/* Right-hand sides of the two solves, mass-weighted for the SIPDG operator
+ * (lambda M - Lap_IPDG) of ipdg_apply / ipdg_pcg_solve:
+ *   velocity (Eq. INS_TD_3_2), lambda = gamma / (nu dt), per component:
+ *     (bu, bv) = M (U^ / (nu dt) - G sigmaP / nu);
+ *   pressure increment (Eq. INS_TD_3_3), lambda = 0 on a mesh with the
+ *     swapped boundary flags (velocity Dirichlet faces are pressure Neumann
+ *     faces and vice versa):  b = -(gamma / dt) M D (U^^). */
+ipdg_status ipdg_ins_velocity_rhs(ipdg_mesh mesh, double nu, double dt, const double* uhat,
+                                  const double* vhat, const double* sigma_p, double* bu, double* bv,
+                                  void* hip_stream);
+ipdg_status ipdg_ins_pressure_rhs(ipdg_mesh mesh, double gamma, double dt, const double* u,
+                                  const double* v, const double* gu, const double* gv, double* b,
+                                  void* hip_stream);
+
+/* Correction (Eq. INS_TD_3_4): u_out = u - (dt / gamma) Gx dp,
+ * v_out = v - (dt / gamma) Gy dp, p_out = dp + sigma_p. */
+ipdg_status ipdg_ins_correct(ipdg_mesh mesh, double gamma, double dt, const double* u, const double* v,
+                             const double* dp, const double* sigma_p, double* u_out, double* v_out,
+                             double* p_out, void* hip_stream);
+
 /* Host-only validation of a mesh, without any device use: the same checks
  * and face matching as ipdg_mesh_create.  EToE (neighbour element, -1 on a
  * boundary face) and EToF (neighbour's face index, -1 on a boundary face)

@@ -28,7 +28,7 @@ FLAGS = [
 ]
 HOST_SOURCES = ["refelem.cpp", "mesh_host.cpp", "ops_table.cpp", "mesh.cpp", "dispatch.cpp",
                 "amg_host.cpp", "solver.cpp", "abi.cpp"]
-DEVICE_SOURCES = ["blas.hip", "noalloc.hip", "probe.hip", "amg.hip"]
+DEVICE_SOURCES = ["blas.hip", "noalloc.hip", "probe.hip", "amg.hip", "gradiv.hip"]
 DEGREES = range(1, 9)
 
 

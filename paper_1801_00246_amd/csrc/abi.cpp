@@ -4,6 +4,7 @@
 #include <cstring>
 #include <string>
 
+#include "gradiv.hpp"
 #include "handle.hpp"
 #include "noalloc.hpp"
 #include "probe.hpp"
@@ -382,6 +383,130 @@ ipdg_status ipdg_helmholtz_solve_batch(int nb, const ipdg_mesh* meshes, const do
     }
     return ipdg::solve_batch(nb, meshes, lambdas, tau, b, x, tol, o, iters, relres,
                              static_cast<hipStream_t>(hip_stream));
+  });
+}
+
+namespace {
+
+ipdg::GradArgs grad_args(ipdg_mesh mesh) {
+  ipdg::GradArgs a;
+  a.geo = mesh->geo64.as<double>();
+  a.conn = mesh->conn.as<ipdg::Conn>();
+  a.ops = static_cast<const double*>(ipdg::device_ops(mesh->host.N, ipdg::Kind::F64));
+  a.K = mesh->host.K;
+  return a;
+}
+
+ipdg::DivArgs div_args(ipdg_mesh mesh) {
+  ipdg::DivArgs a;
+  a.geo = mesh->geo64.as<double>();
+  a.conn = mesh->conn.as<ipdg::Conn>();
+  a.ops = static_cast<const double*>(ipdg::device_ops(mesh->host.N, ipdg::Kind::F64));
+  a.K = mesh->host.K;
+  return a;
+}
+
+}  // namespace
+
+ipdg_status ipdg_grad(ipdg_mesh mesh, const double* p, double* gx, double* gy, void* hip_stream) {
+  return guarded([&]() -> ipdg_status {
+    if (!mesh) return fail(IPDG_EINVAL, "mesh is null");
+    if (mesh->host.K == 0) return IPDG_OK;
+    if (!p || !gx || !gy) return fail(IPDG_EINVAL, "null vector");
+    DeviceGuard dg(mesh);
+    ipdg::GradArgs a = grad_args(mesh);
+    a.p = p;
+    a.out_x = gx;
+    a.out_y = gy;
+    IPDG_HIP(ipdg::grad_apply(mesh->host.N, a, static_cast<hipStream_t>(hip_stream)));
+    return IPDG_OK;
+  });
+}
+
+ipdg_status ipdg_div(ipdg_mesh mesh, const double* u, const double* v, const double* gu,
+                     const double* gv, double* out, void* hip_stream) {
+  return guarded([&]() -> ipdg_status {
+    if (!mesh) return fail(IPDG_EINVAL, "mesh is null");
+    if (mesh->host.K == 0) return IPDG_OK;
+    if (!u || !v || !out) return fail(IPDG_EINVAL, "null vector");
+    DeviceGuard dg(mesh);
+    ipdg::DivArgs a = div_args(mesh);
+    a.u = u;
+    a.v = v;
+    a.gu = gu;
+    a.gv = gv;
+    a.out = out;
+    IPDG_HIP(ipdg::div_apply(mesh->host.N, a, static_cast<hipStream_t>(hip_stream)));
+    return IPDG_OK;
+  });
+}
+
+ipdg_status ipdg_ins_velocity_rhs(ipdg_mesh mesh, double nu, double dt, const double* uhat,
+                                  const double* vhat, const double* sigma_p, double* bu, double* bv,
+                                  void* hip_stream) {
+  return guarded([&]() -> ipdg_status {
+    if (!mesh) return fail(IPDG_EINVAL, "mesh is null");
+    if (!(nu > 0.0) || !(dt > 0.0)) return fail(IPDG_EINVAL, "nu and dt must be positive");
+    if (mesh->host.K == 0) return IPDG_OK;
+    if (!uhat || !vhat || !sigma_p || !bu || !bv) return fail(IPDG_EINVAL, "null vector");
+    DeviceGuard dg(mesh);
+    ipdg::GradArgs a = grad_args(mesh);
+    a.p = sigma_p;
+    a.base_x = uhat;
+    a.base_y = vhat;
+    a.a_base = 1.0 / (nu * dt);
+    a.a_grad = -1.0 / nu;
+    a.mass = true;
+    a.out_x = bu;
+    a.out_y = bv;
+    IPDG_HIP(ipdg::grad_apply(mesh->host.N, a, static_cast<hipStream_t>(hip_stream)));
+    return IPDG_OK;
+  });
+}
+
+ipdg_status ipdg_ins_pressure_rhs(ipdg_mesh mesh, double gamma, double dt, const double* u,
+                                  const double* v, const double* gu, const double* gv, double* b,
+                                  void* hip_stream) {
+  return guarded([&]() -> ipdg_status {
+    if (!mesh) return fail(IPDG_EINVAL, "mesh is null");
+    if (!(gamma > 0.0) || !(dt > 0.0)) return fail(IPDG_EINVAL, "gamma and dt must be positive");
+    if (mesh->host.K == 0) return IPDG_OK;
+    if (!u || !v || !b) return fail(IPDG_EINVAL, "null vector");
+    DeviceGuard dg(mesh);
+    ipdg::DivArgs a = div_args(mesh);
+    a.u = u;
+    a.v = v;
+    a.gu = gu;
+    a.gv = gv;
+    a.out = b;
+    a.scale = -gamma / dt;
+    a.mass = true;
+    IPDG_HIP(ipdg::div_apply(mesh->host.N, a, static_cast<hipStream_t>(hip_stream)));
+    return IPDG_OK;
+  });
+}
+
+ipdg_status ipdg_ins_correct(ipdg_mesh mesh, double gamma, double dt, const double* u, const double* v,
+                             const double* dp, const double* sigma_p, double* u_out, double* v_out,
+                             double* p_out, void* hip_stream) {
+  return guarded([&]() -> ipdg_status {
+    if (!mesh) return fail(IPDG_EINVAL, "mesh is null");
+    if (!(gamma > 0.0) || !(dt > 0.0)) return fail(IPDG_EINVAL, "gamma and dt must be positive");
+    if (mesh->host.K == 0) return IPDG_OK;
+    if (!u || !v || !dp || !sigma_p || !u_out || !v_out || !p_out) return fail(IPDG_EINVAL, "null vector");
+    DeviceGuard dg(mesh);
+    ipdg::GradArgs a = grad_args(mesh);
+    a.p = dp;
+    a.base_x = u;
+    a.base_y = v;
+    a.a_base = 1.0;
+    a.a_grad = -dt / gamma;
+    a.out_x = u_out;
+    a.out_y = v_out;
+    a.add_p = sigma_p;
+    a.p_out = p_out;
+    IPDG_HIP(ipdg::grad_apply(mesh->host.N, a, static_cast<hipStream_t>(hip_stream)));
+    return IPDG_OK;
   });
 }
 

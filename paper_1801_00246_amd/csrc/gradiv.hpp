@@ -1,0 +1,47 @@
+// DG gradient and divergence with central fluxes (Sec. 2.1, Eq. INS_SD_4_1
+// and INS_SD_4_2) and the element-local steps of the algebraic splitting
+// scheme around its two elliptic solves (Sec. 2.2, Eq. INS_TD_3_2 to
+// INS_TD_3_4); kernels in gradiv.hip, FP64.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "device_common.hpp"
+
+namespace ipdg {
+
+struct GradArgs {
+  const double* p = nullptr;       // pressure-like field
+  const double* base_x = nullptr;  // optional: added fields (a_base times)
+  const double* base_y = nullptr;
+  double* out_x = nullptr;
+  double* out_y = nullptr;
+  double a_base = 0.0, a_grad = 1.0;
+  bool mass = false;               // out = J M (a_base base + a_grad G p) when set
+  const double* add_p = nullptr;   // optional: p_out = p + add_p
+  double* p_out = nullptr;
+  const double* geo = nullptr;     // r_x, s_x, r_y, s_y per element
+  const Conn* conn = nullptr;
+  const double* ops = nullptr;     // FP64 reference operators of the degree
+  int K = 0;
+};
+
+struct DivArgs {
+  const double* u = nullptr;
+  const double* v = nullptr;
+  const double* gu = nullptr;      // Dirichlet data (nodal fields, face nodes used); null = 0
+  const double* gv = nullptr;
+  double* out = nullptr;
+  double scale = 1.0;
+  bool mass = false;               // out = scale J M D (u, v) when set, else scale D (u, v)
+  const double* geo = nullptr;
+  const Conn* conn = nullptr;
+  const double* ops = nullptr;
+  int K = 0;
+};
+
+// out = a_base base + a_grad G p (or J M of it), p_out = p + add_p
+hipError_t grad_apply(int N, const GradArgs& a, hipStream_t s);
+// out = scale D (u, v) (or scale J M D (u, v))
+hipError_t div_apply(int N, const DivArgs& a, hipStream_t s);
+
+}  // namespace ipdg

@@ -79,6 +79,11 @@ _SIGS = {
     "ipdg_helmholtz_solve_batch": (C.c_int, [C.c_int, _P, _P, C.c_double, _P, _P, C.c_double,
                                              C.POINTER(SolveOpts), _P, _P, _P]),
     "ipdg_kappa_grad": (C.c_int, [_P, C.c_double, _P, _P, _P, _P]),
+    "ipdg_grad": (C.c_int, [_P, _P, _P, _P, _P]),
+    "ipdg_div": (C.c_int, [_P, _P, _P, _P, _P, _P, _P]),
+    "ipdg_ins_velocity_rhs": (C.c_int, [_P, C.c_double, C.c_double, _P, _P, _P, _P, _P, _P]),
+    "ipdg_ins_pressure_rhs": (C.c_int, [_P, C.c_double, C.c_double, _P, _P, _P, _P, _P, _P]),
+    "ipdg_ins_correct": (C.c_int, [_P, C.c_double, C.c_double, _P, _P, _P, _P, _P, _P, _P, _P]),
     "ipdg_mesh_check": (C.c_int, [C.c_int, C.c_int, _P, _P, C.c_int, _P, _P, _P, _P]),
     "ipdg_reference_element": (C.c_int, [C.c_int, _P, _P, _P, _P, _P, _P]),
     "ipdg_ax_variant_get": (C.c_int, [C.c_int, C.c_int, C.POINTER(C.c_int)]),
@@ -344,6 +349,54 @@ class Mesh:
         check(lib().ipdg_precond_apply(self._h, float(lam), float(tau), C.byref(o), pr, pz,
                                        C.byref(info), _stream(stream)))
         return z, info.as_dict()
+
+    # ---- around the elliptic solves of the splitting scheme (FP64) ----
+    def _vec(self, t, name):
+        import torch
+        return _dev_vec(t, self.ndof, (torch.float64,), name)
+
+    def _opt(self, t, name):
+        return self._vec(t, name) if t is not None else None
+
+    def grad(self, p, stream=None):
+        """(G_x p, G_y p), central fluxes (Eq. INS_SD_4_1)."""
+        import torch
+        gx, gy = torch.empty_like(p), torch.empty_like(p)
+        check(lib().ipdg_grad(self._h, self._vec(p, "p"), self._vec(gx, "gx"), self._vec(gy, "gy"),
+                              _stream(stream)))
+        return gx, gy
+
+    def div(self, u, v, gu=None, gv=None, stream=None):
+        """D (u, v), central fluxes, Dirichlet data gu, gv (Eq. INS_SD_4_2)."""
+        import torch
+        out = torch.empty_like(u)
+        check(lib().ipdg_div(self._h, self._vec(u, "u"), self._vec(v, "v"), self._opt(gu, "gu"),
+                             self._opt(gv, "gv"), self._vec(out, "out"), _stream(stream)))
+        return out
+
+    def ins_velocity_rhs(self, nu, dt, uhat, vhat, sigma_p, stream=None):
+        import torch
+        bu, bv = torch.empty_like(uhat), torch.empty_like(vhat)
+        check(lib().ipdg_ins_velocity_rhs(self._h, float(nu), float(dt), self._vec(uhat, "uhat"),
+                                          self._vec(vhat, "vhat"), self._vec(sigma_p, "sigma_p"),
+                                          self._vec(bu, "bu"), self._vec(bv, "bv"), _stream(stream)))
+        return bu, bv
+
+    def ins_pressure_rhs(self, gamma, dt, u, v, gu=None, gv=None, stream=None):
+        import torch
+        b = torch.empty_like(u)
+        check(lib().ipdg_ins_pressure_rhs(self._h, float(gamma), float(dt), self._vec(u, "u"), self._vec(v, "v"),
+                                          self._opt(gu, "gu"), self._opt(gv, "gv"), self._vec(b, "b"),
+                                          _stream(stream)))
+        return b
+
+    def ins_correct(self, gamma, dt, u, v, dp, sigma_p, stream=None):
+        import torch
+        uo, vo, po = torch.empty_like(u), torch.empty_like(v), torch.empty_like(dp)
+        check(lib().ipdg_ins_correct(self._h, float(gamma), float(dt), self._vec(u, "u"), self._vec(v, "v"),
+                                     self._vec(dp, "dp"), self._vec(sigma_p, "sigma_p"), self._vec(uo, "u_out"),
+                                     self._vec(vo, "v_out"), self._vec(po, "p_out"), _stream(stream)))
+        return uo, vo, po
 
     def kappa_grad(self, u, w, tau=0.0, stream=None):
         import torch

@@ -1,0 +1,118 @@
+"""GPU parity of the DG gradient and divergence (Sec. 2.1, Eq. INS_SD_4_1 and
+INS_SD_4_2) and of the splitting step's right-hand sides and correction
+(Sec. 2.2, Eq. INS_TD_3_2 to INS_TD_3_4) against the oracle's matrices,
+through the C ABI, for every degree and boundary mix; and the projection
+step run on the GPU (pressure right-hand side, PCG on the swapped-boundary
+mesh, correction) against the oracle's with a direct solve."""
+import numpy as np
+import pytest
+
+import synth
+from oracle.assemble import OracleMesh, assemble
+from oracle.gradiv import GradDiv, swapped_bc
+
+torch = pytest.importorskip("torch")
+P = pytest.importorskip("paper_1801_00246_amd")
+
+pytestmark = pytest.mark.gpu
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to("cuda")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def rel(a, b):
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+
+
+@pytest.mark.parametrize("bc", ["dirichlet", "neumann", "mixed"])
+@pytest.mark.parametrize("N", [1, 2, 3, 4, 5, 6, 7, 8])
+def test_grad_div_match_oracle(N, bc):
+    msh = synth.permuted(synth.square_mesh(4 if N >= 6 else 6, jitter=0.2, seed=N, bc=bc), seed=N + 1)
+    m = OracleMesh(msh.VX, msh.VY, msh.EToV, msh.EToB, N)
+    gd = GradDiv(m)
+    rng = np.random.default_rng(N)
+    n = m.K * m.Np
+    p, u, v, gu, gv = (rng.standard_normal(n) for _ in range(5))
+    g = P.Mesh.from_synth(N, msh)
+    gx, gy = g.grad(dev(p))
+    ox, oy = gd.grad(p)
+    d = g.div(dev(u), dev(v), dev(gu), dev(gv))
+    d0 = g.div(dev(u), dev(v))
+    e = (rel(host(gx), ox), rel(host(gy), oy), rel(host(d), gd.div(u, v, gu, gv)), rel(host(d0), gd.div(u, v)))
+    print(f"N={N} {bc}: rel errors grad {e[0]:.1e} {e[1]:.1e}, div {e[2]:.1e}, div (g_D = 0) {e[3]:.1e}")
+    assert max(e) <= 1e-12
+    g.close()
+
+
+@pytest.mark.parametrize("N", [2, 5])
+def test_splitting_rhs_and_correction_match_oracle(N):
+    msh = synth.permuted(synth.square_mesh(5, jitter=0.2, seed=30, bc="mixed"), seed=31)
+    m = OracleMesh(msh.VX, msh.VY, msh.EToV, msh.EToB, N)
+    gd = GradDiv(m)
+    rng = np.random.default_rng(32)
+    n = m.K * m.Np
+    uh, vh, sp_, dp, gu, gv = (rng.standard_normal(n) for _ in range(6))
+    nu, dt, gamma = 0.01, 0.05, 1.5
+    g = P.Mesh.from_synth(N, msh)
+    bu, bv = g.ins_velocity_rhs(nu, dt, dev(uh), dev(vh), dev(sp_))
+    sx, sy = gd.grad(sp_)
+    ru = gd.M @ (uh / (nu * dt) - sx / nu)
+    rv = gd.M @ (vh / (nu * dt) - sy / nu)
+    b = g.ins_pressure_rhs(gamma, dt, dev(uh), dev(vh), dev(gu), dev(gv))
+    rb = gd.pressure_rhs(gamma, dt, uh, vh, gu, gv)
+    uo, vo, po = g.ins_correct(gamma, dt, dev(uh), dev(vh), dev(dp), dev(sp_))
+    cu, cv, cp = gd.correct(gamma, dt, uh, vh, dp, sp_)
+    errs = [rel(host(bu), ru), rel(host(bv), rv), rel(host(b), rb), rel(host(uo), cu), rel(host(vo), cv),
+            rel(host(po), cp)]
+    print(f"N={N}: " + " ".join(f"{x:.1e}" for x in errs))
+    assert max(errs) <= 1e-12
+    g.close()
+
+
+@pytest.mark.parametrize("N", [2, 3])
+def test_projection_step_on_the_gpu(N):
+    """U^^ = grad(phi) + curl(psi) on the unit square with outflow boundaries
+    (pressure Dirichlet p = 0; phi = 0 there): the GPU's pressure right-hand
+    side, PCG solve on the swapped-boundary mesh and correction agree with
+    the oracle's (direct solve), and recover curl(psi) and phi."""
+    msh = synth.square_mesh(12, jitter=0.1, seed=8, bc="neumann")
+    m = OracleMesh(msh.VX, msh.VY, msh.EToV, msh.EToB, N)
+    mp = OracleMesh(msh.VX, msh.VY, msh.EToV, swapped_bc(msh.EToB), N)
+    x, y = (a.ravel() for a in m.node_coords())
+    pi = np.pi
+    phi = np.sin(pi * x) * np.sin(pi * y)
+    cx = -2 * pi * np.cos(pi * x) * np.sin(2 * pi * y)
+    cy = pi * np.sin(pi * x) * np.cos(2 * pi * y)
+    uh = pi * np.cos(pi * x) * np.sin(pi * y) + cx
+    vh = pi * np.sin(pi * x) * np.cos(pi * y) + cy
+    gamma, dt = 1.5, 0.1
+    ctau = float((N + 1) ** 2)
+    gd = GradDiv(m)
+    import scipy.sparse.linalg as spla
+    bo = gd.pressure_rhs(gamma, dt, uh, vh)
+    dpo = spla.spsolve(assemble(mp, 0.0, ctau).tocsc(), bo)
+    uo, vo, po = gd.correct(gamma, dt, uh, vh, dpo, np.zeros_like(dpo))
+    g = P.Mesh.from_synth(N, msh)
+    gp = P.Mesh(N, msh.VX, msh.VY, msh.EToV, swapped_bc(msh.EToB))
+    b = g.ins_pressure_rhs(gamma, dt, dev(uh), dev(vh))
+    dp, info, st = gp.pcg(b, tau=ctau, tol=1e-13, opts=P.default_opts(pc=P.PC_PMG))
+    assert st == 0
+    u, v, p = g.ins_correct(gamma, dt, dev(uh), dev(vh), dp, torch.zeros_like(dp))
+    u, v, p = host(u), host(v), host(p)
+    errs = (rel(u, uo), rel(v, vo), rel(p, po))
+    M = gd.M
+    nrm = lambda a: np.sqrt(a @ (M @ a))
+    eu = np.sqrt(nrm(u - cx) ** 2 + nrm(v - cy) ** 2) / np.sqrt(nrm(cx) ** 2 + nrm(cy) ** 2)
+    ep = nrm(p - (gamma / dt) * phi) / nrm((gamma / dt) * phi)
+    print(f"N={N}: GPU vs oracle {errs[0]:.1e} {errs[1]:.1e} {errs[2]:.1e}; solenoidal part {eu:.2e}, "
+          f"potential {ep:.2e}; {info['iters']} PCG iterations")
+    assert max(errs) <= 1e-10
+    assert eu < 2e-2 and ep < 2e-2
+    g.close()
+    gp.close()
