@@ -311,6 +311,56 @@ def run_pcg_compare(P, torch, coarse_caps=(150, 300)):
     return out
 
 
+def run_gradiv(P, torch, msh, orders=(3, 7), steps=50, rotate_bytes=1.2e9):
+    """DG gradient and divergence (central fluxes) on the 524,288-triangle
+    mesh, FP64: microseconds per launch (HIP events over `steps` launches
+    rotating over independent data sets) and algorithmic bandwidth, each
+    launch reading one (G) or two (D) nodal fields, writing two (G) or one
+    (D), plus the metric (32 B) and connectivity (16 B) per element."""
+    import ctypes as C
+    import synth
+    out = {}
+    K = msh.K
+    for N in orders:
+        Np = np_of(N)
+        nbytes = K * (3 * Np * 8 + 48)
+        R = max(1, math.ceil(rotate_bytes / nbytes))
+        g = P.Mesh.from_synth(N, msh)
+        x0 = torch.from_numpy(synth.nodal_normal(K, Np, seed=3)).to("cuda")
+        ins = [(x0.clone(), x0.clone()) for _ in range(R)]
+        outs = [(torch.empty_like(x0), torch.empty_like(x0)) for _ in range(R)]
+        st = C.c_void_p(torch.cuda.current_stream().cuda_stream)
+        ptr = lambda t: C.c_void_p(t.data_ptr())
+        lib = P.lib()
+
+        def grad(i):
+            a, (o1, o2) = ins[i % R][0], outs[i % R]
+            return lib.ipdg_grad(g.handle, ptr(a), ptr(o1), ptr(o2), st)
+
+        def div(i):
+            (a, b), o = ins[i % R], outs[i % R][0]
+            return lib.ipdg_div(g.handle, ptr(a), ptr(b), None, None, ptr(o), st)
+
+        res = {}
+        for name, fn in (("grad", grad), ("div", div)):
+            for i in range(R + 5):
+                assert fn(i) == 0
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for i in range(steps):
+                fn(i)
+            e1.record()
+            torch.cuda.synchronize()
+            us = e0.elapsed_time(e1) * 1e3 / steps
+            gbs = nbytes / (us * 1e-6) / 1e9
+            res[name] = {"us": round(us, 2), "GB/s": round(gbs, 1), "frac_hbm": round(gbs / 8000.0, 4)}
+        out[f"N{N}"] = res
+        print(f"# gradiv N={N}: {res}", file=sys.stderr, flush=True)
+        g.close()
+    return out
+
+
 def run_batch_compare(P, torch, nb=64, prec=None, tol=1e-8):
     """Batched Helmholtz: nb independent (lambda_i M - Lap) u_i = M f_i on
     n_i x n_i squares (n_i ~ U{32..128}), N_i ~ U{4..8}, lambda_i = 10^U(0,3),
@@ -438,6 +488,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-solve batched Helmholtz leg")
     ap.add_argument("--no-grad", action="store_true", help="skip the differentiable-solve leg")
+    ap.add_argument("--no-gradiv", action="store_true", help="skip the gradient/divergence leg")
     ap.add_argument("--sweep-orders", default="1,2,3,4,5,6,7,8")
     ap.add_argument("--no-autotune", action="store_true",
                     help="time the headline with the default operator variant instead of the tuned one")
@@ -505,6 +556,8 @@ def main():
             line["pcg"] = run_pcg_compare(P, torch)
         except P.IpdgError as e:
             line["pcg"] = {"error": str(e)}
+    if not args.no_gradiv:
+        line["gradiv"] = run_gradiv(P, torch, msh)
     if not args.no_grad:
         line["grad"] = run_grad_compare(P, torch)
     if not args.no_batch:

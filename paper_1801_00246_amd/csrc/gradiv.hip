@@ -18,8 +18,6 @@
 namespace ipdg {
 namespace {
 
-constexpr int kThreads = 256;
-
 // outward face vector of face f: its direction is the unit normal and its
 // length the face scale |F| / |E|
 __device__ __forceinline__ void face_vec(int f, double rx, double sx, double ry, double sy, double& ax, double& ay) {
@@ -35,107 +33,189 @@ __device__ __forceinline__ void face_vec(int f, double rx, double sx, double ry,
   }
 }
 
+// Elements per block: a block stages its elements' contiguous fields through
+// one LDS buffer of kElems x pitch values, so that global loads and stores
+// are coalesced while each lane works on one element from registers.
 template <int N>
-__global__ __launch_bounds__(kThreads) void k_grad(GradArgs a) {
+constexpr int kElems() {
+  return Tri<N>::Np <= 15 ? 256 : 128;
+}
+// LDS row pitch in doubles: odd, so that the lanes' rows start in different
+// banks
+template <int N>
+constexpr int kPitchGD() {
+  constexpr int Np = Tri<N>::Np;
+  return (Np % 2) ? Np : Np + 1;
+}
+
+// the block's n elements' values of src, row by row, into the lanes'
+// registers r[] through the LDS buffer (coalesced global reads)
+template <int N>
+__device__ __forceinline__ void load_rows(const double* __restrict__ src, double* lds, int e0, int n,
+                                          double (&r)[Tri<N>::Np]) {
+  constexpr int Np = Tri<N>::Np, P = kPitchGD<N>(), B = kElems<N>();
+  const int total = n * Np;
+  for (int i = threadIdx.x; i < total; i += B) lds[(i / Np) * P + i % Np] = src[(size_t)e0 * Np + i];
+  __syncthreads();
+  if ((int)threadIdx.x < n)
+#pragma unroll
+    for (int j = 0; j < Np; ++j) r[j] = lds[threadIdx.x * P + j];
+  __syncthreads();
+}
+// the rows the lanes wrote into the LDS buffer, out to dst (coalesced)
+template <int N>
+__device__ __forceinline__ void store_rows(const double* lds, double* __restrict__ dst, int e0, int n) {
+  constexpr int Np = Tri<N>::Np, P = kPitchGD<N>(), B = kElems<N>();
+  __syncthreads();
+  const int total = n * Np;
+  for (int i = threadIdx.x; i < total; i += B) dst[(size_t)e0 * Np + i] = lds[(i / Np) * P + i % Np];
+  __syncthreads();
+}
+
+// J M x for one element's values (registers)
+template <int N>
+__device__ __forceinline__ void mass_rows(const double* __restrict__ ops, double J, double (&x)[Tri<N>::Np]) {
+  using L = OpsLayout<N>;
+  constexpr int Np = Tri<N>::Np;
+  double y[Np];
+  for (int i = 0; i < Np; ++i) {
+    double s = 0.0;
+#pragma unroll
+    for (int j = 0; j < Np; ++j) s += ops[L::M + i * Np + j] * x[j];
+    y[i] = J * s;
+  }
+#pragma unroll
+  for (int i = 0; i < Np; ++i) x[i] = y[i];
+}
+
+template <int N, bool MASS>
+__global__ __launch_bounds__(kElems<N>()) void k_grad(GradArgs a) {
   using T = Tri<N>;
   using L = OpsLayout<N>;
-  constexpr int Np = T::Np, Nfp = T::Nfp;
-  const int e = blockIdx.x * kThreads + threadIdx.x;
-  if (e >= a.K) return;
+  constexpr int Np = T::Np, Nfp = T::Nfp, B = kElems<N>(), P = kPitchGD<N>();
+  __shared__ double buf[B * P];
+  const int e0 = blockIdx.x * B;
+  const int n = min(B, a.K - e0);
   const double* __restrict__ ops = a.ops;
   const double* __restrict__ p = a.p;
   double pe[Np];
-#pragma unroll
-  for (int i = 0; i < Np; ++i) pe[i] = p[(size_t)e * Np + i];
-  const double rx = a.geo[4 * (size_t)e], sx = a.geo[4 * (size_t)e + 1];
-  const double ry = a.geo[4 * (size_t)e + 2], sy = a.geo[4 * (size_t)e + 3];
+  load_rows<N>(p, buf, e0, n, pe);
+  const int t = threadIdx.x, e = e0 + t;
   double gx[Np], gy[Np];
-  for (int i = 0; i < Np; ++i) {
-    double dr = 0.0, ds = 0.0;
+  if (t < n) {
+    const double rx = a.geo[4 * (size_t)e], sx = a.geo[4 * (size_t)e + 1];
+    const double ry = a.geo[4 * (size_t)e + 2], sy = a.geo[4 * (size_t)e + 3];
+    // face terms (p* - p-) per face node
+    double fl[3][Nfp];
+    double fax[3], fay[3];
+    const Conn c = a.conn[e];
 #pragma unroll
-    for (int j = 0; j < Np; ++j) {
-      dr += ops[L::Dr + i * Np + j] * pe[j];
-      ds += ops[L::Ds + i * Np + j] * pe[j];
-    }
-    gx[i] = rx * dr + sx * ds;
-    gy[i] = ry * dr + sy * ds;
-  }
-  const Conn c = a.conn[e];
+    for (int f = 0; f < 3; ++f) {
+      const int bc = conn_bc(c.info, f);
+      const int fp = conn_fp(c.info, f), nb = c.nb[f];
+      face_vec(f, rx, sx, ry, sy, fax[f], fay[f]);
 #pragma unroll
-  for (int f = 0; f < 3; ++f) {
-    const int bc = conn_bc(c.info, f);
-    if (bc == 1) continue;                        // Dirichlet: p* = p-
-    const int fp = conn_fp(c.info, f), nb = c.nb[f];
-    double ax, ay;
-    face_vec(f, rx, sx, ry, sy, ax, ay);
-    double fl[Nfp];
-#pragma unroll
-    for (int k = 0; k < Nfp; ++k) {
-      const double pm = pe[T::fm(f, k)];
-      fl[k] = bc == 0 ? 0.5 * (p[(size_t)nb * Np + T::fm(fp, N - k)] - pm) : -pm;
+      for (int k = 0; k < Nfp; ++k) {
+        const double pm = pe[T::fm(f, k)];
+        // Dirichlet: p* = p-; Neumann: p* = 0; interior: p* = {p}
+        fl[f][k] = bc == 1 ? 0.0 : (bc == 0 ? 0.5 * (p[(size_t)nb * Np + T::fm(fp, N - k)] - pm) : -pm);
+      }
     }
     for (int i = 0; i < Np; ++i) {
-      double s = 0.0;
-#pragma unroll
-      for (int k = 0; k < Nfp; ++k) s += ops[L::LIFT + i * 3 * Nfp + f * Nfp + k] * fl[k];
-      gx[i] += ax * s;
-      gy[i] += ay * s;
-    }
-  }
-  double ox[Np], oy[Np];
-  for (int i = 0; i < Np; ++i) {
-    ox[i] = a.a_grad * gx[i];
-    oy[i] = a.a_grad * gy[i];
-    if (a.base_x) {
-      ox[i] += a.a_base * a.base_x[(size_t)e * Np + i];
-      oy[i] += a.a_base * a.base_y[(size_t)e * Np + i];
-    }
-  }
-  if (a.mass) {
-    const double J = 1.0 / (rx * sy - ry * sx);
-    for (int i = 0; i < Np; ++i) {
-      double sxm = 0.0, sym = 0.0;
+      double dr = 0.0, ds = 0.0;
 #pragma unroll
       for (int j = 0; j < Np; ++j) {
-        sxm += ops[L::M + i * Np + j] * ox[j];
-        sym += ops[L::M + i * Np + j] * oy[j];
+        dr += ops[L::Dr + i * Np + j] * pe[j];
+        ds += ops[L::Ds + i * Np + j] * pe[j];
       }
-      a.out_x[(size_t)e * Np + i] = J * sxm;
-      a.out_y[(size_t)e * Np + i] = J * sym;
-    }
-  } else {
+      double vx = rx * dr + sx * ds, vy = ry * dr + sy * ds;
 #pragma unroll
-    for (int i = 0; i < Np; ++i) {
-      a.out_x[(size_t)e * Np + i] = ox[i];
-      a.out_y[(size_t)e * Np + i] = oy[i];
+      for (int f = 0; f < 3; ++f) {
+        double s = 0.0;
+#pragma unroll
+        for (int k = 0; k < Nfp; ++k) s += ops[L::LIFT + i * 3 * Nfp + f * Nfp + k] * fl[f][k];
+        vx += fax[f] * s;
+        vy += fay[f] * s;
+      }
+      gx[i] = a.a_grad * vx;
+      gy[i] = a.a_grad * vy;
     }
+    if (a.base_x) {
+#pragma unroll
+      for (int i = 0; i < Np; ++i) {
+        gx[i] += a.a_base * a.base_x[(size_t)e * Np + i];
+        gy[i] += a.a_base * a.base_y[(size_t)e * Np + i];
+      }
+    }
+    if constexpr (MASS) {
+      const double J = 1.0 / (rx * sy - ry * sx);
+      mass_rows<N>(ops, J, gx);
+      mass_rows<N>(ops, J, gy);
+    }
+#pragma unroll
+    for (int i = 0; i < Np; ++i) buf[t * P + i] = gx[i];
   }
-  if (a.p_out) {
+  store_rows<N>(buf, a.out_x, e0, n);
+  if (t < n)
 #pragma unroll
-    for (int i = 0; i < Np; ++i) a.p_out[(size_t)e * Np + i] = pe[i] + a.add_p[(size_t)e * Np + i];
+    for (int i = 0; i < Np; ++i) buf[t * P + i] = gy[i];
+  store_rows<N>(buf, a.out_y, e0, n);
+  if (a.p_out) {
+    if (t < n)
+#pragma unroll
+      for (int i = 0; i < Np; ++i) buf[t * P + i] = pe[i];
+    __syncthreads();
+    const int total = n * Np;
+    for (int i = threadIdx.x; i < total; i += B)
+      a.p_out[(size_t)e0 * Np + i] = buf[(i / Np) * P + i % Np] + a.add_p[(size_t)e0 * Np + i];
   }
 }
 
-template <int N>
-__global__ __launch_bounds__(kThreads) void k_div(DivArgs a) {
+template <int N, bool MASS>
+__global__ __launch_bounds__(kElems<N>()) void k_div(DivArgs a) {
   using T = Tri<N>;
   using L = OpsLayout<N>;
-  constexpr int Np = T::Np, Nfp = T::Nfp;
-  const int e = blockIdx.x * kThreads + threadIdx.x;
-  if (e >= a.K) return;
+  constexpr int Np = T::Np, Nfp = T::Nfp, B = kElems<N>(), P = kPitchGD<N>();
+  __shared__ double buf[B * P];
+  const int e0 = blockIdx.x * B;
+  const int n = min(B, a.K - e0);
   const double* __restrict__ ops = a.ops;
   const double* __restrict__ u = a.u;
   const double* __restrict__ v = a.v;
-  const double rx = a.geo[4 * (size_t)e], sx = a.geo[4 * (size_t)e + 1];
-  const double ry = a.geo[4 * (size_t)e + 2], sy = a.geo[4 * (size_t)e + 3];
-  double d[Np];
-  {
-    double ue[Np], ve[Np];
+  double ue[Np], ve[Np];
+  load_rows<N>(u, buf, e0, n, ue);
+  load_rows<N>(v, buf, e0, n, ve);
+  const int t = threadIdx.x, e = e0 + t;
+  if (t < n) {
+    const double rx = a.geo[4 * (size_t)e], sx = a.geo[4 * (size_t)e + 1];
+    const double ry = a.geo[4 * (size_t)e + 2], sy = a.geo[4 * (size_t)e + 3];
+    // face terms n . (u* - u-) per face node
+    double fl[3][Nfp];
+    const Conn c = a.conn[e];
 #pragma unroll
-    for (int i = 0; i < Np; ++i) {
-      ue[i] = u[(size_t)e * Np + i];
-      ve[i] = v[(size_t)e * Np + i];
+    for (int f = 0; f < 3; ++f) {
+      const int bc = conn_bc(c.info, f);
+      const int fp = conn_fp(c.info, f), nb = c.nb[f];
+      double ax, ay;
+      face_vec(f, rx, sx, ry, sy, ax, ay);
+#pragma unroll
+      for (int k = 0; k < Nfp; ++k) {
+        const int m = T::fm(f, k);
+        const double um = ue[m], vm = ve[m];
+        double ju = 0.0, jv = 0.0;   // Neumann: u* = u-
+        if (bc == 0) {
+          const size_t ip = (size_t)nb * Np + T::fm(fp, N - k);
+          ju = 0.5 * (u[ip] - um);
+          jv = 0.5 * (v[ip] - vm);
+        } else if (bc == 1) {
+          const size_t im = (size_t)e * Np + m;
+          ju = (a.gu ? a.gu[im] : 0.0) - um;
+          jv = (a.gv ? a.gv[im] : 0.0) - vm;
+        }
+        fl[f][k] = ax * ju + ay * jv;
+      }
     }
+    double d[Np];
     for (int i = 0; i < Np; ++i) {
       double ur = 0.0, us = 0.0, vr = 0.0, vs = 0.0;
 #pragma unroll
@@ -146,55 +226,25 @@ __global__ __launch_bounds__(kThreads) void k_div(DivArgs a) {
         vr += dr * ve[j];
         vs += ds * ve[j];
       }
-      d[i] = (rx * ur + sx * us) + (ry * vr + sy * vs);
-    }
-  }
-  const Conn c = a.conn[e];
+      double di = (rx * ur + sx * us) + (ry * vr + sy * vs);
 #pragma unroll
-  for (int f = 0; f < 3; ++f) {
-    const int bc = conn_bc(c.info, f);
-    if (bc == 2) continue;                        // Neumann: u* = u-
-    const int fp = conn_fp(c.info, f), nb = c.nb[f];
-    double ax, ay;
-    face_vec(f, rx, sx, ry, sy, ax, ay);
-    double fl[Nfp];
+      for (int f = 0; f < 3; ++f) {
+        double s = 0.0;
 #pragma unroll
-    for (int k = 0; k < Nfp; ++k) {
-      const size_t im = (size_t)e * Np + T::fm(f, k);
-      const double um = u[im], vm = v[im];
-      double ju, jv;
-      if (bc == 0) {
-        const size_t ip = (size_t)nb * Np + T::fm(fp, N - k);
-        ju = 0.5 * (u[ip] - um);
-        jv = 0.5 * (v[ip] - vm);
-      } else {
-        ju = (a.gu ? a.gu[im] : 0.0) - um;
-        jv = (a.gv ? a.gv[im] : 0.0) - vm;
+        for (int k = 0; k < Nfp; ++k) s += ops[L::LIFT + i * 3 * Nfp + f * Nfp + k] * fl[f][k];
+        di += s;
       }
-      fl[k] = ax * ju + ay * jv;
+      d[i] = di;
     }
-    for (int i = 0; i < Np; ++i) {
-      double s = 0.0;
+    if constexpr (MASS) mass_rows<N>(ops, 1.0 / (rx * sy - ry * sx), d);
 #pragma unroll
-      for (int k = 0; k < Nfp; ++k) s += ops[L::LIFT + i * 3 * Nfp + f * Nfp + k] * fl[k];
-      d[i] += s;
-    }
+    for (int i = 0; i < Np; ++i) buf[t * P + i] = a.scale * d[i];
   }
-  if (a.mass) {
-    const double J = 1.0 / (rx * sy - ry * sx);
-    for (int i = 0; i < Np; ++i) {
-      double s = 0.0;
-#pragma unroll
-      for (int j = 0; j < Np; ++j) s += ops[L::M + i * Np + j] * d[j];
-      a.out[(size_t)e * Np + i] = a.scale * (J * s);
-    }
-  } else {
-#pragma unroll
-    for (int i = 0; i < Np; ++i) a.out[(size_t)e * Np + i] = a.scale * d[i];
-  }
+  store_rows<N>(buf, a.out, e0, n);
 }
 
-int blocks(int K) { return (K + kThreads - 1) / kThreads; }
+template <int N>
+int blocks(int K) { return (K + kElems<N>() - 1) / kElems<N>(); }
 
 }  // namespace
 
@@ -202,7 +252,10 @@ hipError_t grad_apply(int N, const GradArgs& a, hipStream_t s) {
   if (a.K == 0) return hipSuccess;
   switch (N) {
 #define IPDG_G(n) \
-  case n: hipLaunchKernelGGL(k_grad<n>, dim3(blocks(a.K)), dim3(kThreads), 0, s, a); break;
+  case n:                                                                                    \
+    if (a.mass) hipLaunchKernelGGL((k_grad<n, true>), dim3(blocks<n>(a.K)), dim3(kElems<n>()), 0, s, a);  \
+    else hipLaunchKernelGGL((k_grad<n, false>), dim3(blocks<n>(a.K)), dim3(kElems<n>()), 0, s, a);       \
+    break;
     IPDG_G(1) IPDG_G(2) IPDG_G(3) IPDG_G(4) IPDG_G(5) IPDG_G(6) IPDG_G(7) IPDG_G(8)
 #undef IPDG_G
     default: return hipErrorInvalidValue;
@@ -214,7 +267,10 @@ hipError_t div_apply(int N, const DivArgs& a, hipStream_t s) {
   if (a.K == 0) return hipSuccess;
   switch (N) {
 #define IPDG_D(n) \
-  case n: hipLaunchKernelGGL(k_div<n>, dim3(blocks(a.K)), dim3(kThreads), 0, s, a); break;
+  case n:                                                                                    \
+    if (a.mass) hipLaunchKernelGGL((k_div<n, true>), dim3(blocks<n>(a.K)), dim3(kElems<n>()), 0, s, a);   \
+    else hipLaunchKernelGGL((k_div<n, false>), dim3(blocks<n>(a.K)), dim3(kElems<n>()), 0, s, a);        \
+    break;
     IPDG_D(1) IPDG_D(2) IPDG_D(3) IPDG_D(4) IPDG_D(5) IPDG_D(6) IPDG_D(7) IPDG_D(8)
 #undef IPDG_D
     default: return hipErrorInvalidValue;
