@@ -260,6 +260,15 @@ ipdg_status ipdg_grad(ipdg_mesh mesh, const double* p, double* gx, double* gy, v
 ipdg_status ipdg_div(ipdg_mesh mesh, const double* u, const double* v, const double* gu,
                      const double* gv, double* out, void* hip_stream);
 
+/* b += the right-hand-side terms of inhomogeneous Dirichlet data g for the
+ * SIPDG operator of ipdg_apply (Sec. 2.1, Eq. INS_SD_5 with its boundary
+ * rules: the mirror ghost 2 g - u- on Dirichlet faces, so that u* = g):
+ * -kappa (g, d_n l_i)_F + 2 tau_F (g, l_i)_F over the mesh's Dirichlet
+ * faces, tau_F = c_tau kappa |F|/|E| (c_tau = tau, or (N+1)^2 when tau <= 0).
+ * g: nodal field whose face-node values on Dirichlet faces are the data;
+ * the operator's solution then takes the trace g there. */
+ipdg_status ipdg_dirichlet_rhs(ipdg_mesh mesh, double tau, const double* g, double* b, void* hip_stream);
+
 /* Right-hand sides of the two solves, mass-weighted for the SIPDG operator
  * (lambda M - Lap_IPDG) of ipdg_apply / ipdg_pcg_solve:
  *   velocity (Eq. INS_TD_3_2), lambda = gamma / (nu dt), per component:

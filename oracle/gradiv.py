@@ -121,3 +121,96 @@ def swapped_bc(EToB):
     B[d] = BC_NEUMANN
     B[nm] = BC_DIRICHLET
     return B
+
+
+def dirichlet_rhs(m: OracleMesh, ctau: float, g, kappa=None):
+    """Right-hand-side contribution of inhomogeneous Dirichlet data g to the
+    SIPDG system of ``assemble`` (Sec. 2.1, Eq. INS_SD_5 with the boundary
+    rules stated after it): the operator's Dirichlet faces take the mirror
+    ghost u+ = 2 g - u-, so that u* = {u} = g; the terms that carry g move to
+    the right-hand side,
+
+        b_i = sum over Dirichlet faces of
+              -kappa (g, d_n l_i)_F + 2 tau_F (g, l_i)_F,
+
+    with tau_F = c_tau kappa |F| / |E| as in ``block_rows``.  g is a nodal
+    field whose trace on each Dirichlet face (its face-node values) is the
+    data.  A = b_f + b_g then reproduces any global polynomial of degree <= N
+    exactly when g is its trace."""
+    from .assemble import _physical_grad
+    ref = m.ref
+    Np = ref.Np
+    kap = np.ones(m.K) if kappa is None else np.asarray(kappa, dtype=np.float64)
+    g = np.asarray(g, dtype=np.float64).reshape(m.K, Np)
+    b = np.zeros((m.K, Np))
+    gq, wq = ref.g1, ref.w1
+    for f in range(3):
+        ef = np.flatnonzero(m.EToB[:, f] == BC_DIRICHLET)
+        if ef.size == 0:
+            continue
+        xa, ya, xb, yb, length, nx, ny = m.face_geometry(ef, f)
+        t = gq[None, :]
+        qx = 0.5 * (1 - t) * xa[:, None] + 0.5 * (1 + t) * xb[:, None]
+        qy = 0.5 * (1 - t) * ya[:, None] + 0.5 * (1 + t) * yb[:, None]
+        Wq = (0.5 * length)[:, None] * wq[None, :]
+        rm, sm = m.to_ref(ef[:, None], qx, qy)
+        V, Lr, Ls = ref.lagrange(rm.ravel(), sm.ravel())
+        nF, q = qx.shape
+        V = V.reshape(nF, q, Np)
+        gx, gy = _physical_grad(m, ef, Lr.reshape(nF, q, Np), Ls.reshape(nF, q, Np))
+        Dn = nx[:, None, None] * gx + ny[:, None, None] * gy        # d_n l_i at the points
+        gval = np.einsum("fqj,fj->fq", V, g[ef])                     # trace of g
+        tau = ctau * kap[ef] * length / m.area[ef]
+        b[ef] += (-kap[ef][:, None] * np.einsum("fq,fqi->fi", Wq * gval, Dn)
+                  + (2.0 * tau)[:, None] * np.einsum("fq,fqi->fi", Wq * gval, V))
+    return b.ravel()
+
+
+def advection(m: OracleMesh, u, v, gu=None, gv=None, lax=1.0):
+    """Nonlinear term N(u) of Sec. 2.1 (Eq. INS_SD_2, INS_SD_3) for the
+    velocity (u, v), component by component, in strong nodal form:
+
+        N_c = div F_c(u) + LIFT (|F|/|E|) (n . F_c* - n . F_c(u-)),
+        F_c(u) = u_c u,   n . F_c* = {n . F_c} + (Lambda / 2) (u_c- - u_c+),
+        Lambda = 2 max(|n . u-|, |n . u+|),
+
+    the flux products taken at the nodes (no cubature).  Readings: Lambda is
+    the largest |eigenvalue| of n . dF/du = (n . u) I + u n^T over the segment
+    [u-, u+] (eigenvalues n . u and 2 n . u; linear along the segment, so the
+    maximum sits at an end); the jump term carries the dissipative sign
+    (u- - u+), the paper's [u] = u+ - u- with its printed sign would remove
+    energy from the wrong side.  Dirichlet faces take u+ = g_D (gu, gv nodal
+    fields read on the face nodes; None = 0), Neumann faces u+ = u-.  ``lax``
+    scales Lambda (1: the paper's flux; 0: the central flux, for tests)."""
+    mf = MatFree(m)
+    K, Np, Nfp = m.K, mf.Np, mf.Nfp
+    U = np.asarray(u, dtype=np.float64).reshape(K, Np)
+    V = np.asarray(v, dtype=np.float64).reshape(K, Np)
+    GU = np.zeros((K, Np)) if gu is None else np.asarray(gu, dtype=np.float64).reshape(K, Np)
+    GV = np.zeros((K, Np)) if gv is None else np.asarray(gv, dtype=np.float64).reshape(K, Np)
+    rx, sx, ry, sy = (a[:, None] for a in (m.rx, m.sx, m.ry, m.sy))
+    dx = lambda w: rx * (w @ mf.Dr.T) + sx * (w @ mf.Ds.T)
+    dy = lambda w: ry * (w @ mf.Dr.T) + sy * (w @ mf.Ds.T)
+    Nu = dx(U * U) + dy(U * V)
+    Nv = dx(U * V) + dy(V * V)
+    uf, vf = U.ravel(), V.ravel()
+    for f in range(3):
+        jm = mf.vmapM[:, f, :]                                 # (K, Nfp)
+        jp = mf.vmapP[:, f, :]
+        um, vm = uf[jm], vf[jm]
+        up, vp = uf[jp], vf[jp]
+        bc = m.EToB[:, f][:, None]
+        dirich = np.broadcast_to(bc == BC_DIRICHLET, um.shape)
+        neum = np.broadcast_to(bc == BC_NEUMANN, um.shape)
+        up = np.where(dirich, GU.ravel()[jm], np.where(neum, um, up))
+        vp = np.where(dirich, GV.ravel()[jm], np.where(neum, vm, vp))
+        nx, ny = mf.nx[:, f][:, None], mf.ny[:, f][:, None]
+        unm, unp = nx * um + ny * vm, nx * up + ny * vp        # n . u-, n . u+
+        lam = lax * 2.0 * np.maximum(np.abs(unm), np.abs(unp))
+        fu = 0.5 * (um * unm + up * unp) + 0.5 * lam * (um - up) - um * unm
+        fv = 0.5 * (vm * unm + vp * unp) + 0.5 * lam * (vm - vp) - vm * unm
+        L = mf.LIFT[:, f * Nfp:(f + 1) * Nfp]
+        sc = mf.fscale[:, f][:, None]
+        Nu += (sc * fu) @ L.T
+        Nv += (sc * fv) @ L.T
+    return Nu.ravel(), Nv.ravel()

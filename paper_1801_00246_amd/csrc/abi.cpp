@@ -441,6 +441,26 @@ ipdg_status ipdg_div(ipdg_mesh mesh, const double* u, const double* v, const dou
   });
 }
 
+ipdg_status ipdg_dirichlet_rhs(ipdg_mesh mesh, double tau, const double* g, double* b, void* hip_stream) {
+  return guarded([&]() -> ipdg_status {
+    if (!mesh) return fail(IPDG_EINVAL, "mesh is null");
+    if (mesh->host.K == 0) return IPDG_OK;
+    if (!g || !b) return fail(IPDG_EINVAL, "null vector");
+    DeviceGuard dg(mesh);
+    ipdg::DirichletArgs a;
+    a.g = g;
+    a.b = b;
+    a.kap = mesh->has_kappa ? mesh->kap64.as<double>() : nullptr;
+    a.ctau = ipdg::ctau_of(mesh->host.N, tau);
+    a.geo = mesh->geo64.as<double>();
+    a.conn = mesh->conn.as<ipdg::Conn>();
+    a.ops = static_cast<const double*>(ipdg::device_ops(mesh->host.N, ipdg::Kind::F64));
+    a.K = mesh->host.K;
+    IPDG_HIP(ipdg::dirichlet_rhs(mesh->host.N, a, static_cast<hipStream_t>(hip_stream)));
+    return IPDG_OK;
+  });
+}
+
 ipdg_status ipdg_ins_velocity_rhs(ipdg_mesh mesh, double nu, double dt, const double* uhat,
                                   const double* vhat, const double* sigma_p, double* bu, double* bv,
                                   void* hip_stream) {

@@ -243,6 +243,76 @@ __global__ __launch_bounds__(kElems<N>()) void k_div(DivArgs a) {
   store_rows<N>(buf, a.out, e0, n);
 }
 
+// One element per lane; only elements with Dirichlet faces add anything.
+// Face integrals from the face-node values: with h = (|F| / 2) M1D g (the
+// face mass on [-1, 1] times the half face length), (g, l_i)_F = h at the
+// face nodes, and (g, d_n l_i)_F = sum_k h_k (d_n l_i)(x_k), d_n l_i at a
+// face node read off the derivative matrices (exact: both traces are
+// polynomials the face nodes represent).
+template <int N>
+__global__ __launch_bounds__(256) void k_dirichlet_rhs(DirichletArgs a) {
+  using T = Tri<N>;
+  using L = OpsLayout<N>;
+  constexpr int Np = T::Np, Nfp = T::Nfp;
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= a.K) return;
+  const Conn c = a.conn[e];
+  if (conn_bc(c.info, 0) != 1 && conn_bc(c.info, 1) != 1 && conn_bc(c.info, 2) != 1) return;
+  const double* __restrict__ ops = a.ops;
+  const double rx = a.geo[4 * (size_t)e], sx = a.geo[4 * (size_t)e + 1];
+  const double ry = a.geo[4 * (size_t)e + 2], sy = a.geo[4 * (size_t)e + 3];
+  const double J = 1.0 / (rx * sy - ry * sx);
+  const double kap = a.kap ? a.kap[e] : 1.0;
+  double* b = a.b + (size_t)e * Np;
+  for (int f = 0; f < 3; ++f) {
+    if (conn_bc(c.info, f) != 1) continue;
+    double ax, ay;
+    face_vec(f, rx, sx, ry, sy, ax, ay);
+    const double fs = sqrt(ax * ax + ay * ay);          // |F| / |E|
+    const double nx = ax / fs, ny = ay / fs;
+    const double half_len = fs * J;                     // |F| / 2 (|E| = 2 J)
+    const double tau = a.ctau * kap * fs;
+    double gk[Nfp], h[Nfp];
+#pragma unroll
+    for (int k = 0; k < Nfp; ++k) gk[k] = a.g[(size_t)e * Np + T::fm(f, k)];
+#pragma unroll
+    for (int k = 0; k < Nfp; ++k) {
+      double s = 0.0;
+#pragma unroll
+      for (int m = 0; m < Nfp; ++m) s += ops[L::M1D + k * Nfp + m] * gk[m];
+      h[k] = half_len * s;
+    }
+    // -kappa (g, d_n l_i)_F for every row i
+    for (int i = 0; i < Np; ++i) {
+      double s = 0.0;
+#pragma unroll
+      for (int k = 0; k < Nfp; ++k) {
+        const int q = T::fm(f, k);
+        const double dx = rx * ops[L::Dr + q * Np + i] + sx * ops[L::Ds + q * Np + i];
+        const double dy = ry * ops[L::Dr + q * Np + i] + sy * ops[L::Ds + q * Np + i];
+        s += h[k] * (nx * dx + ny * dy);
+      }
+      b[i] -= kap * s;
+    }
+    // 2 tau_F (g, l_i)_F on the face nodes
+#pragma unroll
+    for (int k = 0; k < Nfp; ++k) b[T::fm(f, k)] += 2.0 * tau * h[k];
+  }
+}
+
+hipError_t dirichlet_rhs(int N, const DirichletArgs& a, hipStream_t s) {
+  if (a.K == 0) return hipSuccess;
+  const dim3 g((a.K + 255) / 256);
+  switch (N) {
+#define IPDG_R(n) \
+  case n: hipLaunchKernelGGL(k_dirichlet_rhs<n>, g, dim3(256), 0, s, a); break;
+    IPDG_R(1) IPDG_R(2) IPDG_R(3) IPDG_R(4) IPDG_R(5) IPDG_R(6) IPDG_R(7) IPDG_R(8)
+#undef IPDG_R
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 template <int N>
 int blocks(int K) { return (K + kElems<N>() - 1) / kElems<N>(); }
 

@@ -39,6 +39,21 @@ struct DivArgs {
   int K = 0;
 };
 
+// b += the right-hand-side terms of inhomogeneous Dirichlet data g (a nodal
+// field; its face-node values on the Dirichlet faces) for the SIPDG operator:
+// -kappa (g, d_n l_i)_F + 2 tau_F (g, l_i)_F, tau_F = c_tau kappa |F| / |E|
+struct DirichletArgs {
+  const double* g = nullptr;
+  double* b = nullptr;
+  const double* kap = nullptr;     // per-element coefficient, null = 1
+  double ctau = 0.0;
+  const double* geo = nullptr;
+  const Conn* conn = nullptr;
+  const double* ops = nullptr;
+  int K = 0;
+};
+hipError_t dirichlet_rhs(int N, const DirichletArgs& a, hipStream_t s);
+
 // out = a_base base + a_grad G p (or J M of it), p_out = p + add_p
 hipError_t grad_apply(int N, const GradArgs& a, hipStream_t s);
 // out = scale D (u, v) (or scale J M D (u, v))

@@ -80,6 +80,7 @@ _SIGS = {
                                              C.POINTER(SolveOpts), _P, _P, _P]),
     "ipdg_kappa_grad": (C.c_int, [_P, C.c_double, _P, _P, _P, _P]),
     "ipdg_grad": (C.c_int, [_P, _P, _P, _P, _P]),
+    "ipdg_dirichlet_rhs": (C.c_int, [_P, C.c_double, _P, _P, _P]),
     "ipdg_div": (C.c_int, [_P, _P, _P, _P, _P, _P, _P]),
     "ipdg_ins_velocity_rhs": (C.c_int, [_P, C.c_double, C.c_double, _P, _P, _P, _P, _P, _P]),
     "ipdg_ins_pressure_rhs": (C.c_int, [_P, C.c_double, C.c_double, _P, _P, _P, _P, _P, _P]),
@@ -373,6 +374,11 @@ class Mesh:
         check(lib().ipdg_div(self._h, self._vec(u, "u"), self._vec(v, "v"), self._opt(gu, "gu"),
                              self._opt(gv, "gv"), self._vec(out, "out"), _stream(stream)))
         return out
+
+    def dirichlet_rhs(self, g, b, tau=0.0, stream=None):
+        """b += the Dirichlet-data terms of the nodal field g (in place)."""
+        check(lib().ipdg_dirichlet_rhs(self._h, float(tau), self._vec(g, "g"), self._vec(b, "b"), _stream(stream)))
+        return b
 
     def ins_velocity_rhs(self, nu, dt, uhat, vhat, sigma_p, stream=None):
         import torch

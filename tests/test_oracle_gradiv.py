@@ -129,3 +129,88 @@ def test_projection_recovers_the_solenoidal_part(N):
     assert eu2 < 5e-2 and ep2 < 5e-2
     assert eu1 / eu2 > 2 ** (N - 0.5)
     assert ep1 / ep2 > 2 ** (N - 0.5)
+
+
+@pytest.mark.parametrize("bc", ["dirichlet", "mixed"])
+@pytest.mark.parametrize("N", [1, 2, 4])
+def test_dirichlet_data_reproduce_global_polynomials(N, bc):
+    """SIPDG is consistent: for a global polynomial u of degree <= N,
+    A u = M (-lap u + lambda u) + b_g(u) holds exactly once the Dirichlet data
+    g = u enter through dirichlet_rhs.  On Neumann faces the natural condition
+    would need the normal derivative as data, which is not supplied here, so
+    on the mixed mesh only the rows of elements without Neumann faces are
+    checked."""
+    from oracle.assemble import mass_apply
+    from oracle.gradiv import dirichlet_rhs
+    msh = synth.permuted(synth.square_mesh(4, jitter=0.2, seed=40, bc=bc), seed=41)
+    m = OracleMesh(msh.VX, msh.VY, msh.EToV, msh.EToB, N)
+    x, y = m.node_coords()
+    x, y = x.ravel(), y.ravel()
+    rng = np.random.default_rng(42 + N)
+    c = rng.standard_normal((N + 1, N + 1))
+    u = np.zeros_like(x)
+    lap = np.zeros_like(x)
+    for a in range(N + 1):
+        for bb in range(N + 1 - a):
+            u += c[a, bb] * x ** a * y ** bb
+            if a >= 2:
+                lap += c[a, bb] * a * (a - 1) * x ** (a - 2) * y ** bb
+            if bb >= 2:
+                lap += c[a, bb] * bb * (bb - 1) * x ** a * y ** (bb - 2)
+    lam, ctau = 0.7, float((N + 1) ** 2)
+    A = assemble(m, lam, ctau)
+    r = A @ u - mass_apply(m, -lap + lam * u) - dirichlet_rhs(m, ctau, u)
+    scale = np.abs(A @ u).max()
+    if bc == "dirichlet":
+        assert np.abs(r).max() <= 1e-10 * scale
+    else:
+        # rows of elements without Neumann faces see only interior and
+        # Dirichlet faces: consistent there
+        clean = np.all(m.EToB != BC_NEUMANN, axis=1)
+        rr = r.reshape(m.K, m.Np)[clean]
+        assert clean.any() and np.abs(rr).max() <= 1e-10 * scale
+
+
+@pytest.mark.parametrize("bc", ["dirichlet", "neumann", "mixed"])
+@pytest.mark.parametrize("N", [2, 4])
+def test_advection_of_a_linear_field_is_exact(N, bc):
+    """u linear: u (x) u is quadratic, represented exactly at the nodes when
+    N >= 2, and continuous, so with the Dirichlet data equal to u every jump
+    and flux difference vanishes and N(u) = div(u (x) u) exactly (Neumann
+    faces copy u- as the outer state)."""
+    from oracle.gradiv import advection
+    msh = synth.permuted(synth.square_mesh(4, jitter=0.2, seed=50, bc=bc), seed=51)
+    m = OracleMesh(msh.VX, msh.VY, msh.EToV, msh.EToB, N)
+    x, y = (a.ravel() for a in m.node_coords())
+    a, b, c, d, e, f = 0.3, -1.2, 0.7, 0.5, 1.1, -0.4
+    u = a + b * x + c * y
+    v = d + e * x + f * y
+    nu, nv = advection(m, u, v, u, v)
+    # div(u u, u v) = 2 u u_x + u_y v + u v_y; div(v u, v v) = v_x u + v u_x + 2 v v_y
+    ru = 2 * u * b + c * v + u * f
+    rv = e * u + v * b + 2 * v * f
+    assert np.abs(nu - ru).max() <= 1e-10 * np.abs(ru).max()
+    assert np.abs(nv - rv).max() <= 1e-10 * np.abs(rv).max()
+
+
+@pytest.mark.parametrize("bc", ["dirichlet", "neumann"])
+def test_advection_flux_term_dissipates_jumps(bc):
+    """The Lax-Friedrichs part of the flux, (Lambda/2)(c- - c+), adds to the
+    energy rate (U, N(U))_M exactly sum_F int_F (Lambda/2) |u- - u+|^2 >= 0
+    (each interior face seen from both sides; on Dirichlet faces with zero
+    data, int (Lambda/2) |u-|^2): positive for a discontinuous field, zero
+    for a continuous one whose data match it."""
+    from oracle.gradiv import advection
+    from oracle.assemble import mass_matrix
+    msh = synth.square_mesh(5, jitter=0.2, seed=52, bc=bc)
+    m = OracleMesh(msh.VX, msh.VY, msh.EToV, msh.EToB, 3)
+    M = mass_matrix(m)
+    rng = np.random.default_rng(53)
+    n = m.K * m.Np
+    u, v = rng.standard_normal(n), rng.standard_normal(n)
+    rate = lambda lax: sum(a @ (M @ b) for a, b in zip((u, v), advection(m, u, v, lax=lax)))
+    assert rate(1.0) - rate(0.0) > 0.0
+    x, y = (a.ravel() for a in m.node_coords())
+    u, v = 0.3 + x - y, -0.2 + 0.5 * x + y                       # continuous, data = itself
+    rate = lambda lax: sum(a @ (M @ b) for a, b in zip((u, v), advection(m, u, v, u, v, lax=lax)))
+    assert abs(rate(1.0) - rate(0.0)) <= 1e-12 * abs(rate(0.0))
