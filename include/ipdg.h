@@ -289,6 +289,26 @@ ipdg_status ipdg_ins_correct(ipdg_mesh mesh, double gamma, double dt, const doub
                              const double* dp, const double* sigma_p, double* u_out, double* v_out,
                              double* p_out, void* hip_stream);
 
+/* One step of the algebraic splitting scheme (Sec. 2.2, Eq. INS_TD_3), first
+ * order in time (gamma = beta_0 = alpha_0 = 1), the pressure increment taken
+ * over sigma P = 2 P^n - P^{n-1}:
+ *   U^ = U^n - dt N(U^n)  (nodal Lax-Friedrichs advection, data gu_n, gv_n),
+ *   (M / (nu dt) - Lap) U^^ = M (U^ / (nu dt) - G sigmaP / nu) + Dirichlet
+ *     terms of gu_1, gv_1 (the data at t^{n+1}), PCG on `mesh`,
+ *   -Lap dP = -(1 / dt) D(U^^; gu_1, gv_1), PCG on `pmesh` (the same
+ *     triangles with the boundary flags swapped; without Dirichlet faces the
+ *     right-hand side's constant component is removed first),
+ *   U^{n+1} = U^^ - dt G dP,  P^{n+1} = dP + sigma P.
+ * All vectors are device FP64 (K*Np); gu_*, gv_* may be NULL (zero data).
+ * tol: relative tolerance of the three solves; vel_opts / pres_opts may be
+ * NULL (defaults); iters (3 ints: the u, v and pressure solves) may be NULL.
+ * Synchronous: returns when the step is done. */
+ipdg_status ipdg_ins_step(ipdg_mesh mesh, ipdg_mesh pmesh, double nu, double dt, double tau,
+                          const double* u_n, const double* v_n, const double* p_n, const double* p_nm1,
+                          const double* gu_n, const double* gv_n, const double* gu_1, const double* gv_1,
+                          double* u_1, double* v_1, double* p_1, double tol, const ipdg_solve_opts* vel_opts,
+                          const ipdg_solve_opts* pres_opts, int* iters, void* hip_stream);
+
 /* Host-only validation of a mesh, without any device use: the same checks
  * and face matching as ipdg_mesh_create.  EToE (neighbour element, -1 on a
  * boundary face) and EToF (neighbour's face index, -1 on a boundary face)

@@ -214,3 +214,43 @@ def advection(m: OracleMesh, u, v, gu=None, gv=None, lax=1.0):
         Nu += (sc * fu) @ L.T
         Nv += (sc * fv) @ L.T
     return Nu.ravel(), Nv.ravel()
+
+
+def ins_step(m: OracleMesh, mp: OracleMesh, nu, dt, ctau, un, vn, pn, pnm1, gun=None, gvn=None, gu1=None,
+             gv1=None):
+    """One first-order step of the algebraic splitting scheme (Sec. 2.2, Eq.
+    INS_TD_3_1 to INS_TD_3_4 with gamma = beta_0 = alpha_0 = 1 and the
+    pressure increment over sigma P = 2 P^n - P^{n-1}), with direct solves:
+    m carries the velocity boundary flags, mp the swapped ones.  A pressure
+    level without Dirichlet faces is solved with the constraint (M 1, dP) = 0
+    after the constant component of its right-hand side is removed; the
+    velocity is independent of that constant (G 1 = 0 there)."""
+    import scipy.sparse.linalg as spla
+    from .assemble import assemble
+    gd = GradDiv(m)
+    M = gd.M
+    Nu, Nv = advection(m, un, vn, gun, gvn)
+    uh, vh = un - dt * Nu, vn - dt * Nv                       # Eq. INS_TD_3_1
+    sp_ = 2.0 * pn - pnm1
+    gx, gy = gd.grad(sp_)
+    A = assemble(m, 1.0 / (nu * dt), ctau)
+    bu = M @ (uh / (nu * dt) - gx / nu)                        # Eq. INS_TD_3_2
+    bv = M @ (vh / (nu * dt) - gy / nu)
+    if gu1 is not None:
+        bu = bu + dirichlet_rhs(m, ctau, gu1)
+    if gv1 is not None:
+        bv = bv + dirichlet_rhs(m, ctau, gv1)
+    uhh = spla.spsolve(A.tocsc(), bu)
+    vhh = spla.spsolve(A.tocsc(), bv)
+    bp = -(1.0 / dt) * (M @ gd.div(uhh, vhh, gu1, gv1))       # Eq. INS_TD_3_3
+    S = assemble(mp, 0.0, ctau)
+    if np.any(mp.EToB == BC_DIRICHLET):
+        dp = spla.spsolve(S.tocsc(), bp)
+    else:
+        m1 = M @ np.ones(S.shape[0])
+        bp = bp - (bp.sum() / m1.sum()) * m1
+        n = S.shape[0]
+        Sb = sp.bmat([[S, sp.csr_matrix(m1[:, None])], [sp.csr_matrix(m1[None, :]), None]], format="csc")
+        dp = spla.spsolve(Sb, np.concatenate([bp, [0.0]]))[:n]
+    gx, gy = gd.grad(dp)                                       # Eq. INS_TD_3_4
+    return uhh - dt * gx, vhh - dt * gy, dp + sp_

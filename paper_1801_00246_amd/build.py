@@ -27,7 +27,7 @@ FLAGS = [
     "-I", os.path.join(ROOT, "include"),
 ]
 HOST_SOURCES = ["refelem.cpp", "mesh_host.cpp", "ops_table.cpp", "mesh.cpp", "dispatch.cpp",
-                "amg_host.cpp", "solver.cpp", "abi.cpp"]
+                "amg_host.cpp", "solver.cpp", "ins.cpp", "abi.cpp"]
 DEVICE_SOURCES = ["blas.hip", "noalloc.hip", "probe.hip", "amg.hip", "gradiv.hip"]
 DEGREES = range(1, 9)
 

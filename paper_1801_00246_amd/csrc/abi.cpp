@@ -6,6 +6,7 @@
 
 #include "gradiv.hpp"
 #include "handle.hpp"
+#include "ins.hpp"
 #include "noalloc.hpp"
 #include "probe.hpp"
 #include "refelem.hpp"
@@ -527,6 +528,41 @@ ipdg_status ipdg_ins_correct(ipdg_mesh mesh, double gamma, double dt, const doub
     a.p_out = p_out;
     IPDG_HIP(ipdg::grad_apply(mesh->host.N, a, static_cast<hipStream_t>(hip_stream)));
     return IPDG_OK;
+  });
+}
+
+ipdg_status ipdg_ins_step(ipdg_mesh mesh, ipdg_mesh pmesh, double nu, double dt, double tau,
+                          const double* u_n, const double* v_n, const double* p_n, const double* p_nm1,
+                          const double* gu_n, const double* gv_n, const double* gu_1, const double* gv_1,
+                          double* u_1, double* v_1, double* p_1, double tol, const ipdg_solve_opts* vel_opts,
+                          const ipdg_solve_opts* pres_opts, int* iters, void* hip_stream) {
+  return guarded([&]() -> ipdg_status {
+    if (!mesh || !pmesh) return fail(IPDG_EINVAL, "mesh is null");
+    if (mesh->device != pmesh->device) return fail(IPDG_EINVAL, "the two meshes live on different devices");
+    if (mesh->host.K == 0) return IPDG_OK;
+    if (!u_n || !v_n || !p_n || !p_nm1 || !u_1 || !v_1 || !p_1) return fail(IPDG_EINVAL, "null vector");
+    if (!(tol > 0.0)) return fail(IPDG_EINVAL, "tol must be positive");
+    DeviceGuard dg(mesh);
+    ipdg_solve_opts vo, po;
+    if (vel_opts) vo = *vel_opts;
+    else ipdg_default_opts(&vo);
+    if (pres_opts) po = *pres_opts;
+    else ipdg_default_opts(&po);
+    ipdg::InsState in;
+    in.u = u_n;
+    in.v = v_n;
+    in.p = p_n;
+    in.p_prev = p_nm1;
+    in.gu = gu_n;
+    in.gv = gv_n;
+    ipdg::InsOut out;
+    out.u = u_1;
+    out.v = v_1;
+    out.p = p_1;
+    out.gu = gu_1;
+    out.gv = gv_1;
+    return ipdg::ins_step(mesh, pmesh, nu, dt, tau, in, out, tol, vo, po, iters,
+                          static_cast<hipStream_t>(hip_stream));
   });
 }
 

@@ -300,6 +300,147 @@ __global__ __launch_bounds__(256) void k_dirichlet_rhs(DirichletArgs a) {
   }
 }
 
+template <int N>
+__global__ __launch_bounds__(kElems<N>()) void k_advect(AdvectArgs a) {
+  using T = Tri<N>;
+  using L = OpsLayout<N>;
+  constexpr int Np = T::Np, Nfp = T::Nfp, B = kElems<N>(), P = kPitchGD<N>();
+  __shared__ double buf[B * P];
+  const int e0 = blockIdx.x * B;
+  const int n = min(B, a.K - e0);
+  const double* __restrict__ ops = a.ops;
+  const double* __restrict__ u = a.u;
+  const double* __restrict__ v = a.v;
+  double ue[Np], ve[Np];
+  load_rows<N>(u, buf, e0, n, ue);
+  load_rows<N>(v, buf, e0, n, ve);
+  const int t = threadIdx.x, e = e0 + t;
+  double nu[Np], nv[Np];
+  if (t < n) {
+    const double rx = a.geo[4 * (size_t)e], sx = a.geo[4 * (size_t)e + 1];
+    const double ry = a.geo[4 * (size_t)e + 2], sy = a.geo[4 * (size_t)e + 3];
+    // div (u_c u) from the nodal products
+    for (int i = 0; i < Np; ++i) {
+      double uur = 0.0, uus = 0.0, uvr = 0.0, uvs = 0.0, vvr = 0.0, vvs = 0.0;
+#pragma unroll
+      for (int j = 0; j < Np; ++j) {
+        const double dr = ops[L::Dr + i * Np + j], ds = ops[L::Ds + i * Np + j];
+        const double uu = ue[j] * ue[j], uv = ue[j] * ve[j], vv = ve[j] * ve[j];
+        uur += dr * uu;
+        uus += ds * uu;
+        uvr += dr * uv;
+        uvs += ds * uv;
+        vvr += dr * vv;
+        vvs += ds * vv;
+      }
+      nu[i] = (rx * uur + sx * uus) + (ry * uvr + sy * uvs);
+      nv[i] = (rx * uvr + sx * uvs) + (ry * vvr + sy * vvs);
+    }
+    const Conn c = a.conn[e];
+#pragma unroll
+    for (int f = 0; f < 3; ++f) {
+      const int bc = conn_bc(c.info, f);
+      const int fp = conn_fp(c.info, f), nb = c.nb[f];
+      double ax, ay;
+      face_vec(f, rx, sx, ry, sy, ax, ay);
+      const double fs = sqrt(ax * ax + ay * ay);
+      const double nx = ax / fs, ny = ay / fs;
+      double fu[Nfp], fv[Nfp];
+#pragma unroll
+      for (int k = 0; k < Nfp; ++k) {
+        const int m = T::fm(f, k);
+        const double um = ue[m], vm = ve[m];
+        double up = um, vp = vm;                       // Neumann: u+ = u-
+        if (bc == 0) {
+          const size_t ip = (size_t)nb * Np + T::fm(fp, N - k);
+          up = u[ip];
+          vp = v[ip];
+        } else if (bc == 1) {
+          const size_t im = (size_t)e * Np + m;
+          up = a.gu ? a.gu[im] : 0.0;
+          vp = a.gv ? a.gv[im] : 0.0;
+        }
+        const double unm = nx * um + ny * vm, unp = nx * up + ny * vp;
+        const double lam = 2.0 * fmax(fabs(unm), fabs(unp));
+        fu[k] = fs * (0.5 * (um * unm + up * unp) + 0.5 * lam * (um - up) - um * unm);
+        fv[k] = fs * (0.5 * (vm * unm + vp * unp) + 0.5 * lam * (vm - vp) - vm * unm);
+      }
+      for (int i = 0; i < Np; ++i) {
+        double su = 0.0, sv = 0.0;
+#pragma unroll
+        for (int k = 0; k < Nfp; ++k) {
+          const double l = ops[L::LIFT + i * 3 * Nfp + f * Nfp + k];
+          su += l * fu[k];
+          sv += l * fv[k];
+        }
+        nu[i] += su;
+        nv[i] += sv;
+      }
+    }
+    for (int i = 0; i < Np; ++i) {
+      nu[i] *= a.a_adv;
+      nv[i] *= a.a_adv;
+    }
+    if (a.base_u)
+      for (int i = 0; i < Np; ++i) {
+        nu[i] += a.a_base * a.base_u[(size_t)e * Np + i];
+        nv[i] += a.a_base * a.base_v[(size_t)e * Np + i];
+      }
+#pragma unroll
+    for (int i = 0; i < Np; ++i) buf[t * P + i] = nu[i];
+  }
+  store_rows<N>(buf, a.out_u, e0, n);
+  if (t < n)
+#pragma unroll
+    for (int i = 0; i < Np; ++i) buf[t * P + i] = nv[i];
+  store_rows<N>(buf, a.out_v, e0, n);
+}
+
+__global__ __launch_bounds__(256) void k_axpby(double a, const double* __restrict__ x, double b,
+                                               const double* __restrict__ y, double* __restrict__ z, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) z[i] = a * x[i] + b * y[i];
+}
+
+// one block: work[0] = sum b (fixed order)
+__global__ __launch_bounds__(1024) void k_sum(const double* __restrict__ b, size_t n, double* __restrict__ work) {
+  __shared__ double red[16];
+  double s = 0.0;
+  for (size_t i = threadIdx.x; i < n; i += 1024) s += b[i];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < 16; ++w) t += red[w];
+    work[0] = t;
+  }
+}
+
+// b_i -= (work[0] / area) J_e sum_j M_ij
+template <int N>
+__global__ __launch_bounds__(256) void k_sub_mean(double* __restrict__ b, double area, const double* __restrict__ geo,
+                                                  const double* __restrict__ ops, int K,
+                                                  const double* __restrict__ work) {
+  using L = OpsLayout<N>;
+  constexpr int Np = Tri<N>::Np;
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= K) return;
+  const double c = work[0] / area;
+  const double J = 1.0 / (geo[4 * (size_t)e] * geo[4 * (size_t)e + 3] - geo[4 * (size_t)e + 2] * geo[4 * (size_t)e + 1]);
+  for (int i = 0; i < Np; ++i) {
+    double s = 0.0;
+    for (int j = 0; j < Np; ++j) s += ops[L::M + i * Np + j];
+    b[(size_t)e * Np + i] -= c * J * s;
+  }
+}
+
+
+template <int N>
+int blocks(int K) { return (K + kElems<N>() - 1) / kElems<N>(); }
+
+}  // namespace
+
 hipError_t dirichlet_rhs(int N, const DirichletArgs& a, hipStream_t s) {
   if (a.K == 0) return hipSuccess;
   const dim3 g((a.K + 255) / 256);
@@ -313,10 +454,41 @@ hipError_t dirichlet_rhs(int N, const DirichletArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-template <int N>
-int blocks(int K) { return (K + kElems<N>() - 1) / kElems<N>(); }
+hipError_t advect_apply(int N, const AdvectArgs& a, hipStream_t s) {
+  if (a.K == 0) return hipSuccess;
+  switch (N) {
+#define IPDG_A(n) \
+  case n: hipLaunchKernelGGL(k_advect<n>, dim3(blocks<n>(a.K)), dim3(kElems<n>()), 0, s, a); break;
+    IPDG_A(1) IPDG_A(2) IPDG_A(3) IPDG_A(4) IPDG_A(5) IPDG_A(6) IPDG_A(7) IPDG_A(8)
+#undef IPDG_A
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
 
-}  // namespace
+hipError_t axpby(double a, const double* x, double b, const double* y, double* z, size_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  size_t g = (n + 255) / 256;
+  if (g > 65536) g = 65536;
+  hipLaunchKernelGGL(k_axpby, dim3((unsigned)g), dim3(256), 0, s, a, x, b, y, z, n);
+  return hipGetLastError();
+}
+
+hipError_t remove_mean(int N, double* b, double area, const double* geo, const double* ops, int K, double* work,
+                       hipStream_t s) {
+  if (K == 0) return hipSuccess;
+  const size_t n = (size_t)K * ((N + 1) * (N + 2) / 2);
+  hipLaunchKernelGGL(k_sum, dim3(1), dim3(1024), 0, s, b, n, work);
+  const dim3 g((K + 255) / 256);
+  switch (N) {
+#define IPDG_M(nn) \
+  case nn: hipLaunchKernelGGL(k_sub_mean<nn>, g, dim3(256), 0, s, b, area, geo, ops, K, work); break;
+    IPDG_M(1) IPDG_M(2) IPDG_M(3) IPDG_M(4) IPDG_M(5) IPDG_M(6) IPDG_M(7) IPDG_M(8)
+#undef IPDG_M
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
 
 hipError_t grad_apply(int N, const GradArgs& a, hipStream_t s) {
   if (a.K == 0) return hipSuccess;

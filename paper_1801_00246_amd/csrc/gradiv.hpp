@@ -54,6 +54,33 @@ struct DirichletArgs {
 };
 hipError_t dirichlet_rhs(int N, const DirichletArgs& a, hipStream_t s);
 
+// out = a_base base + a_adv N(u, v): the nodal Lax-Friedrichs advection term
+// of Eq. INS_SD_2 / INS_SD_3 per velocity component (Dirichlet faces take
+// u+ = g, Neumann faces u+ = u-)
+struct AdvectArgs {
+  const double* u = nullptr;
+  const double* v = nullptr;
+  const double* gu = nullptr;      // Dirichlet data (nodal fields), null = 0
+  const double* gv = nullptr;
+  const double* base_u = nullptr;  // optional
+  const double* base_v = nullptr;
+  double a_base = 0.0, a_adv = 1.0;
+  double* out_u = nullptr;
+  double* out_v = nullptr;
+  const double* geo = nullptr;
+  const Conn* conn = nullptr;
+  const double* ops = nullptr;
+  int K = 0;
+};
+hipError_t advect_apply(int N, const AdvectArgs& a, hipStream_t s);
+
+// z = a x + b y (n values)
+hipError_t axpby(double a, const double* x, double b, const double* y, double* z, size_t n, hipStream_t s);
+// b -= (sum b / area) J M 1: removes the component of b that a pure-Neumann
+// Laplacian cannot reach (its null space is the constants); work: 1 double
+hipError_t remove_mean(int N, double* b, double area, const double* geo, const double* ops, int K, double* work,
+                       hipStream_t s);
+
 // out = a_base base + a_grad G p (or J M of it), p_out = p + add_p
 hipError_t grad_apply(int N, const GradArgs& a, hipStream_t s);
 // out = scale D (u, v) (or scale J M D (u, v))
