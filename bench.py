@@ -361,6 +361,52 @@ def run_gradiv(P, torch, msh, orders=(3, 7), steps=50, rotate_bytes=1.2e9):
     return out
 
 
+def run_ins_step(P, torch, n=64, N=5, nu=0.01, dt=1e-3, steps=5):
+    """Splitting steps (ipdg_ins_step, first order) of the Taylor vortex on
+    n x n squares at degree N, Dirichlet velocity data from the exact field,
+    p-multigrid PCG to 1e-8 for the three solves: ms per step, solver
+    iterations, and the velocity error after the timed steps."""
+    import numpy as np
+    import synth
+    msh = synth.square_mesh(n, jitter=0.1, seed=60)
+    flags = np.where(msh.EToB == P.BC_DIRICHLET, P.BC_NEUMANN,
+                     np.where(msh.EToB == P.BC_NEUMANN, P.BC_DIRICHLET, msh.EToB))
+    g = P.Mesh.from_synth(N, msh)
+    gp = P.Mesh(N, msh.VX, msh.VY, msh.EToV, flags)
+    x, y = (np.asarray(a).ravel() for a in g.node_coords())
+
+    def taylor(t):
+        f = np.exp(-2 * np.pi ** 2 * nu * t)
+        return [torch.from_numpy(a).to("cuda") for a in
+                (-np.cos(np.pi * x) * np.sin(np.pi * y) * f, np.sin(np.pi * x) * np.cos(np.pi * y) * f,
+                 -0.25 * (np.cos(2 * np.pi * x) + np.cos(2 * np.pi * y)) * f * f)]
+
+    o = P.default_opts(pc=P.PC_PMG)
+    t = 0.0
+    u, v, p = taylor(t)
+    pm1 = taylor(t - dt)[2]
+    data = [taylor(t + k * dt) for k in range(steps + 2)]
+    times, its = [], []
+    for k in range(steps + 1):                          # the first step sets up the solvers (untimed)
+        torch.cuda.synchronize()
+        t0 = time.time()
+        u1, v1, p1, it = g.ins_step(gp, nu, dt, u, v, p, pm1, data[k][0], data[k][1], data[k + 1][0],
+                                    data[k + 1][1], tol=1e-8, vel_opts=o, pres_opts=o)
+        torch.cuda.synchronize()
+        if k:
+            times.append((time.time() - t0) * 1e3)
+            its.append(it)
+        pm1, u, v, p = p, u1, v1, p1
+    ue, ve = data[steps + 1][0], data[steps + 1][1]
+    err = float(torch.sqrt(((u - ue) ** 2).sum() + ((v - ve) ** 2).sum()) / torch.sqrt((ue ** 2).sum() + (ve ** 2).sum()))
+    g.close()
+    gp.close()
+    return {"workload": f"Taylor vortex, {n}x{n} squares ({msh.K} triangles), N={N}, nu={nu}, dt={dt}, "
+                        "first-order splitting, pMG-PCG to 1e-8 for the u, v and pressure solves",
+            "ms_per_step": round(sum(times) / len(times), 2), "solver_iters_per_step": its[-1],
+            "velocity_rel_error_nodal": err}
+
+
 def run_batch_compare(P, torch, nb=64, prec=None, tol=1e-8):
     """Batched Helmholtz: nb independent (lambda_i M - Lap) u_i = M f_i on
     n_i x n_i squares (n_i ~ U{32..128}), N_i ~ U{4..8}, lambda_i = 10^U(0,3),
@@ -558,6 +604,8 @@ def main():
             line["pcg"] = {"error": str(e)}
     if not args.no_gradiv:
         line["gradiv"] = run_gradiv(P, torch, msh)
+        line["ins_step"] = run_ins_step(P, torch)
+        print(f"# ins_step: {line['ins_step']}", file=sys.stderr, flush=True)
     if not args.no_grad:
         line["grad"] = run_grad_compare(P, torch)
     if not args.no_batch:
