@@ -361,6 +361,91 @@ def run_gradiv(P, torch, msh, orders=(3, 7), steps=50, rotate_bytes=1.2e9):
     return out
 
 
+def sub_dims(N):
+    """Cubature sizes of the subcycling operator: q = floor(3N/2) + 1 Gauss
+    points per direction (volume q^2, faces q)."""
+    q = 3 * N // 2 + 1
+    return q * q, q
+
+
+def sub_flops(N):
+    """Algorithmic FP64 flops per element of the subcycling operator as the
+    kernel evaluates it: volume = interpolation of four fields (8 Nc Np),
+    contravariant fluxes (10 Nc), projection with P_r, P_s for two components
+    (8 Np Nc); surface = interpolation of eight traces on three faces
+    (48 Nfc Nfp), the Lax-Friedrichs flux (20 per face point), the lift of two
+    components (12 Np Nfc).  Also the matrix-core flops issued (16 x 16 x 4
+    blocks of 2048 flops, padding included) per element."""
+    Np, Nfp = np_of(N), N + 1
+    Nc, Nfc = sub_dims(N)
+    vol = 16 * Np * Nc + 10 * Nc
+    surf = 48 * Nfc * Nfp + 60 * Nfc + 12 * Np * Nfc
+    TC, KB, RB = -(-Nc // 16), -(-Np // 4), -(-Np // 16)
+    KF, KT = -(-Nfp // 4), -(-Nfc // 4)
+    mf_vol = (TC * KB * 4 + TC * 4 * RB * 4) * 2048 / 16
+    mf_surf = 3 * (KF * 8 + KT * RB * 2) * 2048 / 16
+    return vol, surf, mf_vol, mf_surf
+
+
+def run_subcycle(P, torch, msh, orders=(3, 5, 7), steps=20, Ns=4):
+    """Subcycling advection with cubature (Eq. KSS_3) on the 524,288-triangle
+    mesh, FP64: microseconds per launch of the volume term (Alg. SSV), the
+    surface term (Alg. SSS) and the fused operator (HIP events over `steps`
+    launches on torch's stream), algorithmic TFLOP/s against the FP64 dense
+    matrix-core peak, and the whole subcycle call (Ns five-stage substeps,
+    one fused operator-and-update launch per stage, work allocation and
+    final synchronisation included) per substep."""
+    import ctypes as C
+    import synth
+    out = {"workload": "512x512-square jittered triangulation (524,288 triangles), all Dirichlet, "
+                       "fields ~ N(0,1), FP64"}
+    K = msh.K
+    for N in orders:
+        Np = np_of(N)
+        g = P.Mesh.from_synth(N, msh)
+        f = [torch.from_numpy(synth.nodal_normal(K, Np, seed=20 + i)).to("cuda") for i in range(6)]
+        nu, nv = torch.empty_like(f[0]), torch.empty_like(f[0])
+        st = C.c_void_p(torch.cuda.current_stream().cuda_stream)
+        ptr = lambda t: C.c_void_p(t.data_ptr())
+        lib = P.lib()
+        vol, surf, mf_vol, mf_surf = sub_flops(N)
+        res = {"Nc": sub_dims(N)[0], "Nfc": sub_dims(N)[1]}
+        for name, parts, fl, mf in (("volume", 1, vol, mf_vol), ("surface", 2, surf, mf_surf),
+                                    ("both", 3, vol + surf, mf_vol + mf_surf)):
+            def run():
+                return lib.ipdg_subcycle_rhs(g.handle, ptr(f[0]), ptr(f[1]), ptr(f[2]), ptr(f[3]), ptr(f[4]),
+                                             ptr(f[5]), parts, ptr(nu), ptr(nv), st)
+            for _ in range(3):
+                assert run() == 0
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(steps):
+                run()
+            e1.record()
+            torch.cuda.synchronize()
+            us = e0.elapsed_time(e1) * 1e3 / steps
+            tf = K * fl / (us * 1e-6) / 1e12
+            res[name] = {"us": round(us, 2), "alg_TFLOP/s": round(tf, 2), "frac_fp64_peak": round(tf / 78.6, 4),
+                         "mfma_TFLOP/s_issued": round(K * mf / (us * 1e-6) / 1e12, 2),
+                         "alg_flops_per_element": fl}
+        u, v = f[2].clone(), f[3].clone()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        assert lib.ipdg_subcycle(g.handle, ptr(f[0]), ptr(f[1]), None, None, ptr(f[4]), ptr(f[5]), None, None,
+                                 C.c_double(1e-4), Ns, ptr(u), ptr(v), st) == 0
+        e0.record()
+        assert lib.ipdg_subcycle(g.handle, ptr(f[0]), ptr(f[1]), None, None, ptr(f[4]), ptr(f[5]), None, None,
+                                 C.c_double(1e-4), Ns, ptr(u), ptr(v), st) == 0
+        e1.record()
+        torch.cuda.synchronize()
+        res["subcycle_ms_per_substep"] = round(e0.elapsed_time(e1) / Ns, 4)
+        out[f"N{N}"] = res
+        print(f"# subcycle N={N}: {res}", file=sys.stderr, flush=True)
+        del f, nu, nv, u, v
+        g.close()
+    return out
+
+
 def run_ins_step(P, torch, n=64, N=5, nu=0.01, dt=1e-3, steps=5):
     """Splitting steps (ipdg_ins_step, first order) of the Taylor vortex on
     n x n squares at degree N, Dirichlet velocity data from the exact field,
@@ -535,6 +620,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-solve batched Helmholtz leg")
     ap.add_argument("--no-grad", action="store_true", help="skip the differentiable-solve leg")
     ap.add_argument("--no-gradiv", action="store_true", help="skip the gradient/divergence leg")
+    ap.add_argument("--no-subcycle", action="store_true", help="skip the subcycling advection leg")
     ap.add_argument("--sweep-orders", default="1,2,3,4,5,6,7,8")
     ap.add_argument("--no-autotune", action="store_true",
                     help="time the headline with the default operator variant instead of the tuned one")
@@ -606,6 +692,8 @@ def main():
         line["gradiv"] = run_gradiv(P, torch, msh)
         line["ins_step"] = run_ins_step(P, torch)
         print(f"# ins_step: {line['ins_step']}", file=sys.stderr, flush=True)
+    if not args.no_subcycle:
+        line["subcycle"] = run_subcycle(P, torch, msh)
     if not args.no_grad:
         line["grad"] = run_grad_compare(P, torch)
     if not args.no_batch:

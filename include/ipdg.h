@@ -244,6 +244,37 @@ ipdg_status ipdg_helmholtz_solve_batch(int nb, const ipdg_mesh* meshes, const do
 ipdg_status ipdg_kappa_grad(ipdg_mesh mesh, double tau, const double* u, const double* w,
                             double* dLdkappa, void* hip_stream);
 
+/* ---- Semi-Lagrangian subcycling advection (Sec. 2.3, Eq. SS_3 and
+ * INS_CUB_N; Sec. 5.3, Eq. KSS_3, Alg. SSV and SSS).  Device FP64 vectors of
+ * K*Np values, asynchronous on hip_stream unless stated; outputs must not
+ * overlap inputs.  The operator is
+ *   (v, N~)_E = -(grad v, Ubar (x) U~)_E + (v, n . F~*)_dE,
+ *   n . F~* = {n . (Ubar (x) U~)} + (Lambda / 2) (U~- - U~+),
+ *   Lambda = max(|n . Ubar-|, |n . Ubar+|) at each face cubature point,
+ * integrated with the volume rule (collapsed Gauss product, q^2 points,
+ * q = floor(3N/2) + 1, exact for the volume integrand) and the q-point
+ * Gauss-Legendre rule on faces.  Boundary faces: Ubar+ = Ubar-; U~+ = g on
+ * Dirichlet faces (nodal data, face nodes read; NULL = 0), U~+ = U~- on
+ * Neumann faces. ---- */
+
+/* nu, nv = the selected parts of N~(Ubar, U~): parts = 1 the volume term
+ * (Alg. SSV), 2 the surface term (Alg. SSS), 3 both (Eq. KSS_3).
+ * IPDG_EINVAL for parts outside 1..3 or a null required vector. */
+ipdg_status ipdg_subcycle_rhs(ipdg_mesh mesh, const double* ubar, const double* vbar, const double* u,
+                              const double* v, const double* gu, const double* gv, int parts, double* nu,
+                              double* nv, void* hip_stream);
+
+/* Ns steps of the five-stage fourth-order low-storage Runge-Kutta scheme
+ * (Carpenter and Kennedy) over [0, T] for dU~/dtau = -N~(Ubar(tau), U~)
+ * (Eq. SS_3), with Ubar(tau) = ubar0 + tau ubar1 and Dirichlet data
+ * g(tau) = g0 + tau g1 (ubar1, vbar1, gu1, gv1 may be NULL: constant in tau;
+ * gu0, gv0 NULL: zero data).  (u, v) hold U~(0) on entry and U~(T) on
+ * return; the call allocates 4 K Np doubles of work and synchronises
+ * hip_stream before returning.  IPDG_EINVAL for Ns < 1 or T not finite. */
+ipdg_status ipdg_subcycle(ipdg_mesh mesh, const double* ubar0, const double* vbar0, const double* ubar1,
+                          const double* vbar1, const double* gu0, const double* gv0, const double* gu1,
+                          const double* gv1, double T, int Ns, double* u, double* v, void* hip_stream);
+
 /* ---- Around the elliptic solves of the algebraic splitting scheme (Sec. 2.2,
  * Eq. INS_TD_3); device FP64 vectors of K*Np values, asynchronous on
  * hip_stream, outputs must not overlap inputs.  Boundary faces take the

@@ -133,26 +133,28 @@ def _face_traces(m: OracleMesh, ops: CubatureOps, fields, g, e, f):
         raise ValueError("unmatched face without a boundary rule")
     return minus, plus, length, nx, ny
 
-def advection_operator(m: OracleMesh, ubar, vbar, u, v, gu=None, gv=None, parts=3, ops=None):
+def advection_operator(m: OracleMesh, ubar, vbar, u, v, gu=None, gv=None, parts=3, ops=None, elems=None):
     """N~(Ubar, U~) of Eq. KSS_3 for both velocity components, as nodal
     fields (K Np each): parts = 1 the volume term, 2 the surface term, 3 both.
-    Dirichlet data (gu, gv) give the exterior trace of U~ there (None = 0)."""
+    Dirichlet data (gu, gv) give the exterior trace of U~ there (None = 0).
+    ``elems``: compute only these elements' rows (returned in that order)."""
     ops = ops or CubatureOps(m.N)
     K, Np = m.K, m.Np
+    E = np.arange(K) if elems is None else np.asarray(elems, dtype=np.int64)
     sh = lambda a: np.zeros((K, Np)) if a is None else np.asarray(a, dtype=np.float64).reshape(K, Np)
     UB, VB, U, V, GU, GV = (sh(a) for a in (ubar, vbar, u, v, gu, gv))
-    Nu = np.zeros((K, Np))
-    Nv = np.zeros((K, Np))
+    Nu = np.zeros((E.size, Np))
+    Nv = np.zeros((E.size, Np))
     if parts & 1:
         # volume: -(grad l_n, Ubar U~) at the cubature nodes, divided by J M
-        ub, vb = UB @ ops.I.T, VB @ ops.I.T                       # (K, Nc)
-        uc, vc = U @ ops.I.T, V @ ops.I.T
-        rx, sx, ry, sy = (a[:, None] for a in (m.rx, m.sx, m.ry, m.sy))
+        ub, vb = UB[E] @ ops.I.T, VB[E] @ ops.I.T                 # (|E|, Nc)
+        uc, vc = U[E] @ ops.I.T, V[E] @ ops.I.T
+        rx, sx, ry, sy = (a[E][:, None] for a in (m.rx, m.sx, m.ry, m.sy))
         # the u row of F~ is (ub uc, vb uc), the v row (ub vc, vb vc)
         Nu -= (rx * ub * uc + ry * vb * uc) @ ops.Pr.T + (sx * ub * uc + sy * vb * uc) @ ops.Ps.T
         Nv -= (rx * ub * vc + ry * vb * vc) @ ops.Pr.T + (sx * ub * vc + sy * vb * vc) @ ops.Ps.T
     if parts & 2:
-        for e in range(K):
+        for row, e in enumerate(E):
             for f in range(3):
                 (ubm, vbm, um, vm), (ubp, vbp, up, vp), length, nx, ny = _face_traces(
                     m, ops, (UB, VB, U, V), (GU, GV), e, f)
@@ -162,8 +164,8 @@ def advection_operator(m: OracleMesh, ubar, vbar, u, v, gu=None, gv=None, parts=
                 fu = 0.5 * (anm * um + anp * up) + 0.5 * lam * (um - up)
                 fv = 0.5 * (anm * vm + anp * vp) + 0.5 * lam * (vm - vp)
                 sc = length / m.area[e]                             # J^{ef} / J^e
-                Nu[e] += sc * (ops.Lc[f] @ fu)
-                Nv[e] += sc * (ops.Lc[f] @ fv)
+                Nu[row] += sc * (ops.Lc[f] @ fu)
+                Nv[row] += sc * (ops.Lc[f] @ fv)
     return Nu.ravel(), Nv.ravel()
 
 def subcycle(m: OracleMesh, ubar0, vbar0, u, v, T, Ns, ubar1=None, vbar1=None, gu0=None, gv0=None, gu1=None,

@@ -1,6 +1,7 @@
 // C ABI entry points (include/ipdg.h).  Every call catches library errors and
 // maps them to an ipdg_status; the message is kept per thread.
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <string>
 
@@ -11,6 +12,7 @@
 #include "probe.hpp"
 #include "refelem.hpp"
 #include "solver.hpp"
+#include "subcycle.hpp"
 
 namespace {
 
@@ -563,6 +565,53 @@ ipdg_status ipdg_ins_step(ipdg_mesh mesh, ipdg_mesh pmesh, double nu, double dt,
     out.gv = gv_1;
     return ipdg::ins_step(mesh, pmesh, nu, dt, tau, in, out, tol, vo, po, iters,
                           static_cast<hipStream_t>(hip_stream));
+  });
+}
+
+ipdg_status ipdg_subcycle_rhs(ipdg_mesh mesh, const double* ubar, const double* vbar, const double* u,
+                              const double* v, const double* gu, const double* gv, int parts, double* nu,
+                              double* nv, void* hip_stream) {
+  return guarded([&]() -> ipdg_status {
+    if (!mesh) return fail(IPDG_EINVAL, "mesh is null");
+    if (parts < 1 || parts > 3) return fail(IPDG_EINVAL, "parts must be 1, 2 or 3");
+    if (mesh->host.K == 0) return IPDG_OK;
+    if (!ubar || !vbar || !u || !v || !nu || !nv) return fail(IPDG_EINVAL, "null vector");
+    DeviceGuard dg(mesh);
+    ipdg::SubArgs a;
+    a.ub0 = ubar;
+    a.vb0 = vbar;
+    a.u = u;
+    a.v = v;
+    a.gu0 = gu;
+    a.gv0 = gv;
+    ipdg::subcycle_rhs(mesh, a, parts, nu, nv, static_cast<hipStream_t>(hip_stream));
+    return IPDG_OK;
+  });
+}
+
+ipdg_status ipdg_subcycle(ipdg_mesh mesh, const double* ubar0, const double* vbar0, const double* ubar1,
+                          const double* vbar1, const double* gu0, const double* gv0, const double* gu1,
+                          const double* gv1, double T, int Ns, double* u, double* v, void* hip_stream) {
+  return guarded([&]() -> ipdg_status {
+    if (!mesh) return fail(IPDG_EINVAL, "mesh is null");
+    if (Ns < 1) return fail(IPDG_EINVAL, "Ns must be at least 1");
+    if (!std::isfinite(T)) return fail(IPDG_EINVAL, "T must be finite");
+    if (mesh->host.K == 0) return IPDG_OK;
+    if (!ubar0 || !vbar0 || !u || !v) return fail(IPDG_EINVAL, "null vector");
+    if ((ubar1 == nullptr) != (vbar1 == nullptr)) return fail(IPDG_EINVAL, "give both ubar1 and vbar1 or neither");
+    if ((gu1 || gv1) && (!gu0 || !gv0)) return fail(IPDG_EINVAL, "data rates need the data gu0, gv0");
+    DeviceGuard dg(mesh);
+    ipdg::SubArgs a;
+    a.ub0 = ubar0;
+    a.vb0 = vbar0;
+    a.ub1 = ubar1;
+    a.vb1 = vbar1;
+    a.gu0 = gu0;
+    a.gv0 = gv0;
+    a.gu1 = gu1;
+    a.gv1 = gv1;
+    ipdg::subcycle_advect(mesh, a, T, Ns, u, v, static_cast<hipStream_t>(hip_stream));
+    return IPDG_OK;
   });
 }
 

@@ -54,6 +54,21 @@ __device__ __forceinline__ const T* in_constant(const T* p) {
   return (const T*)((const __attribute__((address_space(4))) T*)(unsigned long long)p);
 }
 
+// outward face vector of face f: its direction is the unit normal and its
+// length the face scale |F| / |E|
+__device__ __forceinline__ void face_vec(int f, double rx, double sx, double ry, double sy, double& ax, double& ay) {
+  if (f == 0) {
+    ax = -sx;
+    ay = -sy;
+  } else if (f == 1) {
+    ax = rx + sx;
+    ay = ry + sy;
+  } else {
+    ax = -rx;
+    ay = -ry;
+  }
+}
+
 // Sum of v over the block, valid in thread 0.  Fixed reduction order, so the
 // result is bitwise reproducible for a given launch shape.
 template <int NV>

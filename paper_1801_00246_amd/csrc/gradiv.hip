@@ -18,21 +18,6 @@
 namespace ipdg {
 namespace {
 
-// outward face vector of face f: its direction is the unit normal and its
-// length the face scale |F| / |E|
-__device__ __forceinline__ void face_vec(int f, double rx, double sx, double ry, double sy, double& ax, double& ay) {
-  if (f == 0) {
-    ax = -sx;
-    ay = -sy;
-  } else if (f == 1) {
-    ax = rx + sx;
-    ay = ry + sy;
-  } else {
-    ax = -rx;
-    ay = -ry;
-  }
-}
-
 // Elements per block: a block stages its elements' contiguous fields through
 // one LDS buffer of kElems x pitch values, so that global loads and stores
 // are coalesced while each lane works on one element from registers.

@@ -263,6 +263,104 @@ const RefOps& ref_ops(int N) {
   return cache[N];
 }
 
+namespace {
+
+// q-point Gauss-Legendre rule: zeros of P_q by Newton from the Chebyshev
+// guesses, weights 2 / ((1 - x^2) P_q'(x)^2).
+void gauss(int q, std::vector<double>& x, std::vector<double>& w) {
+  x.resize(q);
+  w.resize(q);
+  for (int k = 0; k < q; ++k) {
+    double t = -std::cos(M_PI * (k + 0.75) / (q + 0.5));
+    double p = 0.0, dp = 1.0;
+    for (int it = 0; it < 100; ++it) {
+      legendre(q, t, p, dp);
+      const double step = p / dp;
+      t -= step;
+      if (std::fabs(step) < 1e-16) break;
+    }
+    legendre(q, t, p, dp);
+    x[k] = t;
+    w[k] = 2.0 / ((1.0 - t * t) * dp * dp);
+  }
+}
+
+CubOps build_cub(int N) {
+  const RefOps& R = ref_ops(N);
+  CubOps C;
+  C.N = N;
+  C.Np = R.Np;
+  C.Nfp = R.Nfp;
+  C.q = cub_points(N);
+  C.Nc = C.q * C.q;
+  C.Nfc = C.q;
+  const int Np = C.Np, Nfp = C.Nfp, Nc = C.Nc, Nfc = C.Nfc;
+  std::vector<double> g, gw;
+  gauss(C.q, g, gw);
+  // inverse Vandermonde at the nodes: the Lagrange basis at a point is
+  // psi(point)^T V^{-1}
+  Mat V(Np * Np);
+  for (int n = 0; n < Np; ++n) dubiner(N, R.r[n], R.s[n], &V[n * Np], nullptr, nullptr);
+  Mat Vi = inverse(V, Np);
+  Mat Q(Nc * Np), Qr(Nc * Np), Qs(Nc * Np);
+  std::vector<double> wc(Nc);
+  for (int a = 0; a < C.q; ++a)
+    for (int b = 0; b < C.q; ++b) {
+      const int i = a * C.q + b;
+      const double r = (1.0 + g[a]) * (1.0 - g[b]) / 2.0 - 1.0, s = g[b];
+      wc[i] = gw[a] * gw[b] * (1.0 - g[b]) / 2.0;
+      dubiner(N, r, s, &Q[i * Np], &Qr[i * Np], &Qs[i * Np]);
+    }
+  C.I = matmul(Q, Vi, Nc, Np, Np);
+  Mat Ir = matmul(Qr, Vi, Nc, Np, Np), Is = matmul(Qs, Vi, Nc, Np, Np);
+  Mat WIr(Np * Nc), WIs(Np * Nc);
+  for (int i = 0; i < Nc; ++i)
+    for (int m = 0; m < Np; ++m) {
+      WIr[m * Nc + i] = wc[i] * Ir[i * Np + m];
+      WIs[m * Nc + i] = wc[i] * Is[i * Np + m];
+    }
+  C.Pr = matmul(R.Minv, WIr, Np, Np, Nc);
+  C.Ps = matmul(R.Minv, WIs, Np, Np, Nc);
+  for (int f = 0; f < 3; ++f) {
+    Mat F(Nfc * Np);
+    for (int j = 0; j < Nfc; ++j) {
+      const double t = g[j];
+      const double r = f == 0 ? t : (f == 1 ? -t : -1.0);
+      const double s = f == 0 ? -1.0 : (f == 1 ? t : -t);
+      dubiner(N, r, s, &F[j * Np], nullptr, nullptr);
+    }
+    Mat L = matmul(F, Vi, Nfc, Np, Np);
+    C.If[f].assign(Nfc * Nfp, 0.0);
+    for (int j = 0; j < Nfc; ++j)
+      for (int k = 0; k < Nfp; ++k) C.If[f][j * Nfp + k] = L[j * Np + R.fmask[f * Nfp + k]];
+    // the restriction of P_N to a face is fixed by the face nodes: the other
+    // basis functions vanish there
+    for (int j = 0; j < Nfc; ++j)
+      for (int m = 0; m < Np; ++m) {
+        bool face_node = false;
+        for (int k = 0; k < Nfp; ++k) face_node = face_node || R.fmask[f * Nfp + k] == m;
+        if (!face_node && std::fabs(L[j * Np + m]) > 1e-10)
+          throw std::runtime_error("interior basis function not zero on a face at N=" + std::to_string(N));
+      }
+    Mat WL(Np * Nfc);
+    for (int j = 0; j < Nfc; ++j)
+      for (int m = 0; m < Np; ++m) WL[m * Nfc + j] = gw[j] * L[j * Np + m];
+    C.Lc[f] = matmul(R.Minv, WL, Np, Np, Nfc);
+  }
+  return C;
+}
+
+}  // namespace
+
+const CubOps& cub_ops(int N) {
+  static std::mutex mu;
+  static CubOps cache[kMaxN + 1];
+  if (N < 1 || N > kMaxN) throw std::runtime_error("degree out of range");
+  std::lock_guard<std::mutex> lk(mu);
+  if (cache[N].N == 0) cache[N] = build_cub(N);
+  return cache[N];
+}
+
 std::vector<double> interp_matrix(int Nc, int Nf) {
   const RefOps& C = ref_ops(Nc);
   const RefOps& F = ref_ops(Nf);

@@ -34,4 +34,20 @@ std::vector<double> interp_matrix(int Nc, int Nf);
 
 inline int np_of(int N) { return (N + 1) * (N + 2) / 2; }
 
+// Cubature operators of the subcycling advection term (Sec. 5.3, Eq. KSS_3).
+// Volume: the collapsed-coordinate product of two q-point Gauss-Legendre
+// rules, q = floor(3N/2) + 1, exact for the degree-(3N-1) volume integrand on
+// an affine triangle.  Faces: the q-point Gauss-Legendre rule (exact to degree
+// 3N), points running counter-clockwise like the face nodes.
+struct CubOps {
+  int N = 0, Np = 0, Nfp = 0, q = 0, Nc = 0, Nfc = 0;
+  std::vector<double> I;       // Nc x Np: interpolation to the volume nodes
+  std::vector<double> Pr, Ps;  // Np x Nc: M^{-1} (I dl/dr)^T W, M^{-1} (I dl/ds)^T W
+  std::vector<double> If[3];   // Nfc x Nfp: face f's nodes to its Gauss points
+  std::vector<double> Lc[3];   // Np x Nfc: cubature lift M^{-1} (I^f)^T W^f
+};
+inline int cub_points(int N) { return 3 * N / 2 + 1; }
+// Cached per degree (1..8).
+const CubOps& cub_ops(int N);
+
 }  // namespace ipdg

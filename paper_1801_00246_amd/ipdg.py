@@ -83,6 +83,8 @@ _SIGS = {
     "ipdg_dirichlet_rhs": (C.c_int, [_P, C.c_double, _P, _P, _P]),
     "ipdg_ins_step": (C.c_int, [_P, _P, C.c_double, C.c_double, C.c_double] + [_P] * 11 + [C.c_double, _P, _P, _P, _P]),
     "ipdg_div": (C.c_int, [_P, _P, _P, _P, _P, _P, _P]),
+    "ipdg_subcycle_rhs": (C.c_int, [_P] * 7 + [C.c_int, _P, _P, _P]),
+    "ipdg_subcycle": (C.c_int, [_P] * 9 + [C.c_double, C.c_int, _P, _P, _P]),
     "ipdg_ins_velocity_rhs": (C.c_int, [_P, C.c_double, C.c_double, _P, _P, _P, _P, _P, _P]),
     "ipdg_ins_pressure_rhs": (C.c_int, [_P, C.c_double, C.c_double, _P, _P, _P, _P, _P, _P]),
     "ipdg_ins_correct": (C.c_int, [_P, C.c_double, C.c_double, _P, _P, _P, _P, _P, _P, _P, _P]),
@@ -420,6 +422,28 @@ class Mesh:
                                   self._opt(gv_1, "gv_1"), self._vec(u1, "u_1"), self._vec(v1, "v_1"),
                                   self._vec(p1, "p_1"), float(tol), vo, po, it, _stream(stream)))
         return u1, v1, p1, list(it)
+
+    def subcycle_rhs(self, ubar, vbar, u, v, gu=None, gv=None, parts=3, stream=None):
+        """N~(Ubar, U~) of the subcycling advection with cubature (Eq. KSS_3):
+        parts 1 the volume term, 2 the surface term, 3 both."""
+        import torch
+        nu, nv = torch.empty_like(u), torch.empty_like(v)
+        check(lib().ipdg_subcycle_rhs(self._h, self._vec(ubar, "ubar"), self._vec(vbar, "vbar"), self._vec(u, "u"),
+                                      self._vec(v, "v"), self._opt(gu, "gu"), self._opt(gv, "gv"), int(parts),
+                                      self._vec(nu, "nu"), self._vec(nv, "nv"), _stream(stream)))
+        return nu, nv
+
+    def subcycle(self, ubar0, vbar0, u, v, T, Ns, ubar1=None, vbar1=None, gu0=None, gv0=None, gu1=None, gv1=None,
+                 stream=None):
+        """Ns low-storage RK4 steps over [0, T] of dU~/dt = -N~(Ubar(t), U~),
+        Ubar(t) = Ubar0 + t Ubar1, Dirichlet data g0 + t g1 (Eq. SS_3).
+        Returns new tensors (the inputs are left unchanged)."""
+        uo, vo = u.clone(), v.clone()
+        check(lib().ipdg_subcycle(self._h, self._vec(ubar0, "ubar0"), self._vec(vbar0, "vbar0"),
+                                  self._opt(ubar1, "ubar1"), self._opt(vbar1, "vbar1"), self._opt(gu0, "gu0"),
+                                  self._opt(gv0, "gv0"), self._opt(gu1, "gu1"), self._opt(gv1, "gv1"), float(T),
+                                  int(Ns), self._vec(uo, "u"), self._vec(vo, "v"), _stream(stream)))
+        return uo, vo
 
     def kappa_grad(self, u, w, tau=0.0, stream=None):
         import torch
