@@ -446,11 +446,12 @@ def run_subcycle(P, torch, msh, orders=(3, 5, 7), steps=20, Ns=4):
     return out
 
 
-def run_ins_step(P, torch, n=64, N=5, nu=0.01, dt=1e-3, steps=5):
-    """Splitting steps (ipdg_ins_step, first order) of the Taylor vortex on
-    n x n squares at degree N, Dirichlet velocity data from the exact field,
-    p-multigrid PCG to 1e-8 for the three solves: ms per step, solver
-    iterations, and the velocity error after the timed steps."""
+def run_ins_step(P, torch, n=64, N=5, nu=0.01, dt=1e-3, steps=5, subcycles=0):
+    """Splitting steps (ipdg_ins_step, first order; ipdg_ins_step_subcycled
+    when subcycles > 0) of the Taylor vortex on n x n squares at degree N,
+    Dirichlet velocity data from the exact field, p-multigrid PCG to 1e-8 for
+    the three solves: ms per step, solver iterations, and the velocity error
+    after the timed steps."""
     import numpy as np
     import synth
     msh = synth.square_mesh(n, jitter=0.1, seed=60)
@@ -476,7 +477,7 @@ def run_ins_step(P, torch, n=64, N=5, nu=0.01, dt=1e-3, steps=5):
         torch.cuda.synchronize()
         t0 = time.time()
         u1, v1, p1, it = g.ins_step(gp, nu, dt, u, v, p, pm1, data[k][0], data[k][1], data[k + 1][0],
-                                    data[k + 1][1], tol=1e-8, vel_opts=o, pres_opts=o)
+                                    data[k + 1][1], tol=1e-8, vel_opts=o, pres_opts=o, subcycles=subcycles)
         torch.cuda.synchronize()
         if k:
             times.append((time.time() - t0) * 1e3)
@@ -486,8 +487,10 @@ def run_ins_step(P, torch, n=64, N=5, nu=0.01, dt=1e-3, steps=5):
     err = float(torch.sqrt(((u - ue) ** 2).sum() + ((v - ve) ** 2).sum()) / torch.sqrt((ue ** 2).sum() + (ve ** 2).sum()))
     g.close()
     gp.close()
+    adv = (f"advection subcycled ({subcycles} low-storage RK4 substeps, cubature operator)" if subcycles
+           else "explicit nodal advection")
     return {"workload": f"Taylor vortex, {n}x{n} squares ({msh.K} triangles), N={N}, nu={nu}, dt={dt}, "
-                        "first-order splitting, pMG-PCG to 1e-8 for the u, v and pressure solves",
+                        f"first-order splitting, {adv}, pMG-PCG to 1e-8 for the u, v and pressure solves",
             "ms_per_step": round(sum(times) / len(times), 2), "solver_iters_per_step": its[-1],
             "velocity_rel_error_nodal": err}
 
@@ -692,6 +695,10 @@ def main():
         line["gradiv"] = run_gradiv(P, torch, msh)
         line["ins_step"] = run_ins_step(P, torch)
         print(f"# ins_step: {line['ins_step']}", file=sys.stderr, flush=True)
+        # the subcycled step at the same dt, and at four times the step with four substeps
+        line["ins_step_subcycled"] = [run_ins_step(P, torch, subcycles=1),
+                                      run_ins_step(P, torch, dt=4e-3, subcycles=4)]
+        print(f"# ins_step_subcycled: {line['ins_step_subcycled']}", file=sys.stderr, flush=True)
     if not args.no_subcycle:
         line["subcycle"] = run_subcycle(P, torch, msh)
     if not args.no_grad:

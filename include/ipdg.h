@@ -268,9 +268,11 @@ ipdg_status ipdg_subcycle_rhs(ipdg_mesh mesh, const double* ubar, const double* 
  * (Carpenter and Kennedy) over [0, T] for dU~/dtau = -N~(Ubar(tau), U~)
  * (Eq. SS_3), with Ubar(tau) = ubar0 + tau ubar1 and Dirichlet data
  * g(tau) = g0 + tau g1 (ubar1, vbar1, gu1, gv1 may be NULL: constant in tau;
- * gu0, gv0 NULL: zero data).  (u, v) hold U~(0) on entry and U~(T) on
- * return; the call allocates 4 K Np doubles of work and synchronises
- * hip_stream before returning.  IPDG_EINVAL for Ns < 1 or T not finite. */
+ * gu0, gv0 NULL: zero data).  (u, v) hold U~(0) on entry and U~(T) when
+ * the work enqueued on hip_stream has run.  The mesh keeps 4 K Np doubles of
+ * Runge-Kutta registers after the first call (allocated then, freed with the
+ * mesh); calls on one mesh must not overlap.  IPDG_EINVAL for Ns < 1 or T not
+ * finite. */
 ipdg_status ipdg_subcycle(ipdg_mesh mesh, const double* ubar0, const double* vbar0, const double* ubar1,
                           const double* vbar1, const double* gu0, const double* gv0, const double* gu1,
                           const double* gv1, double T, int Ns, double* u, double* v, void* hip_stream);
@@ -339,6 +341,20 @@ ipdg_status ipdg_ins_step(ipdg_mesh mesh, ipdg_mesh pmesh, double nu, double dt,
                           const double* gu_n, const double* gv_n, const double* gu_1, const double* gv_1,
                           double* u_1, double* v_1, double* p_1, double tol, const ipdg_solve_opts* vel_opts,
                           const ipdg_solve_opts* pres_opts, int* iters, void* hip_stream);
+
+/* The same step with the semi-Lagrangian subcycling of Sec. 2.3 at first
+ * order (S = 0) in place of the explicit advection step:
+ *   U^ = U~(t^{n+1}),  dU~/dt = -N~(U^n, U~),  U~(t^n) = U^n,
+ * advanced by `subcycles` substeps of ipdg_subcycle (cubature operator of
+ * Eq. KSS_3, five-stage fourth-order low-storage Runge-Kutta), the Dirichlet
+ * data of U~ linear in time from (gu_n, gv_n) to (gu_1, gv_1).  The rest of
+ * the step is that of ipdg_ins_step.  IPDG_EINVAL for subcycles < 1. */
+ipdg_status ipdg_ins_step_subcycled(ipdg_mesh mesh, ipdg_mesh pmesh, double nu, double dt, double tau,
+                                    int subcycles, const double* u_n, const double* v_n, const double* p_n,
+                                    const double* p_nm1, const double* gu_n, const double* gv_n,
+                                    const double* gu_1, const double* gv_1, double* u_1, double* v_1,
+                                    double* p_1, double tol, const ipdg_solve_opts* vel_opts,
+                                    const ipdg_solve_opts* pres_opts, int* iters, void* hip_stream);
 
 /* Host-only validation of a mesh, without any device use: the same checks
  * and face matching as ipdg_mesh_create.  EToE (neighbour element, -1 on a

@@ -217,20 +217,34 @@ def advection(m: OracleMesh, u, v, gu=None, gv=None, lax=1.0):
 
 
 def ins_step(m: OracleMesh, mp: OracleMesh, nu, dt, ctau, un, vn, pn, pnm1, gun=None, gvn=None, gu1=None,
-             gv1=None):
+             gv1=None, subcycles=0):
     """One first-order step of the algebraic splitting scheme (Sec. 2.2, Eq.
     INS_TD_3_1 to INS_TD_3_4 with gamma = beta_0 = alpha_0 = 1 and the
     pressure increment over sigma P = 2 P^n - P^{n-1}), with direct solves:
     m carries the velocity boundary flags, mp the swapped ones.  A pressure
     level without Dirichlet faces is solved with the constraint (M 1, dP) = 0
     after the constant component of its right-hand side is removed; the
-    velocity is independent of that constant (G 1 = 0 there)."""
+    velocity is independent of that constant (G 1 = 0 there).
+
+    ``subcycles`` > 0: the advection stage is the Lagrangian form of Sec. 2.3
+    at first order (S = 0): U^ = U~(t^{n+1}) with dU~/dt = -N~(U^n, U~) from
+    U~(t^n) = U^n, advanced by that many substeps of ``subcycle.subcycle``,
+    the Dirichlet data linear in time from g^n to g^{n+1}."""
     import scipy.sparse.linalg as spla
     from .assemble import assemble
     gd = GradDiv(m)
     M = gd.M
-    Nu, Nv = advection(m, un, vn, gun, gvn)
-    uh, vh = un - dt * Nu, vn - dt * Nv                       # Eq. INS_TD_3_1
+    if subcycles:
+        from .subcycle import subcycle
+        z = np.zeros_like(np.asarray(un, dtype=np.float64))
+        g0u = z if gun is None else np.asarray(gun, dtype=np.float64)
+        g0v = z if gvn is None else np.asarray(gvn, dtype=np.float64)
+        g1u = ((z if gu1 is None else np.asarray(gu1, dtype=np.float64)) - g0u) / dt
+        g1v = ((z if gv1 is None else np.asarray(gv1, dtype=np.float64)) - g0v) / dt
+        uh, vh = subcycle(m, un, vn, un, vn, dt, subcycles, gu0=g0u, gv0=g0v, gu1=g1u, gv1=g1v)
+    else:
+        Nu, Nv = advection(m, un, vn, gun, gvn)
+        uh, vh = un - dt * Nu, vn - dt * Nv                   # Eq. INS_TD_3_1
     sp_ = 2.0 * pn - pnm1
     gx, gy = gd.grad(sp_)
     A = assemble(m, 1.0 / (nu * dt), ctau)

@@ -106,24 +106,32 @@ class CubatureOps:
             self.If.append(Lf)
             self.Lc.append(Minv @ (Lf * self.wf[:, None]).T)        # (Np, Nfc)
 
-def _face_traces(m: OracleMesh, ops: CubatureOps, fields, g, e, f):
-    """Interior and exterior values of the nodal fields (Ubar, Vbar, U~, V~)
-    at the face cubature nodes of face f of element e.  The exterior trace is
-    evaluated in the neighbour at the same physical points (mapped back to its
-    reference coordinates), or taken from the boundary rule (g: the data of
-    U~, V~)."""
+def face_maps(m: OracleMesh, ops: CubatureOps, e, f):
+    """Interpolation of face f of element e to its cubature points: the
+    interior trace matrix (Nfc x Np, in element e), the exterior one (in the
+    neighbour, at the same physical points mapped back to its reference
+    coordinates; None on a boundary face), the face length and the outward
+    unit normal."""
     xa, ya, xb, yb, length, nx, ny = m.face_geometry(e, f)
     t = ops.tf
     px = xa + 0.5 * (1.0 + t) * (xb - xa)
     py = ya + 0.5 * (1.0 + t) * (yb - ya)
-    r, s = m.to_ref(e, px, py)
-    L, _, _ = ops.ref.lagrange(r, s)
+    L, _, _ = ops.ref.lagrange(*m.to_ref(e, px, py))
+    nb = m.EToE[e, f]
+    Ln = ops.ref.lagrange(*m.to_ref(nb, px, py))[0] if nb >= 0 else None
+    return L, Ln, length, nx, ny
+
+
+def _face_traces(m: OracleMesh, fm, fields, g, e, f):
+    """Interior and exterior values of the nodal fields (Ubar, Vbar, U~, V~)
+    at the face cubature nodes of face f of element e, from its face maps
+    ``fm``; on a boundary face the exterior trace follows the boundary rule
+    (g: the data of U~, V~)."""
+    L, Ln, length, nx, ny = fm
     minus = [L @ F[e] for F in fields]
     bc = m.EToB[e, f]
     nb = m.EToE[e, f]
     if nb >= 0:
-        rn, sn = m.to_ref(nb, px, py)
-        Ln, _, _ = ops.ref.lagrange(rn, sn)
         plus = [Ln @ F[nb] for F in fields]
     elif bc == BC_DIRICHLET:
         plus = [minus[0].copy(), minus[1].copy()] + [L @ G[e] for G in g]
@@ -133,11 +141,15 @@ def _face_traces(m: OracleMesh, ops: CubatureOps, fields, g, e, f):
         raise ValueError("unmatched face without a boundary rule")
     return minus, plus, length, nx, ny
 
-def advection_operator(m: OracleMesh, ubar, vbar, u, v, gu=None, gv=None, parts=3, ops=None, elems=None):
+
+def advection_operator(m: OracleMesh, ubar, vbar, u, v, gu=None, gv=None, parts=3, ops=None, elems=None,
+                       maps=None):
     """N~(Ubar, U~) of Eq. KSS_3 for both velocity components, as nodal
     fields (K Np each): parts = 1 the volume term, 2 the surface term, 3 both.
     Dirichlet data (gu, gv) give the exterior trace of U~ there (None = 0).
-    ``elems``: compute only these elements' rows (returned in that order)."""
+    ``elems``: compute only these elements' rows (returned in that order).
+    ``maps``: the face maps of every (e, f) from ``face_maps``, if already
+    built (they depend only on the mesh)."""
     ops = ops or CubatureOps(m.N)
     K, Np = m.K, m.Np
     E = np.arange(K) if elems is None else np.asarray(elems, dtype=np.int64)
@@ -156,8 +168,9 @@ def advection_operator(m: OracleMesh, ubar, vbar, u, v, gu=None, gv=None, parts=
     if parts & 2:
         for row, e in enumerate(E):
             for f in range(3):
+                fm = maps[e][f] if maps is not None else face_maps(m, ops, e, f)
                 (ubm, vbm, um, vm), (ubp, vbp, up, vp), length, nx, ny = _face_traces(
-                    m, ops, (UB, VB, U, V), (GU, GV), e, f)
+                    m, fm, (UB, VB, U, V), (GU, GV), e, f)
                 anm = nx * ubm + ny * vbm
                 anp = nx * ubp + ny * vbp
                 lam = np.maximum(np.abs(anm), np.abs(anp))
@@ -174,6 +187,7 @@ def subcycle(m: OracleMesh, ubar0, vbar0, u, v, T, Ns, ubar1=None, vbar1=None, g
     -N~(Ubar(t), U~) with Ubar(t) = Ubar0 + t Ubar1 and Dirichlet data
     g(t) = g0 + t g1 (Sec. 2.3, Eq. SS_3).  Returns U~(T)."""
     ops = CubatureOps(m.N)
+    maps = [[face_maps(m, ops, e, f) for f in range(3)] for e in range(m.K)]
     n = m.K * m.Np
     z = np.zeros(n)
     arr = lambda a: z if a is None else np.asarray(a, dtype=np.float64).ravel()
@@ -189,7 +203,7 @@ def subcycle(m: OracleMesh, ubar0, vbar0, u, v, T, Ns, ubar1=None, vbar1=None, g
         for k in range(5):
             t = t0 + LSERK_C[k] * dt
             Nu, Nv = advection_operator(m, UB0 + t * UB1, VB0 + t * VB1, U, V, G0u + t * G1u, G0v + t * G1v,
-                                        ops=ops)
+                                        ops=ops, maps=maps)
             du = LSERK_A[k] * du - dt * Nu
             dv = LSERK_A[k] * dv - dt * Nv
             U = U + LSERK_B[k] * du

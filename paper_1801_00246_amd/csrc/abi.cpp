@@ -533,14 +533,17 @@ ipdg_status ipdg_ins_correct(ipdg_mesh mesh, double gamma, double dt, const doub
   });
 }
 
-ipdg_status ipdg_ins_step(ipdg_mesh mesh, ipdg_mesh pmesh, double nu, double dt, double tau,
-                          const double* u_n, const double* v_n, const double* p_n, const double* p_nm1,
-                          const double* gu_n, const double* gv_n, const double* gu_1, const double* gv_1,
-                          double* u_1, double* v_1, double* p_1, double tol, const ipdg_solve_opts* vel_opts,
-                          const ipdg_solve_opts* pres_opts, int* iters, void* hip_stream) {
+namespace {
+
+ipdg_status ins_step_entry(ipdg_mesh mesh, ipdg_mesh pmesh, double nu, double dt, double tau, int subcycles,
+                           const double* u_n, const double* v_n, const double* p_n, const double* p_nm1,
+                           const double* gu_n, const double* gv_n, const double* gu_1, const double* gv_1,
+                           double* u_1, double* v_1, double* p_1, double tol, const ipdg_solve_opts* vel_opts,
+                           const ipdg_solve_opts* pres_opts, int* iters, void* hip_stream) {
   return guarded([&]() -> ipdg_status {
     if (!mesh || !pmesh) return fail(IPDG_EINVAL, "mesh is null");
     if (mesh->device != pmesh->device) return fail(IPDG_EINVAL, "the two meshes live on different devices");
+    if (subcycles < 0) return fail(IPDG_EINVAL, "subcycles must not be negative");
     if (mesh->host.K == 0) return IPDG_OK;
     if (!u_n || !v_n || !p_n || !p_nm1 || !u_1 || !v_1 || !p_1) return fail(IPDG_EINVAL, "null vector");
     if (!(tol > 0.0)) return fail(IPDG_EINVAL, "tol must be positive");
@@ -557,6 +560,7 @@ ipdg_status ipdg_ins_step(ipdg_mesh mesh, ipdg_mesh pmesh, double nu, double dt,
     in.p_prev = p_nm1;
     in.gu = gu_n;
     in.gv = gv_n;
+    in.subcycles = subcycles;
     ipdg::InsOut out;
     out.u = u_1;
     out.v = v_1;
@@ -566,6 +570,28 @@ ipdg_status ipdg_ins_step(ipdg_mesh mesh, ipdg_mesh pmesh, double nu, double dt,
     return ipdg::ins_step(mesh, pmesh, nu, dt, tau, in, out, tol, vo, po, iters,
                           static_cast<hipStream_t>(hip_stream));
   });
+}
+
+}  // namespace
+
+ipdg_status ipdg_ins_step(ipdg_mesh mesh, ipdg_mesh pmesh, double nu, double dt, double tau,
+                          const double* u_n, const double* v_n, const double* p_n, const double* p_nm1,
+                          const double* gu_n, const double* gv_n, const double* gu_1, const double* gv_1,
+                          double* u_1, double* v_1, double* p_1, double tol, const ipdg_solve_opts* vel_opts,
+                          const ipdg_solve_opts* pres_opts, int* iters, void* hip_stream) {
+  return ins_step_entry(mesh, pmesh, nu, dt, tau, 0, u_n, v_n, p_n, p_nm1, gu_n, gv_n, gu_1, gv_1, u_1, v_1, p_1,
+                        tol, vel_opts, pres_opts, iters, hip_stream);
+}
+
+ipdg_status ipdg_ins_step_subcycled(ipdg_mesh mesh, ipdg_mesh pmesh, double nu, double dt, double tau,
+                                    int subcycles, const double* u_n, const double* v_n, const double* p_n,
+                                    const double* p_nm1, const double* gu_n, const double* gv_n,
+                                    const double* gu_1, const double* gv_1, double* u_1, double* v_1,
+                                    double* p_1, double tol, const ipdg_solve_opts* vel_opts,
+                                    const ipdg_solve_opts* pres_opts, int* iters, void* hip_stream) {
+  if (subcycles < 1) return fail(IPDG_EINVAL, "subcycles must be at least 1");
+  return ins_step_entry(mesh, pmesh, nu, dt, tau, subcycles, u_n, v_n, p_n, p_nm1, gu_n, gv_n, gu_1, gv_1, u_1,
+                        v_1, p_1, tol, vel_opts, pres_opts, iters, hip_stream);
 }
 
 ipdg_status ipdg_subcycle_rhs(ipdg_mesh mesh, const double* ubar, const double* vbar, const double* u,

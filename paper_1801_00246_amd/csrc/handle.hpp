@@ -73,6 +73,7 @@ struct ipdg_mesh_s {
   unsigned kappa_version = 0;     // changes whenever the coefficient values change
   ipdg::DevBuf geo64, geo32, conn, kap64, kap32;
   ipdg::DevBuf ones64;            // kappa = 1 for the coefficient gradient of a plain mesh
+  ipdg::DevBuf sub_work;          // Runge-Kutta registers of the subcycle (4 K Np doubles)
   std::unique_ptr<ipdg::SolverWork> work;
   ~ipdg_mesh_s();
 };

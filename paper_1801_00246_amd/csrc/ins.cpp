@@ -7,6 +7,11 @@
 //   -Lap dP = -(gamma / dt) D U^^                            (Eq. INS_TD_3_3)
 //   U^{n+1} = U^^ - (dt / gamma) G dP,  P^{n+1} = dP + sigma P   (Eq. INS_TD_3_4)
 //
+// With subcycles > 0 the first line is the Lagrangian form of Sec. 2.3 at
+// first order (S = 0): U^ = U~(t^{n+1}), where dU~/dt = -N~(U^n, U~) is
+// advanced from U~(t^n) = U^n by that many low-storage Runge-Kutta substeps,
+// the Dirichlet data of U~ interpolated linearly between t^n and t^{n+1}.
+//
 // Every step runs in the library's kernels (advection, gradient,
 // divergence, Dirichlet data, vector updates) and its PCG; the velocity mesh
 // carries the velocity boundary flags, the pressure mesh the same triangles
@@ -19,6 +24,7 @@
 #include "gradiv.hpp"
 #include "ins.hpp"
 #include "solver.hpp"
+#include "subcycle.hpp"
 
 namespace ipdg {
 
@@ -35,11 +41,36 @@ ipdg_status ins_step(ipdg_mesh_s* m, ipdg_mesh_s* pm, double nu, double dt, doub
   const double* geo = m->geo64.as<double>();
   const Conn* conn = m->conn.as<Conn>();
   const double* ops = static_cast<const double*>(device_ops(N, Kind::F64));
-  DevBuf work(9 * n * sizeof(double) + 64);
+  const bool sub = in.subcycles > 0;
+  const bool data = in.gu || in.gv || out.gu || out.gv;
+  DevBuf work(((sub && data) ? 13 : 9) * n * sizeof(double) + 64);
   double* w = work.as<double>();
   double *uh = w, *vh = w + n, *bu = w + 2 * n, *bv = w + 3 * n, *uhh = w + 4 * n, *vhh = w + 5 * n;
   double *bp = w + 6 * n, *dp = w + 7 * n, *sp = w + 8 * n;
   double* scal = w + 9 * n;
+
+  if (sub) {
+    // Sec. 2.3: U^ = U~(t^{n+1}) with Ubar = U^n; data g(tau) = g^n + tau (g^{n+1} - g^n) / dt
+    SubArgs sa;
+    sa.ub0 = in.u;
+    sa.vb0 = in.v;
+    if (data) {
+      double *g0u = w + 9 * n + 8, *g0v = g0u + n, *g1u = g0v + n, *g1v = g1u + n;
+      IPDG_HIP(hipMemsetAsync(g0u, 0, 4 * n * sizeof(double), s));
+      if (in.gu) IPDG_HIP(hipMemcpyAsync(g0u, in.gu, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+      if (in.gv) IPDG_HIP(hipMemcpyAsync(g0v, in.gv, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+      // g1 = (g^{n+1} - g^n) / dt (absent data are zero)
+      IPDG_HIP(axpby(1.0 / dt, out.gu ? out.gu : g1u, -1.0 / dt, g0u, g1u, n, s));
+      IPDG_HIP(axpby(1.0 / dt, out.gv ? out.gv : g1v, -1.0 / dt, g0v, g1v, n, s));
+      sa.gu0 = g0u;
+      sa.gv0 = g0v;
+      sa.gu1 = g1u;
+      sa.gv1 = g1v;
+    }
+    IPDG_HIP(hipMemcpyAsync(uh, in.u, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    IPDG_HIP(hipMemcpyAsync(vh, in.v, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    subcycle_advect(m, sa, dt, in.subcycles, uh, vh, s);
+  }
 
   // Eq. INS_TD_3_1 (data at t^n)
   AdvectArgs aa;
@@ -57,7 +88,7 @@ ipdg_status ins_step(ipdg_mesh_s* m, ipdg_mesh_s* pm, double nu, double dt, doub
   aa.conn = conn;
   aa.ops = ops;
   aa.K = K;
-  IPDG_HIP(advect_apply(N, aa, s));
+  if (!sub) IPDG_HIP(advect_apply(N, aa, s));
   IPDG_HIP(axpby(2.0, in.p, -1.0, in.p_prev, sp, n, s));
 
   // Eq. INS_TD_3_2 (data at t^{n+1})

@@ -13,6 +13,9 @@ struct InsState {
   const double* p_prev = nullptr;   // input only: P^{n-1}
   const double* gu = nullptr;
   const double* gv = nullptr;
+  // > 0: the advection stage is the semi-Lagrangian subcycle (Sec. 2.3) of
+  // this many Runge-Kutta substeps instead of one explicit step
+  int subcycles = 0;
 };
 struct InsOut {
   double* u = nullptr;

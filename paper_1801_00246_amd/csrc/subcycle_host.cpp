@@ -107,8 +107,8 @@ void subcycle_rhs(ipdg_mesh_s* m, const SubArgs& in, int parts, double* nu, doub
 
 void subcycle_advect(ipdg_mesh_s* m, const SubArgs& in, double T, int Ns, double* u, double* v, hipStream_t s) {
   const size_t n = (size_t)m->host.K * m->Np;
-  DevBuf work(4 * n * sizeof(double));
-  double* w = work.as<double>();
+  m->sub_work.ensure(4 * n * sizeof(double));
+  double* w = m->sub_work.as<double>();
   SubArgs a = with_mesh(m, in);
   a.res_u = w;
   a.res_v = w + n;
@@ -135,8 +135,6 @@ void subcycle_advect(ipdg_mesh_s* m, const SubArgs& in, double T, int Ns, double
     IPDG_HIP(hipMemcpyAsync(u, cur_u, n * sizeof(double), hipMemcpyDeviceToDevice, s));
     IPDG_HIP(hipMemcpyAsync(v, cur_v, n * sizeof(double), hipMemcpyDeviceToDevice, s));
   }
-  // the work buffer is released on return
-  IPDG_HIP(hipStreamSynchronize(s));
 }
 
 }  // namespace ipdg

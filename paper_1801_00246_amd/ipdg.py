@@ -82,6 +82,8 @@ _SIGS = {
     "ipdg_grad": (C.c_int, [_P, _P, _P, _P, _P]),
     "ipdg_dirichlet_rhs": (C.c_int, [_P, C.c_double, _P, _P, _P]),
     "ipdg_ins_step": (C.c_int, [_P, _P, C.c_double, C.c_double, C.c_double] + [_P] * 11 + [C.c_double, _P, _P, _P, _P]),
+    "ipdg_ins_step_subcycled": (C.c_int, [_P, _P, C.c_double, C.c_double, C.c_double, C.c_int] + [_P] * 11
+                                + [C.c_double, _P, _P, _P, _P]),
     "ipdg_div": (C.c_int, [_P, _P, _P, _P, _P, _P, _P]),
     "ipdg_subcycle_rhs": (C.c_int, [_P] * 7 + [C.c_int, _P, _P, _P]),
     "ipdg_subcycle": (C.c_int, [_P] * 9 + [C.c_double, C.c_int, _P, _P, _P]),
@@ -408,19 +410,24 @@ class Mesh:
         return uo, vo, po
 
     def ins_step(self, pmesh, nu, dt, u, v, p, p_prev, gu_n=None, gv_n=None, gu_1=None, gv_1=None, tau=0.0,
-                 tol=1e-10, vel_opts=None, pres_opts=None, stream=None):
-        """One first-order step of the splitting scheme (ipdg_ins_step);
-        returns (u, v, p) at t^{n+1} and the three solves' iteration counts."""
+                 tol=1e-10, vel_opts=None, pres_opts=None, subcycles=0, stream=None):
+        """One first-order step of the splitting scheme (ipdg_ins_step, or
+        ipdg_ins_step_subcycled when subcycles > 0); returns (u, v, p) at
+        t^{n+1} and the three solves' iteration counts."""
         import torch
         u1, v1, p1 = torch.empty_like(u), torch.empty_like(v), torch.empty_like(p)
         it = (C.c_int * 3)()
         vo = C.byref(vel_opts) if vel_opts is not None else None
         po = C.byref(pres_opts) if pres_opts is not None else None
-        check(lib().ipdg_ins_step(self._h, pmesh.handle, float(nu), float(dt), float(tau), self._vec(u, "u"),
-                                  self._vec(v, "v"), self._vec(p, "p"), self._vec(p_prev, "p_prev"),
-                                  self._opt(gu_n, "gu_n"), self._opt(gv_n, "gv_n"), self._opt(gu_1, "gu_1"),
-                                  self._opt(gv_1, "gv_1"), self._vec(u1, "u_1"), self._vec(v1, "v_1"),
-                                  self._vec(p1, "p_1"), float(tol), vo, po, it, _stream(stream)))
+        vecs = (self._vec(u, "u"), self._vec(v, "v"), self._vec(p, "p"), self._vec(p_prev, "p_prev"),
+                self._opt(gu_n, "gu_n"), self._opt(gv_n, "gv_n"), self._opt(gu_1, "gu_1"), self._opt(gv_1, "gv_1"),
+                self._vec(u1, "u_1"), self._vec(v1, "v_1"), self._vec(p1, "p_1"))
+        if subcycles:
+            check(lib().ipdg_ins_step_subcycled(self._h, pmesh.handle, float(nu), float(dt), float(tau),
+                                                int(subcycles), *vecs, float(tol), vo, po, it, _stream(stream)))
+        else:
+            check(lib().ipdg_ins_step(self._h, pmesh.handle, float(nu), float(dt), float(tau), *vecs, float(tol),
+                                      vo, po, it, _stream(stream)))
         return u1, v1, p1, list(it)
 
     def subcycle_rhs(self, ubar, vbar, u, v, gu=None, gv=None, parts=3, stream=None):
