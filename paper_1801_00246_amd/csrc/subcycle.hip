@@ -36,7 +36,7 @@ __device__ __forceinline__ v4d mma(double a, double b, v4d c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
-constexpr int kSubWaves = 4;   // waves per block, 16 elements each
+constexpr int kSubWaves = 2;   // waves per block, 16 elements each (two blocks of 2 waves beat one of 4)
 
 // x0[i] + tau x1[i] (x1 may be null)
 __device__ __forceinline__ double lin(const double* __restrict__ x0, const double* __restrict__ x1, double tau,
@@ -122,7 +122,7 @@ __global__ __launch_bounds__(64 * kSubWaves) void k_subcycle(SubArgs a) {
 
   if constexpr ((PARTS & 2) != 0) {
     const Conn c = a.conn[ec];
-#pragma unroll 1
+#pragma unroll
     for (int f = 0; f < 3; ++f) {
       const int bc = conn_bc(c.info, f), fp = conn_fp(c.info, f), nb = c.nb[f];
       // traces at face node 4 kb + l/16 (in this element's orientation):
