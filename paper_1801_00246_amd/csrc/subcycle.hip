@@ -192,6 +192,26 @@ __global__ __launch_bounds__(64 * kSubWaves) void k_subcycle(SubArgs a) {
     }
   }
 
+  const int ne = a.K - e0 < 16 ? a.K - e0 : 16;
+  const size_t g0 = (size_t)e0 * Np;
+  // Runge-Kutta stage at degrees whose wave covers at most 6 values per lane
+  // and register (N <= 5): the registers' old values are loaded before the
+  // staging barrier, so that their latency overlaps it (beyond that the extra
+  // live values cost more than they hide)
+  constexpr int kIt = (16 * Np + 63) / 64;
+  constexpr bool kPre = STAGE && kIt <= 6;
+  double oru[kPre ? kIt : 1], orv[kPre ? kIt : 1], ou[kPre ? kIt : 1], ov[kPre ? kIt : 1];
+  if constexpr (kPre) {
+#pragma unroll
+    for (int j = 0; j < kIt; ++j) {
+      const int idx = lane + 64 * j;
+      const size_t gi = idx < ne * Np ? g0 + idx : 0;   // index 0 is valid (K >= 1)
+      oru[j] = a.rk_a != 0.0 ? a.res_u[gi] : 0.0;
+      orv[j] = a.rk_a != 0.0 ? a.res_v[gi] : 0.0;
+      ou[j] = u[gi];
+      ov[j] = v[gi];
+    }
+  }
   // accumulator entry r of lane l: node 16 R + l/16 + 4 r of element l%16
   double* su = stage[w][0];
   double* sv = stage[w][1];
@@ -206,20 +226,34 @@ __global__ __launch_bounds__(64 * kSubWaves) void k_subcycle(SubArgs a) {
       }
     }
   __syncthreads();
-  const int ne = a.K - e0 < 16 ? a.K - e0 : 16;
-  const size_t g0 = (size_t)e0 * Np;
-  for (int idx = lane; idx < ne * Np; idx += 64) {
-    const size_t gi = g0 + idx;
-    if constexpr (!STAGE) {
-      a.out_u[gi] = su[idx];
-      a.out_v[gi] = sv[idx];
-    } else {
-      const double ru = (a.rk_a != 0.0 ? a.rk_a * a.res_u[gi] : 0.0) - a.dt * su[idx];
-      const double rv = (a.rk_a != 0.0 ? a.rk_a * a.res_v[gi] : 0.0) - a.dt * sv[idx];
-      a.res_u[gi] = ru;
-      a.res_v[gi] = rv;
-      a.new_u[gi] = u[gi] + a.rk_b * ru;
-      a.new_v[gi] = v[gi] + a.rk_b * rv;
+  if constexpr (kPre) {
+#pragma unroll
+    for (int j = 0; j < kIt; ++j) {
+      const int idx = lane + 64 * j;
+      if (idx < ne * Np) {
+        const size_t gi = g0 + idx;
+        const double ru = a.rk_a * oru[j] - a.dt * su[idx];
+        const double rv = a.rk_a * orv[j] - a.dt * sv[idx];
+        a.res_u[gi] = ru;
+        a.res_v[gi] = rv;
+        a.new_u[gi] = ou[j] + a.rk_b * ru;
+        a.new_v[gi] = ov[j] + a.rk_b * rv;
+      }
+    }
+  } else {
+    for (int idx = lane; idx < ne * Np; idx += 64) {
+      const size_t gi = g0 + idx;
+      if constexpr (!STAGE) {
+        a.out_u[gi] = su[idx];
+        a.out_v[gi] = sv[idx];
+      } else {
+        const double ru = (a.rk_a != 0.0 ? a.rk_a * a.res_u[gi] : 0.0) - a.dt * su[idx];
+        const double rv = (a.rk_a != 0.0 ? a.rk_a * a.res_v[gi] : 0.0) - a.dt * sv[idx];
+        a.res_u[gi] = ru;
+        a.res_v[gi] = rv;
+        a.new_u[gi] = u[gi] + a.rk_b * ru;
+        a.new_v[gi] = v[gi] + a.rk_b * rv;
+      }
     }
   }
 }

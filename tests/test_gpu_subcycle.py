@@ -166,3 +166,37 @@ def test_errors():
     with pytest.raises(P.IpdgError):
         g.subcycle(z, z, z, z, float("nan"), 2)
     g.close()
+
+
+def test_single_element_and_empty_mesh():
+    # one triangle: one wave whose other 15 columns read the same element and
+    # store nothing; Dirichlet and Neumann faces
+    VX = np.array([0.0, 1.0, 0.2])
+    VY = np.array([0.0, 0.1, 0.9])
+    EToV = np.array([[0, 1, 2]])
+    EToB = np.array([[P.BC_DIRICHLET, P.BC_NEUMANN, P.BC_DIRICHLET]], np.int8)
+    for N in (1, 8):
+        m = OracleMesh(VX, VY, EToV, EToB, N)
+        rng = np.random.default_rng(N)
+        ub, vb, u, v, gu, gv = (rng.standard_normal(m.Np) for _ in range(6))
+        g = P.Mesh(N, VX, VY, EToV, EToB)
+        nu, nv = g.subcycle_rhs(dev(ub), dev(vb), dev(u), dev(v), dev(gu), dev(gv))
+        ou, ov = advection_operator(m, ub, vb, u, v, gu, gv)
+        assert max(rel(host(nu), ou), rel(host(nv), ov)) <= 1e-12
+        su, sv = g.subcycle(dev(ub), dev(vb), dev(u), dev(v), 1e-3, 3, gu0=dev(gu), gv0=dev(gv))
+        tu, tv = subcycle(m, ub, vb, u, v, 1e-3, 3, gu0=gu, gv0=gv)
+        assert max(rel(host(su), tu), rel(host(sv), tv)) <= 1e-12
+        g.close()
+    # an empty mesh: both calls are no-ops
+    g0 = P.Mesh(3, np.zeros(0), np.zeros(0), np.zeros((0, 3), np.int32), np.zeros((0, 3), np.int8))
+    assert g0.K == 0
+    P.ipdg.check(P.lib().ipdg_subcycle_rhs(g0.handle, None, None, None, None, None, None, 3, None, None, None))
+    P.ipdg.check(P.lib().ipdg_subcycle(g0.handle, None, None, None, None, None, None, None, None, 0.1, 2, None, None,
+                                       None))
+    # a vector of the wrong length is refused by the binding
+    msh = synth.square_mesh(3)
+    g = P.Mesh.from_synth(2, msh)
+    z = torch.zeros(g.ndof, dtype=torch.float64, device="cuda")
+    with pytest.raises(ValueError):
+        g.subcycle_rhs(z[:-1], z, z, z)
+    g.close()
