@@ -46,8 +46,24 @@ __device__ __forceinline__ double lin(const double* __restrict__ x0, const doubl
   return x;
 }
 
+// Waves per SIMD the kernels are compiled for (measured per degree on
+// 524,288 triangles).  Left alone, the compiler gives the volume and fused
+// kernels one or two waves from degree 7, with the wave's latency exposed;
+// two are 1.2-1.7x faster there.  Three are 10-16 % faster for the fused
+// kernel at degrees 3 and 4 and a few per cent for the volume kernel at 3-6;
+// the fused kernel at 5 and 6 and the surface kernel keep the compiler's
+// choice.
+template <int N, int PARTS>
+constexpr int sub_waves_per_eu() {
+  if (PARTS == 2) return 1;
+  if (N >= 7) return 2;
+  if (PARTS == 3) return N == 3 || N == 4 ? 3 : 1;
+  return N >= 3 ? 3 : 1;
+}
+
 template <int N, int PARTS, bool STAGE>
-__global__ __launch_bounds__(64 * kSubWaves) void k_subcycle(SubArgs a) {
+__global__ __launch_bounds__(64 * kSubWaves) __attribute__((amdgpu_waves_per_eu(sub_waves_per_eu<N, PARTS>())))
+void k_subcycle(SubArgs a) {
   using Tr = Tri<N>;
   constexpr SubDims D = sub_dims(N);
   constexpr int Np = D.Np, Nfp = D.Nfp;
@@ -194,12 +210,12 @@ __global__ __launch_bounds__(64 * kSubWaves) void k_subcycle(SubArgs a) {
 
   const int ne = a.K - e0 < 16 ? a.K - e0 : 16;
   const size_t g0 = (size_t)e0 * Np;
-  // Runge-Kutta stage at degrees whose wave covers at most 6 values per lane
-  // and register (N <= 5): the registers' old values are loaded before the
+  // Runge-Kutta stage at degrees whose wave covers at most 7 values per lane
+  // and register (N <= 6): the registers' old values are loaded before the
   // staging barrier, so that their latency overlaps it (beyond that the extra
   // live values cost more than they hide)
   constexpr int kIt = (16 * Np + 63) / 64;
-  constexpr bool kPre = STAGE && kIt <= 6;
+  constexpr bool kPre = STAGE && kIt <= 7;
   double oru[kPre ? kIt : 1], orv[kPre ? kIt : 1], ou[kPre ? kIt : 1], ov[kPre ? kIt : 1];
   if constexpr (kPre) {
 #pragma unroll
