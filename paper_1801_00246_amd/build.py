@@ -27,7 +27,7 @@ FLAGS = [
     "-I", os.path.join(ROOT, "include"),
 ]
 HOST_SOURCES = ["refelem.cpp", "mesh_host.cpp", "ops_table.cpp", "mesh.cpp", "dispatch.cpp",
-                "amg_host.cpp", "solver.cpp", "ins.cpp", "subcycle_host.cpp", "abi.cpp"]
+                "amg_host.cpp", "solver.cpp", "ins.cpp", "subcycle_host.cpp", "gradiv_host.cpp", "abi.cpp"]
 DEVICE_SOURCES = ["blas.hip", "noalloc.hip", "probe.hip", "amg.hip", "gradiv.hip", "subcycle.hip"]
 DEGREES = range(1, 9)
 

@@ -3,11 +3,14 @@
 //   G p = grad p + LIFT (|F|/|E|) n (p* - p-),
 //   D u = div u  + LIFT (|F|/|E|) n . (u* - u-),
 // p* = {p}, u* = {u} on interior faces; on Dirichlet (velocity) faces
-// u* = g_D and p* = p-, on Neumann faces u* = u- and p* = 0.  One element per
-// lane; the reference operators D_r, D_s, LIFT and M come from the degree's
-// FP64 table through wave-uniform loads, the normals and face scales
-// |F|/|E| from the element's metric terms (face 0: -grad s, face 1:
-// grad r + grad s, face 2: -grad r; each vector's length is |F|/|E|).
+// u* = g_D and p* = p-, on Neumann faces u* = u- and p* = 0.  The divergence,
+// and the gradient from degree 2, run on the matrix cores, 16 elements per
+// wave (the form below `Matrix-core form`); the gradient at degree 1, the
+// advection term and the Dirichlet-data terms run one element per lane, the
+// reference operators read from the degree's FP64 table through wave-uniform
+// loads.  Normals and face scales |F|/|E| come from the element's metric
+// terms (face 0: -grad s, face 1: grad r + grad s, face 2: -grad r; each
+// vector's length is |F|/|E|).
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -156,76 +159,212 @@ __global__ __launch_bounds__(kElems<N>()) void k_grad(GradArgs a) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// Matrix-core form (layout GdDims in gradiv.hpp; the divergence at every
+// degree, the gradient from degree 2).  A wave
+// computes 16 elements as the columns of 16 x 16 blocks of
+// v_mfma_f64_16x16x4f64: D_r and D_s times the elements' nodal values (B
+// operands in registers), the face terms as LIFT_f times the face-node fluxes
+// (B operands formed per lane from the gathered traces), the metric terms
+// applied lane by lane on the accumulators.  With the mass option the
+// accumulators are fed back as B operands of J M: accumulator entry r of lane
+// l is row l/16 + 4 r of its block, the B operand of k-step r.  Outputs leave
+// through LDS as one contiguous block per wave.
+// ---------------------------------------------------------------------------
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ v4d mma(double a, double b, v4d c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+constexpr int kGdWaves = 2;   // waves per block, 16 elements each
+
+// J M g for the wave's 16 columns (g in accumulator layout, RB blocks)
+template <int N>
+__device__ __forceinline__ void mf_mass(const double* __restrict__ tab, int lane, double J,
+                                        v4d (&g)[gd_dims(N).RB]) {
+  constexpr GdDims D = gd_dims(N);
+  v4d m[D.RB];
+#pragma unroll
+  for (int R = 0; R < D.RB; ++R) m[R] = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int R2 = 0; R2 < D.RB; ++R2)
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int R = 0; R < D.RB; ++R) m[R] = mma(tab[D.oM + ((R * D.RB + R2) * 4 + t) * 64 + lane], g[R2][t], m[R]);
+#pragma unroll
+  for (int R = 0; R < D.RB; ++R) g[R] = J * m[R];
+}
+
+// the wave's 16 columns (accumulator layout) into its LDS block, element-major
+template <int N>
+__device__ __forceinline__ void mf_stage(double* st, int nn, int kk, const v4d (&g)[gd_dims(N).RB]) {
+  constexpr GdDims D = gd_dims(N);
+#pragma unroll
+  for (int R = 0; R < D.RB; ++R)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int n = 16 * R + kk + 4 * r;
+      if (n < D.Np) st[nn * D.Np + n] = g[R][r];
+    }
+}
+
 template <int N, bool MASS>
-__global__ __launch_bounds__(kElems<N>()) void k_div(DivArgs a) {
+__global__ __launch_bounds__(64 * kGdWaves) void k_grad_mf(GradArgs a, const double* __restrict__ tab) {
   using T = Tri<N>;
-  using L = OpsLayout<N>;
-  constexpr int Np = T::Np, Nfp = T::Nfp, B = kElems<N>(), P = kPitchGD<N>();
-  __shared__ double buf[B * P];
-  const int e0 = blockIdx.x * B;
-  const int n = min(B, a.K - e0);
-  const double* __restrict__ ops = a.ops;
+  constexpr GdDims D = gd_dims(N);
+  constexpr int Np = D.Np, Nfp = D.Nfp;
+  __shared__ double stage[kGdWaves][2][16 * Np];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int nn = lane & 15, kk = lane >> 4;
+  const int e0 = (blockIdx.x * kGdWaves + w) * 16;
+  const int ec = e0 + nn < a.K ? e0 + nn : a.K - 1;   // lanes past the end read a valid element
+  const double* __restrict__ p = a.p;
+  const double rx = a.geo[4 * (size_t)ec], sx = a.geo[4 * (size_t)ec + 1];
+  const double ry = a.geo[4 * (size_t)ec + 2], sy = a.geo[4 * (size_t)ec + 3];
+  v4d gr[D.RB], gs[D.RB], fx[D.RB], fy[D.RB];
+#pragma unroll
+  for (int R = 0; R < D.RB; ++R) gr[R] = gs[R] = fx[R] = fy[R] = v4d{0.0, 0.0, 0.0, 0.0};
+  {
+    double pb[D.KB];
+#pragma unroll
+    for (int kb = 0; kb < D.KB; ++kb) pb[kb] = p[(size_t)ec * Np + (4 * kb + kk < Np ? 4 * kb + kk : Np - 1)];
+#pragma unroll
+    for (int kb = 0; kb < D.KB; ++kb)
+#pragma unroll
+      for (int R = 0; R < D.RB; ++R) {
+        gr[R] = mma(tab[D.oDr + (R * D.KB + kb) * 64 + lane], pb[kb], gr[R]);
+        gs[R] = mma(tab[D.oDs + (R * D.KB + kb) * 64 + lane], pb[kb], gs[R]);
+      }
+  }
+  // face terms: LIFT_f ((|F|/|E|) n (p* - p-)) at the face nodes
+  const Conn c = a.conn[ec];
+#pragma unroll
+  for (int f = 0; f < 3; ++f) {
+    const int bc = conn_bc(c.info, f), fp = conn_fp(c.info, f), nb = c.nb[f];
+    double ax, ay;
+    face_vec(f, rx, sx, ry, sy, ax, ay);
+#pragma unroll
+    for (int kb = 0; kb < D.KF; ++kb) {
+      const int k = 4 * kb + kk < Nfp ? 4 * kb + kk : Nfp - 1;
+      const double pm = p[(size_t)ec * Np + T::fm(f, k)];
+      // Dirichlet: p* = p-; Neumann: p* = 0; interior: p* = {p}
+      const double fl = bc == 1 ? 0.0 : (bc == 0 ? 0.5 * (p[(size_t)nb * Np + T::fm(fp, N - k)] - pm) : -pm);
+#pragma unroll
+      for (int R = 0; R < D.RB; ++R) {
+        const double L = tab[D.oL + ((f * D.RB + R) * D.KF + kb) * 64 + lane];
+        fx[R] = mma(L, ax * fl, fx[R]);
+        fy[R] = mma(L, ay * fl, fy[R]);
+      }
+    }
+  }
+  // metric terms, scaling and the optional base fields (rows 16 R + l/16 + 4 r)
+#pragma unroll
+  for (int R = 0; R < D.RB; ++R)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      double vx = a.a_grad * (rx * gr[R][r] + sx * gs[R][r] + fx[R][r]);
+      double vy = a.a_grad * (ry * gr[R][r] + sy * gs[R][r] + fy[R][r]);
+      if (a.base_x) {
+        const int n = 16 * R + kk + 4 * r;
+        const size_t i = (size_t)ec * Np + (n < Np ? n : Np - 1);
+        vx += a.a_base * a.base_x[i];
+        vy += a.a_base * a.base_y[i];
+      }
+      gr[R][r] = vx;
+      gs[R][r] = vy;
+    }
+  if constexpr (MASS) {
+    const double J = 1.0 / (rx * sy - ry * sx);
+    mf_mass<N>(tab, lane, J, gr);
+    mf_mass<N>(tab, lane, J, gs);
+  }
+  mf_stage<N>(stage[w][0], nn, kk, gr);
+  mf_stage<N>(stage[w][1], nn, kk, gs);
+  __syncthreads();
+  const int ne = a.K - e0 < 16 ? a.K - e0 : 16;
+  const size_t g0 = (size_t)e0 * Np;
+  for (int idx = lane; idx < ne * Np; idx += 64) {
+    a.out_x[g0 + idx] = stage[w][0][idx];
+    a.out_y[g0 + idx] = stage[w][1][idx];
+    if (a.p_out) a.p_out[g0 + idx] = p[g0 + idx] + a.add_p[g0 + idx];
+  }
+}
+
+template <int N, bool MASS>
+__global__ __launch_bounds__(64 * kGdWaves) void k_div_mf(DivArgs a, const double* __restrict__ tab) {
+  using T = Tri<N>;
+  constexpr GdDims D = gd_dims(N);
+  constexpr int Np = D.Np, Nfp = D.Nfp;
+  __shared__ double stage[kGdWaves][16 * Np];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int nn = lane & 15, kk = lane >> 4;
+  const int e0 = (blockIdx.x * kGdWaves + w) * 16;
+  const int ec = e0 + nn < a.K ? e0 + nn : a.K - 1;
   const double* __restrict__ u = a.u;
   const double* __restrict__ v = a.v;
-  double ue[Np], ve[Np];
-  load_rows<N>(u, buf, e0, n, ue);
-  load_rows<N>(v, buf, e0, n, ve);
-  const int t = threadIdx.x, e = e0 + t;
-  if (t < n) {
-    const double rx = a.geo[4 * (size_t)e], sx = a.geo[4 * (size_t)e + 1];
-    const double ry = a.geo[4 * (size_t)e + 2], sy = a.geo[4 * (size_t)e + 3];
-    // face terms n . (u* - u-) per face node
-    double fl[3][Nfp];
-    const Conn c = a.conn[e];
+  const double rx = a.geo[4 * (size_t)ec], sx = a.geo[4 * (size_t)ec + 1];
+  const double ry = a.geo[4 * (size_t)ec + 2], sy = a.geo[4 * (size_t)ec + 3];
+  v4d ur[D.RB], us[D.RB], vr[D.RB], vs[D.RB], fl[D.RB];
 #pragma unroll
-    for (int f = 0; f < 3; ++f) {
-      const int bc = conn_bc(c.info, f);
-      const int fp = conn_fp(c.info, f), nb = c.nb[f];
-      double ax, ay;
-      face_vec(f, rx, sx, ry, sy, ax, ay);
+  for (int R = 0; R < D.RB; ++R) ur[R] = us[R] = vr[R] = vs[R] = fl[R] = v4d{0.0, 0.0, 0.0, 0.0};
+  {
+    double ub[D.KB], vb[D.KB];
 #pragma unroll
-      for (int k = 0; k < Nfp; ++k) {
-        const int m = T::fm(f, k);
-        const double um = ue[m], vm = ve[m];
-        double ju = 0.0, jv = 0.0;   // Neumann: u* = u-
-        if (bc == 0) {
-          const size_t ip = (size_t)nb * Np + T::fm(fp, N - k);
-          ju = 0.5 * (u[ip] - um);
-          jv = 0.5 * (v[ip] - vm);
-        } else if (bc == 1) {
-          const size_t im = (size_t)e * Np + m;
-          ju = (a.gu ? a.gu[im] : 0.0) - um;
-          jv = (a.gv ? a.gv[im] : 0.0) - vm;
-        }
-        fl[f][k] = ax * ju + ay * jv;
-      }
+    for (int kb = 0; kb < D.KB; ++kb) {
+      const size_t i = (size_t)ec * Np + (4 * kb + kk < Np ? 4 * kb + kk : Np - 1);
+      ub[kb] = u[i];
+      vb[kb] = v[i];
     }
-    double d[Np];
-    for (int i = 0; i < Np; ++i) {
-      double ur = 0.0, us = 0.0, vr = 0.0, vs = 0.0;
 #pragma unroll
-      for (int j = 0; j < Np; ++j) {
-        const double dr = ops[L::Dr + i * Np + j], ds = ops[L::Ds + i * Np + j];
-        ur += dr * ue[j];
-        us += ds * ue[j];
-        vr += dr * ve[j];
-        vs += ds * ve[j];
+    for (int kb = 0; kb < D.KB; ++kb)
+#pragma unroll
+      for (int R = 0; R < D.RB; ++R) {
+        const double Ar = tab[D.oDr + (R * D.KB + kb) * 64 + lane], As = tab[D.oDs + (R * D.KB + kb) * 64 + lane];
+        ur[R] = mma(Ar, ub[kb], ur[R]);
+        us[R] = mma(As, ub[kb], us[R]);
+        vr[R] = mma(Ar, vb[kb], vr[R]);
+        vs[R] = mma(As, vb[kb], vs[R]);
       }
-      double di = (rx * ur + sx * us) + (ry * vr + sy * vs);
-#pragma unroll
-      for (int f = 0; f < 3; ++f) {
-        double s = 0.0;
-#pragma unroll
-        for (int k = 0; k < Nfp; ++k) s += ops[L::LIFT + i * 3 * Nfp + f * Nfp + k] * fl[f][k];
-        di += s;
-      }
-      d[i] = di;
-    }
-    if constexpr (MASS) mass_rows<N>(ops, 1.0 / (rx * sy - ry * sx), d);
-#pragma unroll
-    for (int i = 0; i < Np; ++i) buf[t * P + i] = a.scale * d[i];
   }
-  store_rows<N>(buf, a.out, e0, n);
+  // face terms: LIFT_f ((|F|/|E|) n . (u* - u-)) at the face nodes
+  const Conn c = a.conn[ec];
+#pragma unroll
+  for (int f = 0; f < 3; ++f) {
+    const int bc = conn_bc(c.info, f), fp = conn_fp(c.info, f), nb = c.nb[f];
+    double ax, ay;
+    face_vec(f, rx, sx, ry, sy, ax, ay);
+#pragma unroll
+    for (int kb = 0; kb < D.KF; ++kb) {
+      const int k = 4 * kb + kk < Nfp ? 4 * kb + kk : Nfp - 1;
+      const size_t im = (size_t)ec * Np + T::fm(f, k);
+      const double um = u[im], vm = v[im];
+      double ju = 0.0, jv = 0.0;   // Neumann: u* = u-
+      if (bc == 0) {
+        const size_t ip = (size_t)nb * Np + T::fm(fp, N - k);
+        ju = 0.5 * (u[ip] - um);
+        jv = 0.5 * (v[ip] - vm);
+      } else if (bc == 1) {
+        ju = (a.gu ? a.gu[im] : 0.0) - um;
+        jv = (a.gv ? a.gv[im] : 0.0) - vm;
+      }
+      const double b = ax * ju + ay * jv;
+#pragma unroll
+      for (int R = 0; R < D.RB; ++R) fl[R] = mma(tab[D.oL + ((f * D.RB + R) * D.KF + kb) * 64 + lane], b, fl[R]);
+    }
+  }
+#pragma unroll
+  for (int R = 0; R < D.RB; ++R)
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+      ur[R][r] = (rx * ur[R][r] + sx * us[R][r]) + (ry * vr[R][r] + sy * vs[R][r]) + fl[R][r];
+  if constexpr (MASS) mf_mass<N>(tab, lane, 1.0 / (rx * sy - ry * sx), ur);
+  mf_stage<N>(stage[w], nn, kk, ur);
+  __syncthreads();
+  const int ne = a.K - e0 < 16 ? a.K - e0 : 16;
+  const size_t g0 = (size_t)e0 * Np;
+  for (int idx = lane; idx < ne * Np; idx += 64) a.out[g0 + idx] = a.scale * stage[w][idx];
 }
 
 // One element per lane; only elements with Dirichlet faces add anything.
@@ -475,16 +614,39 @@ hipError_t remove_mean(int N, double* b, double area, const double* geo, const d
   return hipGetLastError();
 }
 
+namespace {
+
+template <int N>
+void launch_grad_mf(const GradArgs& a, hipStream_t s) {
+  const dim3 grid((a.K + 16 * kGdWaves - 1) / (16 * kGdWaves)), block(64 * kGdWaves);
+  if (a.mass) hipLaunchKernelGGL((k_grad_mf<N, true>), grid, block, 0, s, a, device_gd_tab(N));
+  else hipLaunchKernelGGL((k_grad_mf<N, false>), grid, block, 0, s, a, device_gd_tab(N));
+}
+
+template <int N>
+void launch_div_mf(const DivArgs& a, hipStream_t s) {
+  const dim3 grid((a.K + 16 * kGdWaves - 1) / (16 * kGdWaves)), block(64 * kGdWaves);
+  if (a.mass) hipLaunchKernelGGL((k_div_mf<N, true>), grid, block, 0, s, a, device_gd_tab(N));
+  else hipLaunchKernelGGL((k_div_mf<N, false>), grid, block, 0, s, a, device_gd_tab(N));
+}
+
+}  // namespace
+
 hipError_t grad_apply(int N, const GradArgs& a, hipStream_t s) {
   if (a.K == 0) return hipSuccess;
   switch (N) {
-#define IPDG_G(n) \
-  case n:                                                                                    \
-    if (a.mass) hipLaunchKernelGGL((k_grad<n, true>), dim3(blocks<n>(a.K)), dim3(kElems<n>()), 0, s, a);  \
-    else hipLaunchKernelGGL((k_grad<n, false>), dim3(blocks<n>(a.K)), dim3(kElems<n>()), 0, s, a);       \
-    break;
-    IPDG_G(1) IPDG_G(2) IPDG_G(3) IPDG_G(4) IPDG_G(5) IPDG_G(6) IPDG_G(7) IPDG_G(8)
-#undef IPDG_G
+    // one element per lane is faster only at degree 1
+    case 1:
+      if (a.mass) hipLaunchKernelGGL((k_grad<1, true>), dim3(blocks<1>(a.K)), dim3(kElems<1>()), 0, s, a);
+      else hipLaunchKernelGGL((k_grad<1, false>), dim3(blocks<1>(a.K)), dim3(kElems<1>()), 0, s, a);
+      break;
+    case 2: launch_grad_mf<2>(a, s); break;
+    case 3: launch_grad_mf<3>(a, s); break;
+    case 4: launch_grad_mf<4>(a, s); break;
+    case 5: launch_grad_mf<5>(a, s); break;
+    case 6: launch_grad_mf<6>(a, s); break;
+    case 7: launch_grad_mf<7>(a, s); break;
+    case 8: launch_grad_mf<8>(a, s); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -493,13 +655,14 @@ hipError_t grad_apply(int N, const GradArgs& a, hipStream_t s) {
 hipError_t div_apply(int N, const DivArgs& a, hipStream_t s) {
   if (a.K == 0) return hipSuccess;
   switch (N) {
-#define IPDG_D(n) \
-  case n:                                                                                    \
-    if (a.mass) hipLaunchKernelGGL((k_div<n, true>), dim3(blocks<n>(a.K)), dim3(kElems<n>()), 0, s, a);   \
-    else hipLaunchKernelGGL((k_div<n, false>), dim3(blocks<n>(a.K)), dim3(kElems<n>()), 0, s, a);        \
-    break;
-    IPDG_D(1) IPDG_D(2) IPDG_D(3) IPDG_D(4) IPDG_D(5) IPDG_D(6) IPDG_D(7) IPDG_D(8)
-#undef IPDG_D
+    case 1: launch_div_mf<1>(a, s); break;
+    case 2: launch_div_mf<2>(a, s); break;
+    case 3: launch_div_mf<3>(a, s); break;
+    case 4: launch_div_mf<4>(a, s); break;
+    case 5: launch_div_mf<5>(a, s); break;
+    case 6: launch_div_mf<6>(a, s); break;
+    case 7: launch_div_mf<7>(a, s); break;
+    case 8: launch_div_mf<8>(a, s); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

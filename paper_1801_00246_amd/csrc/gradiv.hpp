@@ -81,6 +81,34 @@ hipError_t axpby(double a, const double* x, double b, const double* y, double* z
 hipError_t remove_mean(int N, double* b, double area, const double* geo, const double* ops, int K, double* work,
                        hipStream_t s);
 
+// Matrix-core form of the gradient (degrees 2-8) and the divergence: 16 elements
+// per wave as the columns of v_mfma_f64_16x16x4f64 blocks, the operators as A
+// operands in lane order (64 values per block; entries outside the operators
+// zero):
+//   Dr, Ds [RB][KB]      lane l: D[16 R + l%16][4 kb + l/16]          (Np x Np)
+//   L      [3][RB][KF]   lane l: LIFT[16 R + l%16][f Nfp + 4 kb + l/16] (face f's columns)
+//   M      [RB][RB][4]   lane l: M[16 R + l%16][16 R2 + 4 t + l/16]
+struct GdDims {
+  int Np, Nfp, RB, KB, KF;
+  int oDr, oDs, oL, oM, total;
+};
+__host__ __device__ constexpr GdDims gd_dims(int N) {
+  GdDims d{};
+  d.Np = (N + 1) * (N + 2) / 2;
+  d.Nfp = N + 1;
+  d.RB = (d.Np + 15) / 16;
+  d.KB = (d.Np + 3) / 4;
+  d.KF = (d.Nfp + 3) / 4;
+  d.oDr = 0;
+  d.oDs = d.oDr + 64 * d.RB * d.KB;
+  d.oL = d.oDs + 64 * d.RB * d.KB;
+  d.oM = d.oL + 64 * 3 * d.RB * d.KF;
+  d.total = d.oM + 64 * d.RB * d.RB * 4;
+  return d;
+}
+// Device copy of that table for degree N (cached per device; gradiv_host.cpp).
+const double* device_gd_tab(int N);
+
 // out = a_base base + a_grad G p (or J M of it), p_out = p + add_p
 hipError_t grad_apply(int N, const GradArgs& a, hipStream_t s);
 // out = scale D (u, v) (or scale J M D (u, v))
