@@ -312,11 +312,12 @@ def run_pcg_compare(P, torch, coarse_caps=(150, 300)):
 
 
 def run_gradiv(P, torch, msh, orders=(3, 7), steps=50, rotate_bytes=1.2e9):
-    """DG gradient and divergence (central fluxes) on the 524,288-triangle
-    mesh, FP64: microseconds per launch (HIP events over `steps` launches
-    rotating over independent data sets) and algorithmic bandwidth, each
-    launch reading one (G) or two (D) nodal fields, writing two (G) or one
-    (D), plus the metric (32 B) and connectivity (16 B) per element."""
+    """DG gradient and divergence (central fluxes) and the nodal advection
+    term on the 524,288-triangle mesh, FP64: microseconds per launch (HIP
+    events over `steps` launches rotating over independent data sets) and
+    algorithmic bandwidth, each launch reading one (G) or two (D, advection)
+    nodal fields, writing two (G, advection) or one (D), plus the metric
+    (32 B) and connectivity (16 B) per element."""
     import ctypes as C
     import synth
     out = {}
@@ -341,8 +342,12 @@ def run_gradiv(P, torch, msh, orders=(3, 7), steps=50, rotate_bytes=1.2e9):
             (a, b), o = ins[i % R], outs[i % R][0]
             return lib.ipdg_div(g.handle, ptr(a), ptr(b), None, None, ptr(o), st)
 
+        def advect(i):
+            (a, b), (o1, o2) = ins[i % R], outs[i % R]
+            return lib.ipdg_advect(g.handle, ptr(a), ptr(b), None, None, ptr(o1), ptr(o2), st)
+
         res = {}
-        for name, fn in (("grad", grad), ("div", div)):
+        for name, fn in (("grad", grad), ("div", div), ("advect", advect)):
             for i in range(R + 5):
                 assert fn(i) == 0
             torch.cuda.synchronize()
@@ -353,7 +358,8 @@ def run_gradiv(P, torch, msh, orders=(3, 7), steps=50, rotate_bytes=1.2e9):
             e1.record()
             torch.cuda.synchronize()
             us = e0.elapsed_time(e1) * 1e3 / steps
-            gbs = nbytes / (us * 1e-6) / 1e9
+            nb = nbytes if name != "advect" else K * (4 * Np * 8 + 48)
+            gbs = nb / (us * 1e-6) / 1e9
             res[name] = {"us": round(us, 2), "GB/s": round(gbs, 1), "frac_hbm": round(gbs / 8000.0, 4)}
         out[f"N{N}"] = res
         print(f"# gradiv N={N}: {res}", file=sys.stderr, flush=True)

@@ -287,6 +287,17 @@ ipdg_status ipdg_subcycle(ipdg_mesh mesh, const double* ubar0, const double* vba
  * (gx, gy) = G p. */
 ipdg_status ipdg_grad(ipdg_mesh mesh, const double* p, double* gx, double* gy, void* hip_stream);
 
+/* Nodal Lax-Friedrichs advection term of the splitting scheme's explicit
+ * stage (Sec. 2.1, Eq. INS_SD_2 / INS_SD_3), per velocity component c:
+ *   N_c = div(u_c u) + LIFT (|F|/|E|) (n . F_c* - n . F_c(u-)),
+ *   n . F_c* = {n . F_c} + (Lambda / 2) (u_c- - u_c+),
+ *   Lambda = 2 max(|n . u-|, |n . u+|),
+ * the flux products taken at the nodes.  Dirichlet faces take u+ = g (gu, gv
+ * nodal fields, face nodes read; NULL = 0), Neumann faces u+ = u-.
+ * (nu, nv) = N(u, v). */
+ipdg_status ipdg_advect(ipdg_mesh mesh, const double* u, const double* v, const double* gu, const double* gv,
+                        double* nu, double* nv, void* hip_stream);
+
 /* DG divergence with the central flux u* = {u} (Eq. INS_SD_4_2):
  * out = D (u, v).  gu, gv: Dirichlet data g_D as nodal fields (only their
  * values on Dirichlet face nodes are read), or NULL for g_D = 0. */

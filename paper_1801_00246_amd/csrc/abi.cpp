@@ -444,6 +444,29 @@ ipdg_status ipdg_div(ipdg_mesh mesh, const double* u, const double* v, const dou
   });
 }
 
+ipdg_status ipdg_advect(ipdg_mesh mesh, const double* u, const double* v, const double* gu, const double* gv,
+                        double* nu, double* nv, void* hip_stream) {
+  return guarded([&]() -> ipdg_status {
+    if (!mesh) return fail(IPDG_EINVAL, "mesh is null");
+    if (mesh->host.K == 0) return IPDG_OK;
+    if (!u || !v || !nu || !nv) return fail(IPDG_EINVAL, "null vector");
+    DeviceGuard dg(mesh);
+    ipdg::AdvectArgs a;
+    a.u = u;
+    a.v = v;
+    a.gu = gu;
+    a.gv = gv;
+    a.out_u = nu;
+    a.out_v = nv;
+    a.geo = mesh->geo64.as<double>();
+    a.conn = mesh->conn.as<ipdg::Conn>();
+    a.ops = static_cast<const double*>(ipdg::device_ops(mesh->host.N, ipdg::Kind::F64));
+    a.K = mesh->host.K;
+    IPDG_HIP(ipdg::advect_apply(mesh->host.N, a, static_cast<hipStream_t>(hip_stream)));
+    return IPDG_OK;
+  });
+}
+
 ipdg_status ipdg_dirichlet_rhs(ipdg_mesh mesh, double tau, const double* g, double* b, void* hip_stream) {
   return guarded([&]() -> ipdg_status {
     if (!mesh) return fail(IPDG_EINVAL, "mesh is null");

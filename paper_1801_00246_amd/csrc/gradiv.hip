@@ -4,9 +4,9 @@
 //   D u = div u  + LIFT (|F|/|E|) n . (u* - u-),
 // p* = {p}, u* = {u} on interior faces; on Dirichlet (velocity) faces
 // u* = g_D and p* = p-, on Neumann faces u* = u- and p* = 0.  The divergence,
-// and the gradient from degree 2, run on the matrix cores, 16 elements per
-// wave (the form below `Matrix-core form`); the gradient at degree 1, the
-// advection term and the Dirichlet-data terms run one element per lane, the
+// and the gradient and the advection term from degree 2, run on the matrix
+// cores, 16 elements per wave (the form below `Matrix-core form`); at degree
+// 1 those two and the Dirichlet-data terms run one element per lane, the
 // reference operators read from the degree's FP64 table through wave-uniform
 // loads.  Normals and face scales |F|/|E| come from the element's metric
 // terms (face 0: -grad s, face 1: grad r + grad s, face 2: -grad r; each
@@ -161,7 +161,7 @@ __global__ __launch_bounds__(kElems<N>()) void k_grad(GradArgs a) {
 
 // ---------------------------------------------------------------------------
 // Matrix-core form (layout GdDims in gradiv.hpp; the divergence at every
-// degree, the gradient from degree 2).  A wave
+// degree, the gradient and the advection term from degree 2).  A wave
 // computes 16 elements as the columns of 16 x 16 blocks of
 // v_mfma_f64_16x16x4f64: D_r and D_s times the elements' nodal values (B
 // operands in registers), the face terms as LIFT_f times the face-node fluxes
@@ -365,6 +365,93 @@ __global__ __launch_bounds__(64 * kGdWaves) void k_div_mf(DivArgs a, const doubl
   const int ne = a.K - e0 < 16 ? a.K - e0 : 16;
   const size_t g0 = (size_t)e0 * Np;
   for (int idx = lane; idx < ne * Np; idx += 64) a.out[g0 + idx] = a.scale * stage[w][idx];
+}
+
+// Nodal Lax-Friedrichs advection term on the matrix cores (same shape as
+// k_div_mf): the metric terms are folded into the nodal products first,
+//   N_u = D_r (r_x uu + r_y uv) + D_s (s_x uu + s_y uv) + sum_f LIFT_f (|F|/|E|) flux_u,
+// and likewise for N_v with (uv, vv); out = a_base base + a_adv N.
+template <int N>
+__global__ __launch_bounds__(64 * kGdWaves) void k_advect_mf(AdvectArgs a, const double* __restrict__ tab) {
+  using T = Tri<N>;
+  constexpr GdDims D = gd_dims(N);
+  constexpr int Np = D.Np, Nfp = D.Nfp;
+  __shared__ double stage[kGdWaves][2][16 * Np];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int nn = lane & 15, kk = lane >> 4;
+  const int e0 = (blockIdx.x * kGdWaves + w) * 16;
+  const int ec = e0 + nn < a.K ? e0 + nn : a.K - 1;   // lanes past the end read a valid element
+  const double* __restrict__ u = a.u;
+  const double* __restrict__ v = a.v;
+  const double rx = a.geo[4 * (size_t)ec], sx = a.geo[4 * (size_t)ec + 1];
+  const double ry = a.geo[4 * (size_t)ec + 2], sy = a.geo[4 * (size_t)ec + 3];
+  v4d nu[D.RB], nv[D.RB];
+#pragma unroll
+  for (int R = 0; R < D.RB; ++R) nu[R] = nv[R] = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int kb = 0; kb < D.KB; ++kb) {
+    const size_t i = (size_t)ec * Np + (4 * kb + kk < Np ? 4 * kb + kk : Np - 1);
+    const double uj = u[i], vj = v[i];
+    const double uu = uj * uj, uv = uj * vj, vv = vj * vj;
+    const double bru = rx * uu + ry * uv, bsu = sx * uu + sy * uv;
+    const double brv = rx * uv + ry * vv, bsv = sx * uv + sy * vv;
+#pragma unroll
+    for (int R = 0; R < D.RB; ++R) {
+      const double Ar = tab[D.oDr + (R * D.KB + kb) * 64 + lane], As = tab[D.oDs + (R * D.KB + kb) * 64 + lane];
+      nu[R] = mma(Ar, bru, nu[R]);
+      nu[R] = mma(As, bsu, nu[R]);
+      nv[R] = mma(Ar, brv, nv[R]);
+      nv[R] = mma(As, bsv, nv[R]);
+    }
+  }
+  const Conn c = a.conn[ec];
+#pragma unroll
+  for (int f = 0; f < 3; ++f) {
+    const int bc = conn_bc(c.info, f), fp = conn_fp(c.info, f), nb = c.nb[f];
+    double ax, ay;
+    face_vec(f, rx, sx, ry, sy, ax, ay);
+    const double fs = sqrt(ax * ax + ay * ay);
+    const double nx = ax / fs, ny = ay / fs;
+#pragma unroll
+    for (int kb = 0; kb < D.KF; ++kb) {
+      const int k = 4 * kb + kk < Nfp ? 4 * kb + kk : Nfp - 1;
+      const size_t im = (size_t)ec * Np + T::fm(f, k);
+      const double um = u[im], vm = v[im];
+      double up = um, vp = vm;                       // Neumann: u+ = u-
+      if (bc == 0) {
+        const size_t ip = (size_t)nb * Np + T::fm(fp, N - k);
+        up = u[ip];
+        vp = v[ip];
+      } else if (bc == 1) {
+        up = a.gu ? a.gu[im] : 0.0;
+        vp = a.gv ? a.gv[im] : 0.0;
+      }
+      const double unm = nx * um + ny * vm, unp = nx * up + ny * vp;
+      const double lam = 2.0 * fmax(fabs(unm), fabs(unp));
+      const double fu = fs * (0.5 * (um * unm + up * unp) + 0.5 * lam * (um - up) - um * unm);
+      const double fv = fs * (0.5 * (vm * unm + vp * unp) + 0.5 * lam * (vm - vp) - vm * unm);
+#pragma unroll
+      for (int R = 0; R < D.RB; ++R) {
+        const double L = tab[D.oL + ((f * D.RB + R) * D.KF + kb) * 64 + lane];
+        nu[R] = mma(L, fu, nu[R]);
+        nv[R] = mma(L, fv, nv[R]);
+      }
+    }
+  }
+  mf_stage<N>(stage[w][0], nn, kk, nu);
+  mf_stage<N>(stage[w][1], nn, kk, nv);
+  __syncthreads();
+  const int ne = a.K - e0 < 16 ? a.K - e0 : 16;
+  const size_t g0 = (size_t)e0 * Np;
+  for (int idx = lane; idx < ne * Np; idx += 64) {
+    double ou = a.a_adv * stage[w][0][idx], ov = a.a_adv * stage[w][1][idx];
+    if (a.base_u) {
+      ou += a.a_base * a.base_u[g0 + idx];
+      ov += a.a_base * a.base_v[g0 + idx];
+    }
+    a.out_u[g0 + idx] = ou;
+    a.out_v[g0 + idx] = ov;
+  }
 }
 
 // One element per lane; only elements with Dirichlet faces add anything.
@@ -580,10 +667,13 @@ hipError_t dirichlet_rhs(int N, const DirichletArgs& a, hipStream_t s) {
 
 hipError_t advect_apply(int N, const AdvectArgs& a, hipStream_t s) {
   if (a.K == 0) return hipSuccess;
+  const dim3 grid((a.K + 16 * kGdWaves - 1) / (16 * kGdWaves)), block(64 * kGdWaves);
   switch (N) {
+    // one element per lane is faster only at degree 1
+    case 1: hipLaunchKernelGGL(k_advect<1>, dim3(blocks<1>(a.K)), dim3(kElems<1>()), 0, s, a); break;
 #define IPDG_A(n) \
-  case n: hipLaunchKernelGGL(k_advect<n>, dim3(blocks<n>(a.K)), dim3(kElems<n>()), 0, s, a); break;
-    IPDG_A(1) IPDG_A(2) IPDG_A(3) IPDG_A(4) IPDG_A(5) IPDG_A(6) IPDG_A(7) IPDG_A(8)
+  case n: hipLaunchKernelGGL(k_advect_mf<n>, grid, block, 0, s, a, device_gd_tab(n)); break;
+    IPDG_A(2) IPDG_A(3) IPDG_A(4) IPDG_A(5) IPDG_A(6) IPDG_A(7) IPDG_A(8)
 #undef IPDG_A
     default: return hipErrorInvalidValue;
   }

@@ -81,7 +81,8 @@ hipError_t axpby(double a, const double* x, double b, const double* y, double* z
 hipError_t remove_mean(int N, double* b, double area, const double* geo, const double* ops, int K, double* work,
                        hipStream_t s);
 
-// Matrix-core form of the gradient (degrees 2-8) and the divergence: 16 elements
+// Matrix-core form of the gradient and the advection term (degrees 2-8) and
+// the divergence: 16 elements
 // per wave as the columns of v_mfma_f64_16x16x4f64 blocks, the operators as A
 // operands in lane order (64 values per block; entries outside the operators
 // zero):

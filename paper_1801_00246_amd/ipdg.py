@@ -85,6 +85,7 @@ _SIGS = {
     "ipdg_ins_step_subcycled": (C.c_int, [_P, _P, C.c_double, C.c_double, C.c_double, C.c_int] + [_P] * 11
                                 + [C.c_double, _P, _P, _P, _P]),
     "ipdg_div": (C.c_int, [_P, _P, _P, _P, _P, _P, _P]),
+    "ipdg_advect": (C.c_int, [_P] * 8),
     "ipdg_subcycle_rhs": (C.c_int, [_P] * 7 + [C.c_int, _P, _P, _P]),
     "ipdg_subcycle": (C.c_int, [_P] * 9 + [C.c_double, C.c_int, _P, _P, _P]),
     "ipdg_ins_velocity_rhs": (C.c_int, [_P, C.c_double, C.c_double, _P, _P, _P, _P, _P, _P]),
@@ -379,6 +380,14 @@ class Mesh:
         check(lib().ipdg_div(self._h, self._vec(u, "u"), self._vec(v, "v"), self._opt(gu, "gu"),
                              self._opt(gv, "gv"), self._vec(out, "out"), _stream(stream)))
         return out
+
+    def advect(self, u, v, gu=None, gv=None, stream=None):
+        """N(u, v): the nodal Lax-Friedrichs advection term (Eq. INS_SD_2/3)."""
+        import torch
+        nu, nv = torch.empty_like(u), torch.empty_like(v)
+        check(lib().ipdg_advect(self._h, self._vec(u, "u"), self._vec(v, "v"), self._opt(gu, "gu"),
+                                self._opt(gv, "gv"), self._vec(nu, "nu"), self._vec(nv, "nv"), _stream(stream)))
+        return nu, nv
 
     def dirichlet_rhs(self, g, b, tau=0.0, stream=None):
         """b += the Dirichlet-data terms of the nodal field g (in place)."""

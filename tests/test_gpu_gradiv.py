@@ -116,3 +116,23 @@ def test_projection_step_on_the_gpu(N):
     assert eu < 2e-2 and ep < 2e-2
     g.close()
     gp.close()
+
+
+@pytest.mark.parametrize("bc", ["dirichlet", "neumann", "mixed"])
+@pytest.mark.parametrize("N", [1, 2, 3, 4, 5, 6, 7, 8])
+def test_advection_matches_oracle(N, bc):
+    from oracle.gradiv import advection
+    msh = synth.permuted(synth.square_mesh(4 if N >= 6 else 6, jitter=0.2, seed=40 + N, bc=bc), seed=41 + N)
+    m = OracleMesh(msh.VX, msh.VY, msh.EToV, msh.EToB, N)
+    rng = np.random.default_rng(40 + N)
+    n = m.K * m.Np
+    u, v, gu, gv = (rng.standard_normal(n) for _ in range(4))
+    g = P.Mesh.from_synth(N, msh)
+    nu, nv = g.advect(dev(u), dev(v), dev(gu), dev(gv))
+    ou, ov = advection(m, u, v, gu, gv)
+    nu0, nv0 = g.advect(dev(u), dev(v))
+    ou0, ov0 = advection(m, u, v)
+    e = (rel(host(nu), ou), rel(host(nv), ov), rel(host(nu0), ou0), rel(host(nv0), ov0))
+    print(f"N={N} {bc}: advection rel errors {e[0]:.1e} {e[1]:.1e}; zero data {e[2]:.1e} {e[3]:.1e}")
+    assert max(e) <= 1e-12
+    g.close()
