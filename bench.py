@@ -41,7 +41,7 @@ FP32_PEAK_TFS = 157.3          # vector FP32, published
 # counter's reading for a device-to-device copy of known size.  Valid only for
 # the kernel sources it was measured on (their SHA-256), else reported null.
 MEASURED_TRAFFIC = {"N": 3, "dtype": "f64", "lambda": 100.0, "variant": 4, "bytes": 111073404,
-                    "sources_sha256": "41c847603c88bd1a9827c1894c2d2ad4202eb5fdb139a79864e7e9c8969219be",
+                    "sources_sha256": "901241b4655e18fb6030ea9cbdadb70cd6fa3aafea58299de02bbb73355439c2",
                     "profile": "profiles/k_axc_N3_f64_524288.md"}
 
 KERNEL_SOURCES = ("elem_inst.hip", "sipdg_core.hpp", "sipdg_coop.hpp", "tri.hpp", "device_common.hpp",
