@@ -210,15 +210,17 @@ __device__ __forceinline__ void mf_stage(double* st, int nn, int kk, const v4d (
     }
 }
 
+// One wave's tile of 16 elements from e0 (tab: the operator table in global
+// memory or LDS; st0, st1: the wave's two LDS staging rows of 16 Np values).
+// Contains a block barrier: every wave of the block calls it equally often.
 template <int N, bool MASS>
-__global__ __launch_bounds__(64 * kGdWaves) void k_grad_mf(GradArgs a, const double* __restrict__ tab) {
+__device__ __forceinline__ void grad_tile(const GradArgs& a, const double* __restrict__ tab, int e0, double* st0,
+                                          double* st1) {
   using T = Tri<N>;
   constexpr GdDims D = gd_dims(N);
   constexpr int Np = D.Np, Nfp = D.Nfp;
-  __shared__ double stage[kGdWaves][2][16 * Np];
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
   const int nn = lane & 15, kk = lane >> 4;
-  const int e0 = (blockIdx.x * kGdWaves + w) * 16;
   const int ec = e0 + nn < a.K ? e0 + nn : a.K - 1;   // lanes past the end read a valid element
   const double* __restrict__ p = a.p;
   const double rx = a.geo[4 * (size_t)ec], sx = a.geo[4 * (size_t)ec + 1];
@@ -280,27 +282,26 @@ __global__ __launch_bounds__(64 * kGdWaves) void k_grad_mf(GradArgs a, const dou
     mf_mass<N>(tab, lane, J, gr);
     mf_mass<N>(tab, lane, J, gs);
   }
-  mf_stage<N>(stage[w][0], nn, kk, gr);
-  mf_stage<N>(stage[w][1], nn, kk, gs);
+  mf_stage<N>(st0, nn, kk, gr);
+  mf_stage<N>(st1, nn, kk, gs);
   __syncthreads();
   const int ne = a.K - e0 < 16 ? a.K - e0 : 16;
   const size_t g0 = (size_t)e0 * Np;
   for (int idx = lane; idx < ne * Np; idx += 64) {
-    a.out_x[g0 + idx] = stage[w][0][idx];
-    a.out_y[g0 + idx] = stage[w][1][idx];
+    a.out_x[g0 + idx] = st0[idx];
+    a.out_y[g0 + idx] = st1[idx];
     if (a.p_out) a.p_out[g0 + idx] = p[g0 + idx] + a.add_p[g0 + idx];
   }
 }
 
 template <int N, bool MASS>
-__global__ __launch_bounds__(64 * kGdWaves) void k_div_mf(DivArgs a, const double* __restrict__ tab) {
+__device__ __forceinline__ void div_tile(const DivArgs& a, const double* __restrict__ tab, int e0, double* st0,
+                                         double*) {
   using T = Tri<N>;
   constexpr GdDims D = gd_dims(N);
   constexpr int Np = D.Np, Nfp = D.Nfp;
-  __shared__ double stage[kGdWaves][16 * Np];
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
   const int nn = lane & 15, kk = lane >> 4;
-  const int e0 = (blockIdx.x * kGdWaves + w) * 16;
   const int ec = e0 + nn < a.K ? e0 + nn : a.K - 1;
   const double* __restrict__ u = a.u;
   const double* __restrict__ v = a.v;
@@ -360,26 +361,25 @@ __global__ __launch_bounds__(64 * kGdWaves) void k_div_mf(DivArgs a, const doubl
     for (int r = 0; r < 4; ++r)
       ur[R][r] = (rx * ur[R][r] + sx * us[R][r]) + (ry * vr[R][r] + sy * vs[R][r]) + fl[R][r];
   if constexpr (MASS) mf_mass<N>(tab, lane, 1.0 / (rx * sy - ry * sx), ur);
-  mf_stage<N>(stage[w], nn, kk, ur);
+  mf_stage<N>(st0, nn, kk, ur);
   __syncthreads();
   const int ne = a.K - e0 < 16 ? a.K - e0 : 16;
   const size_t g0 = (size_t)e0 * Np;
-  for (int idx = lane; idx < ne * Np; idx += 64) a.out[g0 + idx] = a.scale * stage[w][idx];
+  for (int idx = lane; idx < ne * Np; idx += 64) a.out[g0 + idx] = a.scale * st0[idx];
 }
 
 // Nodal Lax-Friedrichs advection term on the matrix cores (same shape as
 // k_div_mf): the metric terms are folded into the nodal products first,
 //   N_u = D_r (r_x uu + r_y uv) + D_s (s_x uu + s_y uv) + sum_f LIFT_f (|F|/|E|) flux_u,
 // and likewise for N_v with (uv, vv); out = a_base base + a_adv N.
-template <int N>
-__global__ __launch_bounds__(64 * kGdWaves) void k_advect_mf(AdvectArgs a, const double* __restrict__ tab) {
+template <int N, bool MASS_UNUSED>
+__device__ __forceinline__ void advect_tile(const AdvectArgs& a, const double* __restrict__ tab, int e0, double* st0,
+                                            double* st1) {
   using T = Tri<N>;
   constexpr GdDims D = gd_dims(N);
   constexpr int Np = D.Np, Nfp = D.Nfp;
-  __shared__ double stage[kGdWaves][2][16 * Np];
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
   const int nn = lane & 15, kk = lane >> 4;
-  const int e0 = (blockIdx.x * kGdWaves + w) * 16;
   const int ec = e0 + nn < a.K ? e0 + nn : a.K - 1;   // lanes past the end read a valid element
   const double* __restrict__ u = a.u;
   const double* __restrict__ v = a.v;
@@ -438,13 +438,13 @@ __global__ __launch_bounds__(64 * kGdWaves) void k_advect_mf(AdvectArgs a, const
       }
     }
   }
-  mf_stage<N>(stage[w][0], nn, kk, nu);
-  mf_stage<N>(stage[w][1], nn, kk, nv);
+  mf_stage<N>(st0, nn, kk, nu);
+  mf_stage<N>(st1, nn, kk, nv);
   __syncthreads();
   const int ne = a.K - e0 < 16 ? a.K - e0 : 16;
   const size_t g0 = (size_t)e0 * Np;
   for (int idx = lane; idx < ne * Np; idx += 64) {
-    double ou = a.a_adv * stage[w][0][idx], ov = a.a_adv * stage[w][1][idx];
+    double ou = a.a_adv * st0[idx], ov = a.a_adv * st1[idx];
     if (a.base_u) {
       ou += a.a_base * a.base_u[g0 + idx];
       ov += a.a_base * a.base_v[g0 + idx];
@@ -453,6 +453,45 @@ __global__ __launch_bounds__(64 * kGdWaves) void k_advect_mf(AdvectArgs a, const
     a.out_v[g0 + idx] = ov;
   }
 }
+
+// The two launch forms of a tile function: one tile per wave with the table
+// read from global memory, or persistent blocks of gd_pwaves waves that keep
+// the table in LDS and walk over the tiles (all waves of a block take the
+// same number of steps, so the tile's barrier is reached by all).
+// waves per persistent block with ROWS staging rows per wave: 8 if the table
+// and eight waves' rows fit the 160 KiB of LDS, else 4
+template <int N, int ROWS>
+constexpr int gd_pwaves() {
+  return (gd_dims(N).total + 8 * ROWS * 16 * gd_dims(N).Np) * 8 <= 160 * 1024 ? 8 : 4;
+}
+
+#define IPDG_GD_KERNELS(NAME, TILE, ARGS, ROWS)                                                                    \
+  template <int N, bool MASS>                                                                                \
+  __global__ __launch_bounds__(64 * kGdWaves) void NAME(ARGS a, const double* __restrict__ tab) {            \
+    __shared__ double stage[kGdWaves][ROWS][16 * gd_dims(N).Np];                                             \
+    const int w = threadIdx.x >> 6;                                                                          \
+    TILE<N, MASS>(a, tab, (blockIdx.x * kGdWaves + w) * 16, stage[w][0], stage[w][ROWS - 1]);                \
+  }                                                                                                          \
+  template <int N, bool MASS>                                                                                \
+  __global__ __launch_bounds__((64 * gd_pwaves<N, ROWS>())) void NAME##p(ARGS a, const double* __restrict__ gtab) { \
+    constexpr GdDims D = gd_dims(N);                                                                         \
+    constexpr int W = gd_pwaves<N, ROWS>();                                                                  \
+    __shared__ double tab[D.total];                                                                          \
+    __shared__ double stage[W][ROWS][16 * D.Np];                                                             \
+    for (int i = threadIdx.x; i < D.total; i += 64 * W) tab[i] = gtab[i];                                    \
+    __syncthreads();                                                                                         \
+    const int w = threadIdx.x >> 6;                                                                          \
+    const int ntiles = (a.K + 16 * W - 1) / (16 * W);                                                        \
+    for (int bt = blockIdx.x; bt < ntiles; bt += gridDim.x) {                                                \
+      TILE<N, MASS>(a, tab, (bt * W + w) * 16, stage[w][0], stage[w][ROWS - 1]);                             \
+      __syncthreads();                                                                                       \
+    }                                                                                                        \
+  }
+
+IPDG_GD_KERNELS(k_grad_mf, grad_tile, GradArgs, 2)
+IPDG_GD_KERNELS(k_div_mf, div_tile, DivArgs, 1)
+IPDG_GD_KERNELS(k_advect_mf, advect_tile, AdvectArgs, 2)
+#undef IPDG_GD_KERNELS
 
 // One element per lane; only elements with Dirichlet faces add anything.
 // Face integrals from the face-node values: with h = (|F| / 2) M1D g (the
@@ -665,16 +704,60 @@ hipError_t dirichlet_rhs(int N, const DirichletArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
+namespace {
+
+// degrees from which the persistent form (table in LDS) runs: measured on
+// 524,288 triangles it is 10-28 % faster from degree 3 (the plain form reads
+// the whole table from L2 for every 16 elements, three to four times the
+// kernel's HBM bytes at degree 7), and even at degree 2
+template <int N>
+constexpr bool gd_persistent() {
+  return N >= 3;
+}
+
+template <int N, int ROWS, typename Args, typename K1, typename K2>
+void launch_gd(const Args& a, hipStream_t s, K1 plain, K2 persistent) {
+  if constexpr (gd_persistent<N>()) {
+    constexpr int W = gd_pwaves<N, ROWS>();
+    const int ntiles = (a.K + 16 * W - 1) / (16 * W);
+    hipLaunchKernelGGL(persistent, dim3(ntiles < 512 ? ntiles : 512), dim3(64 * W), 0, s, a, device_gd_tab(N));
+  } else {
+    hipLaunchKernelGGL(plain, dim3((a.K + 16 * kGdWaves - 1) / (16 * kGdWaves)), dim3(64 * kGdWaves), 0, s, a,
+                       device_gd_tab(N));
+  }
+}
+
+template <int N>
+void launch_grad_mf(const GradArgs& a, hipStream_t s) {
+  if (a.mass) launch_gd<N, 2>(a, s, k_grad_mf<N, true>, k_grad_mfp<N, true>);
+  else launch_gd<N, 2>(a, s, k_grad_mf<N, false>, k_grad_mfp<N, false>);
+}
+
+template <int N>
+void launch_div_mf(const DivArgs& a, hipStream_t s) {
+  if (a.mass) launch_gd<N, 1>(a, s, k_div_mf<N, true>, k_div_mfp<N, true>);
+  else launch_gd<N, 1>(a, s, k_div_mf<N, false>, k_div_mfp<N, false>);
+}
+
+template <int N>
+void launch_advect_mf(const AdvectArgs& a, hipStream_t s) {
+  launch_gd<N, 2>(a, s, k_advect_mf<N, false>, k_advect_mfp<N, false>);
+}
+
+}  // namespace
+
 hipError_t advect_apply(int N, const AdvectArgs& a, hipStream_t s) {
   if (a.K == 0) return hipSuccess;
-  const dim3 grid((a.K + 16 * kGdWaves - 1) / (16 * kGdWaves)), block(64 * kGdWaves);
   switch (N) {
     // one element per lane is faster only at degree 1
     case 1: hipLaunchKernelGGL(k_advect<1>, dim3(blocks<1>(a.K)), dim3(kElems<1>()), 0, s, a); break;
-#define IPDG_A(n) \
-  case n: hipLaunchKernelGGL(k_advect_mf<n>, grid, block, 0, s, a, device_gd_tab(n)); break;
-    IPDG_A(2) IPDG_A(3) IPDG_A(4) IPDG_A(5) IPDG_A(6) IPDG_A(7) IPDG_A(8)
-#undef IPDG_A
+    case 2: launch_advect_mf<2>(a, s); break;
+    case 3: launch_advect_mf<3>(a, s); break;
+    case 4: launch_advect_mf<4>(a, s); break;
+    case 5: launch_advect_mf<5>(a, s); break;
+    case 6: launch_advect_mf<6>(a, s); break;
+    case 7: launch_advect_mf<7>(a, s); break;
+    case 8: launch_advect_mf<8>(a, s); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -704,23 +787,6 @@ hipError_t remove_mean(int N, double* b, double area, const double* geo, const d
   return hipGetLastError();
 }
 
-namespace {
-
-template <int N>
-void launch_grad_mf(const GradArgs& a, hipStream_t s) {
-  const dim3 grid((a.K + 16 * kGdWaves - 1) / (16 * kGdWaves)), block(64 * kGdWaves);
-  if (a.mass) hipLaunchKernelGGL((k_grad_mf<N, true>), grid, block, 0, s, a, device_gd_tab(N));
-  else hipLaunchKernelGGL((k_grad_mf<N, false>), grid, block, 0, s, a, device_gd_tab(N));
-}
-
-template <int N>
-void launch_div_mf(const DivArgs& a, hipStream_t s) {
-  const dim3 grid((a.K + 16 * kGdWaves - 1) / (16 * kGdWaves)), block(64 * kGdWaves);
-  if (a.mass) hipLaunchKernelGGL((k_div_mf<N, true>), grid, block, 0, s, a, device_gd_tab(N));
-  else hipLaunchKernelGGL((k_div_mf<N, false>), grid, block, 0, s, a, device_gd_tab(N));
-}
-
-}  // namespace
 
 hipError_t grad_apply(int N, const GradArgs& a, hipStream_t s) {
   if (a.K == 0) return hipSuccess;
