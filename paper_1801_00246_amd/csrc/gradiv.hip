@@ -715,16 +715,24 @@ constexpr bool gd_persistent() {
   return N >= 3;
 }
 
+// The persistent form needs enough tiles to fill the device with blocks that
+// each pay for one table load: below 256 block tiles (32,768 elements at
+// eight waves) the plain form is faster (8,192 triangles at N = 5: 10-12
+// against 14-15 us).
+constexpr int kGdPersistentMinK = 32768;
+
 template <int N, int ROWS, typename Args, typename K1, typename K2>
 void launch_gd(const Args& a, hipStream_t s, K1 plain, K2 persistent) {
   if constexpr (gd_persistent<N>()) {
-    constexpr int W = gd_pwaves<N, ROWS>();
-    const int ntiles = (a.K + 16 * W - 1) / (16 * W);
-    hipLaunchKernelGGL(persistent, dim3(ntiles < 512 ? ntiles : 512), dim3(64 * W), 0, s, a, device_gd_tab(N));
-  } else {
-    hipLaunchKernelGGL(plain, dim3((a.K + 16 * kGdWaves - 1) / (16 * kGdWaves)), dim3(64 * kGdWaves), 0, s, a,
-                       device_gd_tab(N));
+    if (a.K >= kGdPersistentMinK) {
+      constexpr int W = gd_pwaves<N, ROWS>();
+      const int ntiles = (a.K + 16 * W - 1) / (16 * W);
+      hipLaunchKernelGGL(persistent, dim3(ntiles < 512 ? ntiles : 512), dim3(64 * W), 0, s, a, device_gd_tab(N));
+      return;
+    }
   }
+  hipLaunchKernelGGL(plain, dim3((a.K + 16 * kGdWaves - 1) / (16 * kGdWaves)), dim3(64 * kGdWaves), 0, s, a,
+                     device_gd_tab(N));
 }
 
 template <int N>

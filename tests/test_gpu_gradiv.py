@@ -136,3 +136,61 @@ def test_advection_matches_oracle(N, bc):
     print(f"N={N} {bc}: advection rel errors {e[0]:.1e} {e[1]:.1e}; zero data {e[2]:.1e} {e[3]:.1e}")
     assert max(e) <= 1e-12
     g.close()
+
+
+def _poly(x, y, N, seed):
+    c = np.random.default_rng(seed).standard_normal((N + 1, N + 1))
+    f, fx, fy = np.zeros_like(x), np.zeros_like(x), np.zeros_like(x)
+    for i in range(N + 1):
+        for j in range(N + 1 - i):
+            f += c[i, j] * x ** i * y ** j
+            if i:
+                fx += c[i, j] * i * x ** (i - 1) * y ** j
+            if j:
+                fy += c[i, j] * j * x ** i * y ** (j - 1)
+    return f, fx, fy
+
+
+@pytest.mark.parametrize("N", [3, 5, 8])
+def test_persistent_form_at_scale(N):
+    """The persistent launch form (operator table in LDS, blocks walking over
+    the tiles) runs from 32,768 elements: on 131 x 131 squares (34,322
+    triangles, a ragged last tile) every launch of the gradient, divergence,
+    advection, the mass-weighted right-hand sides and the correction is
+    checked by properties that hold at any size: exact derivatives of global
+    polynomials of degree <= N, exact advection of a linear field, and the
+    right-hand sides against the separate mass kernel."""
+    n = 131
+    # all faces Dirichlet: there p* = p- and u* = g (the field itself), so the
+    # central fluxes reproduce global polynomials exactly
+    msh = synth.permuted(synth.square_mesh(n, jitter=0.2, seed=50 + N, bc="dirichlet"), seed=51 + N)
+    g = P.Mesh.from_synth(N, msh)
+    assert g.K >= 32768 and g.K % 128
+    x, y = (np.asarray(a).ravel() for a in g.node_coords())
+    p, px, py = _poly(x, y, N, seed=52)
+    u, ux, uy = _poly(x, y, N, seed=53)
+    v, vx, vy = _poly(x, y, N, seed=54)
+    tol = 5e-14 * N * N * n                     # rounding amplified by the operator's norm, ~ N^2 / h
+    gx, gy = g.grad(dev(p))
+    e = [rel(host(gx), px), rel(host(gy), py)]
+    d = g.div(dev(u), dev(v), dev(u), dev(v))
+    e.append(rel(host(d), ux + vy))
+    # a linear field: the nodal products (degree 2) are represented exactly
+    c = np.random.default_rng(55).standard_normal(6)
+    ul, vl = c[0] + c[1] * x + c[2] * y, c[3] + c[4] * x + c[5] * y
+    nu_, nv_ = g.advect(dev(ul), dev(vl), dev(ul), dev(vl))
+    div_l = c[1] + c[5]
+    e += [rel(host(nu_), ul * c[1] + vl * c[2] + ul * div_l), rel(host(nv_), ul * c[4] + vl * c[5] + vl * div_l)]
+    # mass-weighted right-hand sides and the correction
+    nu, dt = 0.1, 0.01
+    bu, bv = g.ins_velocity_rhs(nu, dt, dev(u), dev(v), dev(p))
+    eu = g.mass(dev(u / (nu * dt) - px / nu))
+    ev = g.mass(dev(v / (nu * dt) - py / nu))
+    e += [rel(host(bu), host(eu)), rel(host(bv), host(ev))]
+    b = g.ins_pressure_rhs(1.0, dt, dev(u), dev(v), dev(u), dev(v))
+    e.append(rel(host(b), host(g.mass(dev(-(ux + vy) / dt)))))
+    uo, vo, po = g.ins_correct(1.0, dt, dev(u), dev(v), dev(p), dev(v))
+    e += [rel(host(uo), u - dt * px), rel(host(vo), v - dt * py), rel(host(po), p + v)]
+    print(f"N={N} K={g.K}: " + " ".join(f"{a:.1e}" for a in e))
+    assert max(e) <= tol
+    g.close()
