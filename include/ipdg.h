@@ -359,7 +359,9 @@ ipdg_status ipdg_ins_step(ipdg_mesh mesh, ipdg_mesh pmesh, double nu, double dt,
  * advanced by `subcycles` substeps of ipdg_subcycle (cubature operator of
  * Eq. KSS_3, five-stage fourth-order low-storage Runge-Kutta), the Dirichlet
  * data of U~ linear in time from (gu_n, gv_n) to (gu_1, gv_1).  The rest of
- * the step is that of ipdg_ins_step.  IPDG_EINVAL for subcycles < 1. */
+ * the step is that of ipdg_ins_step.  Uses the Runge-Kutta registers the mesh
+ * keeps for ipdg_subcycle: calls on one mesh must not overlap.  IPDG_EINVAL
+ * for subcycles < 1. */
 ipdg_status ipdg_ins_step_subcycled(ipdg_mesh mesh, ipdg_mesh pmesh, double nu, double dt, double tau,
                                     int subcycles, const double* u_n, const double* v_n, const double* p_n,
                                     const double* p_nm1, const double* gu_n, const double* gv_n,
