@@ -399,8 +399,8 @@ def run_subcycle(P, torch, msh, orders=(3, 5, 7), steps=20, Ns=4):
     surface term (Alg. SSS) and the fused operator (HIP events over `steps`
     launches on torch's stream), algorithmic TFLOP/s against the FP64 dense
     matrix-core peak, and the whole subcycle call (Ns five-stage substeps,
-    one fused operator-and-update launch per stage, work allocation and
-    final synchronisation included) per substep."""
+    one fused operator-and-update launch per stage; HIP events around the
+    call on the same stream) per substep."""
     import ctypes as C
     import synth
     out = {"workload": "512x512-square jittered triangulation (524,288 triangles), all Dirichlet, "
